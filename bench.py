@@ -1,0 +1,306 @@
+"""Benchmark: large-number add/sub/mul on one MI355X.
+
+One JSON line on stdout.  The headline `value` is add/sub operand throughput on
+the batched workload (2^20 pairs of 64-limb operands): a step is one batched add
+plus one batched subtract over that batch, inputs resident in HBM, and `value` is
+the algorithmic bytes of the step (24 B per limb: two operands read, one result
+written, plus 8 B per pair of carry/borrow) divided by the step time.  The other
+workloads are measured in the same run and reported under "workloads": 4-limb
+pairs (latency, graph replay), one 2^26-limb pair (look-back scan), 2^16 ragged
+multiply pairs (persistent launch, graph replay, mad vs MFMA), 64 products of
+16384-limb operands (mad vs MFMA) and a square-size sweep for the mad/MFMA
+crossover.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, published (ops = 2 x MAC)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flat_scan_c2_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_addsub.hip", "bn_internal.h"):
+        with open(os.path.join(ROOT, "paper_2604_21566_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(per_launch_bytes_alg: float):
+    """HBM bytes per launch of the scan kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_src_sha") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def gpu_time(fn, reps: int, warmup: int = 1):
+    """Mean and per-rep ms of fn() on torch's current stream (HIP events)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    ts = [e0.elapsed_time(e1) for e0, e1 in evs]
+    return float(np.mean(ts)), ts
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tuning", default=None, help="tuning JSON written by bn_autotune")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this library has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2604_21566_amd as bn
+    from paper_2604_21566_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    ctx = bn.bn_create(0)
+    if args.tuning:
+        bn.bn_load_tuning(ctx, args.tuning)
+    D = bn.to_device
+
+    # ------------------------------------------------------------ headline: c2 add + sub
+    n, npairs = 64, 1 << 20
+    N = n * npairs
+    log("generating c2 operands")
+    a_add, b_add = wl.c2("add", npairs=npairs, n=n)
+    a_sub, b_sub = wl.c2("sub", npairs=npairs, n=n)
+    ta, tb, sa, sb = D(a_add), D(b_add), D(a_sub), D(b_sub)
+    tr = torch.empty(N, dtype=torch.int64, device="cuda")
+    tc = torch.empty(npairs, dtype=torch.int64, device="cuda")
+    bytes_per_launch = 24.0 * N + 8.0 * npairs
+
+    def add():
+        bn.bn_add_n_batch(ctx, tr, ta, tb, n, npairs, tc)
+
+    def sub():
+        bn.bn_sub_n_batch(ctx, tr, sa, sb, n, npairs, tc)
+
+    for _ in range(args.warmup):
+        add()
+        sub()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[3 * k].record()
+        add()
+        ev[3 * k + 1].record()
+        sub()
+        ev[3 * k + 2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = []
+    step_ms = []
+    for k in range(args.steps):
+        launch_ms += [ev[3 * k].elapsed_time(ev[3 * k + 1]), ev[3 * k + 1].elapsed_time(ev[3 * k + 2])]
+        step_ms.append(ev[3 * k].elapsed_time(ev[3 * k + 2]))
+    ms_per_step = wall * 1e3 / args.steps
+    value = 2 * bytes_per_launch / (ms_per_step * 1e-3) / 1e9
+    avg_launch = float(np.mean(launch_ms))
+    achieved = bytes_per_launch / (avg_launch * 1e-3) / 1e9
+    traffic = measured_traffic(bytes_per_launch)
+    st, flags = bn.bn_check(ctx)
+    if st != bn.BN_OK:
+        log(f"device error latch set: {flags}")
+    log(f"c2: step {ms_per_step:.4f} ms, kernel {avg_launch:.4f} ms, {achieved:.1f} GB/s")
+    workloads = {"c2_addsub": {"GBps_add": bytes_per_launch / (np.mean(launch_ms[0::2]) * 1e-3) / 1e9,
+                               "GBps_sub": bytes_per_launch / (np.mean(launch_ms[1::2]) * 1e-3) / 1e9,
+                               "kernel_ms_mean": avg_launch, "kernel_ms_min": float(np.min(launch_ms)),
+                               "ci95_ms": float(1.96 * np.std(launch_ms) / np.sqrt(len(launch_ms)))}}
+
+    # ------------------------------------------------------------ CPU oracle baseline (same workload)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("timing the CPU oracle on the full c2 batch (add + sub, one thread)")
+        oracle._load()
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.add_batch(a_add, b_add, n)
+            oracle.sub_batch(a_sub, b_sub, n)
+            reps += 1
+            if time.perf_counter() - t0 > 10.0 or reps >= 20:
+                break
+        dt = (time.perf_counter() - t0) / reps
+        cpu = {"value": 2 * bytes_per_launch / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"full 2^20 x 64-limb batch, add + sub, {reps} repetitions, one thread",
+               "ms_per_step": dt * 1e3}
+    del a_sub, b_sub, sa, sb
+
+    if not args.quick:
+        workloads.update(extra_workloads(ctx, bn, wl, torch))
+
+    bn.bn_destroy(ctx)
+    out = {
+        "metric": "add/sub operand GB/s vs HBM peak; mul products/s by size, MFMA vs plain form",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "batched add+sub: 2^20 pairs x 64 u64 limbs (10% adversarial carry runs)",
+                   "pairs": npairs, "limbs_per_operand": n, "bytes_per_step": 2 * bytes_per_launch},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "cpu_baseline": cpu,
+        "workloads": workloads,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def extra_workloads(ctx, bn, wl, torch):
+    D = bn.to_device
+    res = {}
+
+    # ---- c1: 1088 pairs of 4 limbs, graph replay (latency)
+    log("c1")
+    c1 = {}
+    s = torch.cuda.Stream()
+    for op in ("add", "sub", "mul_mad", "mul_mfma"):
+        a, b = wl.c1("sub" if op == "sub" else "add")
+        ta, tb = D(a), D(b)
+        if op.startswith("mul"):
+            tr = torch.empty(1088 * 8, dtype=torch.int64, device="cuda")
+            g = bn.bn_graph_capture_batch(ctx, 2, tr, ta, tb, 4, 4, 1088, None, op[4:], s)
+        else:
+            tr = torch.empty(1088 * 4, dtype=torch.int64, device="cuda")
+            tc = torch.empty(1088, dtype=torch.int64, device="cuda")
+            g = bn.bn_graph_capture_batch(ctx, 0 if op == "add" else 1, tr, ta, tb, 4, 0, 1088, tc, 0, s)
+        with torch.cuda.stream(s):
+            ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 50, 5)
+        bn.bn_graph_destroy(g)
+        c1[op + "_us"] = ms * 1e3
+        c1[op + "_pairs_per_s"] = 1088 / (ms * 1e-3)
+    res["c1"] = c1
+
+    # ---- c3: one pair of 2^26 limbs (random with runs, and the all-propagate worst case)
+    log("c3")
+    c3 = {}
+    n3 = 1 << 26
+    tr = torch.empty(n3, dtype=torch.int64, device="cuda")
+    tc = torch.empty(1, dtype=torch.int64, device="cuda")
+    for op in ("add", "sub"):
+        for worst in (False, True):
+            a, b = wl.c3(op, n=n3, worst=worst)
+            ta, tb = D(a), D(b)
+            f = bn.bn_add if op == "add" else bn.bn_sub
+            ms, _ = gpu_time(lambda: f(ctx, tr, ta, tb, tc), 10, 2)
+            c3[f"{op}{'_worst' if worst else ''}_GBps"] = 24.0 * n3 / (ms * 1e-3) / 1e9
+            del ta, tb
+    res["c3"] = c3
+
+    # ---- c4: 2^16 ragged products, persistent launch captured in a graph
+    log("c4")
+    a, b, desc, rsz = wl.c4()
+    work = float((desc[:, 3].astype(np.float64) * desc[:, 4].astype(np.float64)).sum())
+    ta, tb = D(a), D(b)
+    tr = torch.empty(rsz, dtype=torch.int64, device="cuda")
+    c4 = {"limb_products": work}
+    for form in ("mad", "mfma", "auto"):
+        plan = bn.bn_plan_mul_ragged(ctx, desc, form)
+        g = bn.bn_graph_capture_mul_ragged(ctx, plan, tr, ta, tb, s)
+        with torch.cuda.stream(s):
+            ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 10, 2)
+        bn.bn_graph_destroy(g)
+        bn.bn_plan_destroy(plan)
+        c4[f"{form}_ms"] = ms
+        c4[f"{form}_limb_products_per_s"] = work / (ms * 1e-3)
+        c4[f"{form}_pairs_per_s"] = len(desc) / (ms * 1e-3)
+    res["c4"] = c4
+
+    # ---- c5: 64 products of 16384-limb operands
+    log("c5")
+    n5 = 16384
+    a, b = wl.c5()
+    ta, tb = D(a), D(b)
+    tr = torch.empty(64 * 2 * n5, dtype=torch.int64, device="cuda")
+    c5 = {"limb_products": 64.0 * n5 * n5}
+    for form in ("mad", "mfma"):
+        ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, tr, ta, tb, n5, n5, 64, form), 3, 1)
+        c5[f"{form}_ms"] = ms
+        c5[f"{form}_limb_products_per_s"] = 64.0 * n5 * n5 / (ms * 1e-3)
+        c5[f"{form}_products_per_s"] = 64 / (ms * 1e-3)
+    c5["mfma_int8_TOPS"] = 2 * 64.0 * 64.0 * n5 * n5 / (c5["mfma_ms"] * 1e-3) / 1e12
+    c5["mfma_frac_of_int8_peak"] = c5["mfma_int8_TOPS"] / INT8_PEAK_TOPS
+    c5["mfma_over_mad"] = c5["mad_ms"] / c5["mfma_ms"]
+    res["c5"] = c5
+
+    # ---- crossover sweep: square products, similar work per size
+    log("crossover sweep")
+    sweep = {}
+    crossover = None
+    n = 4
+    big = torch.empty(1 << 25, dtype=torch.int64, device="cuda").random_()
+    out = torch.empty(1 << 26, dtype=torch.int64, device="cuda")
+    while n <= 16384:
+        npairs = int(max(1, min(65535, (1 << 28) // (n * n), (1 << 25) // n)))
+        row = {}
+        for form in ("mad", "mfma"):
+            ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, out, big, big, n, n, npairs, form), 3, 1)
+            row[form + "_limb_products_per_s"] = npairs * n * n / (ms * 1e-3)
+        row["pairs"] = npairs
+        sweep[str(n)] = row
+        faster = row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"]
+        if faster and crossover is None:
+            crossover = n
+        elif not faster:
+            crossover = None
+        n *= 2
+    res["crossover"] = {"sweep": sweep, "mfma_faster_from_limbs": crossover}
+    st, flags = bn.bn_check(ctx)
+    res["device_error_latch"] = flags
+    return res
+
+
+if __name__ == "__main__":
+    main()

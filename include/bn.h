@@ -1,0 +1,196 @@
+/*
+ * bn.h -- C ABI of the MI355X (gfx950) large-number arithmetic library.
+ *
+ * Operations follow the problem statements of "Leveraging SIMD for Accelerating
+ * Large-number Arithmetic" (DigitsOnTurbo, DoT):
+ *   - add/sub: DoT-Add-Words(A, B, m) -> (S, c_out) of Algorithm 1 / Theorem 1
+ *     (Sec. 3.1), subtraction being its borrow mirror (Sec. 3.1, "Subtraction");
+ *   - mul: DoT-Mul-Words(A, B, m, k) -> P = A x B of Algorithm 2 / Theorem 2
+ *     (Sec. 3.2), with unequal operand lengths allowed (the proof of Theorem 2
+ *     pads the shorter operand with zero limbs, Appendix B).
+ *
+ * Number format (Sec. 2.1, Theorem 1): little-endian arrays of 64-bit limbs,
+ * limb 0 least significant, radix X = 2^64.
+ *
+ * Memory: every r/a/b/carry pointer is a DEVICE pointer owned by the caller.
+ * Pointers must be 8-byte aligned; 16-byte alignment of r, a and b selects the
+ * vector-load fast path.  The library owns a per-context device workspace
+ * (look-back status words, column accumulators) that it grows on demand; grow it
+ * beforehand with bn_reserve() when calls will be captured into a HIP graph.
+ *
+ * Streams: `bn_stream` is a hipStream_t (NULL = the legacy default stream).
+ * Every compute call is asynchronous and stream-ordered: it validates its
+ * arguments on the host, enqueues kernels and returns without synchronising.
+ * Calls on one context must not overlap in time (they share the workspace):
+ * issue them on one stream, or use one context per concurrently used stream.
+ *
+ * Errors: every entry point returns a bn_status.  Argument errors are detected
+ * synchronously and nothing is enqueued.  HIP launch errors map to BN_EHIP.
+ * Asynchronous device-side conditions (the look-back watchdog) are latched in
+ * the context and read with bn_check().  No C++ exception crosses the ABI.
+ */
+#ifndef BN_H_
+#define BN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int bn_status;
+#define BN_OK 0
+#define BN_EINVAL (-1)        /* null pointer for a non-empty operand, misalignment, bad enum */
+#define BN_EALIAS (-2)        /* output overlaps an input in a way the operation forbids */
+#define BN_ERANGE (-3)        /* a size beyond the supported limits */
+#define BN_ENOMEM (-4)        /* device workspace allocation failed */
+#define BN_EHIP (-5)          /* a HIP runtime call or kernel launch failed */
+#define BN_EUNSUPPORTED (-6)  /* no gfx950 device, or a feature not built */
+#define BN_ECAPTURE (-7)      /* workspace would have to grow while the stream is being captured */
+#define BN_EWATCHDOG (-8)     /* returned by bn_check: a look-back wait hit its spin limit */
+
+typedef struct bn_ctx bn_ctx;
+typedef void *bn_stream; /* hipStream_t */
+
+/* Size limits (limbs).  A single operand may hold up to 2^34 limbs (128 GiB). */
+#define BN_MAX_LIMBS (1ull << 34)
+
+/* ---------------------------------------------------------------- context ---- */
+
+/* Create a context on HIP device `device` (makes it current for the call).
+ * Allocates the small control block; the workspace grows lazily.
+ * Errors: BN_EINVAL (ctx NULL), BN_EUNSUPPORTED (device is not gfx950), BN_EHIP, BN_ENOMEM. */
+bn_status bn_create(bn_ctx **ctx, int device);
+
+/* Synchronises the device and frees everything the context owns.  NULL is a no-op. */
+bn_status bn_destroy(bn_ctx *ctx);
+
+/* Human-readable text for a status code (static storage). */
+const char *bn_strerror(bn_status s);
+
+/* Grow the workspace to at least `bytes` now (host-synchronous allocation), so that
+ * later calls, including captured ones, need no allocation. */
+bn_status bn_reserve(bn_ctx *ctx, size_t bytes);
+
+/* Workspace bytes a call would need (for bn_reserve).  op: 0 add/sub, 1 mul.
+ * For add/sub pass n, npairs (na = n); for mul pass na, nb, npairs, form. */
+size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form);
+
+/* Synchronise `stream`, then read and clear the context's device-side error latch.
+ * *flags (may be NULL) receives the raw latch (bit 0: look-back watchdog).
+ * Returns BN_EWATCHDOG if the watchdog fired since the last check, else BN_OK. */
+bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags);
+
+/* ------------------------------------------------------- add / subtract ---- */
+
+/* r = (a + b) mod 2^(64n); *carry_out = carry-out c_n in {0,1} (Theorem 1).
+ * r may equal a or b exactly (in place); any other overlap is BN_EALIAS.
+ * carry_out (device, one uint64) may be NULL.  n = 0 is valid (carry 0).
+ * One pass over the operands: limb sums, generate/propagate flags, a wave64
+ * ballot prefix scan, an LDS scan across waves and a decoupled look-back across
+ * workgroups (Sec. 3.1 phases 1-4 restated as a parallel prefix computation). */
+bn_status bn_add(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                 uint64_t *carry_out, bn_stream stream);
+
+/* r = (a - b) mod 2^(64n); *borrow_out = [a < b].  Same rules as bn_add. */
+bn_status bn_sub(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                 uint64_t *borrow_out, bn_stream stream);
+
+/* Uniform batch: pair p is limbs [p*n, (p+1)*n) of r, a and b; carry_out[p] (device,
+ * npairs uint64, may be NULL) receives its carry/borrow.  Pairs are independent. */
+bn_status bn_add_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b,
+                         size_t n, size_t npairs, uint64_t *carry_out, bn_stream stream);
+bn_status bn_sub_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b,
+                         size_t n, size_t npairs, uint64_t *borrow_out, bn_stream stream);
+
+/* ------------------------------------------------------------ multiply ---- */
+
+#define BN_MUL_AUTO 0 /* pick per size from the tuning table (mad below the crossover) */
+#define BN_MUL_MAD 1  /* 32x32->64-bit v_mad_u64_u32 column products */
+#define BN_MUL_MFMA 2 /* 8-bit digit convolution on int8 MFMA, int32 accumulation */
+
+/* r[0 .. na+nb) = a * b (Theorem 2), exactly na+nb limbs, leading zeros kept.
+ * Column products (all independent), then one deferred carry-normalise pass
+ * (Algorithm 2, phases 1-5).  r must not overlap a or b (BN_EALIAS).
+ * na = 0 or nb = 0 gives r = 0 (na+nb limbs). */
+bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
+                 int form, bn_stream stream);
+
+/* Uniform batch: a of pair p at a + p*na, b at b + p*nb, product at r + p*(na+nb). */
+bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na,
+                         size_t nb, size_t npairs, int form, bn_stream stream);
+
+/* ------------------------------------------------- ragged batches + plans ---- */
+
+/* One pair of a ragged batch: offsets in limbs into pooled device arrays. */
+typedef struct bn_pair {
+    uint64_t a_off, b_off, r_off;
+    uint32_t na, nb;
+} bn_pair;
+
+typedef struct bn_plan bn_plan;
+
+/* Build a plan for a ragged multiply batch from a HOST copy of the descriptors:
+ * validates sizes (1 <= na, nb <= 2^20), sorts the pairs by work (na*nb,
+ * largest first), picks mad or MFMA per pair (form, or the tuned crossover for
+ * BN_MUL_AUTO), and uploads the work list to device memory it owns.
+ * Synchronous (allocates).  Product ranges must not overlap each other or the inputs. */
+bn_status bn_plan_mul_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, int form,
+                             bn_plan **plan);
+bn_status bn_plan_destroy(bn_plan *plan);
+
+/* Run a planned ragged multiply: one persistent kernel pulls pairs from an atomic
+ * work counter until the list is exhausted.  No allocation, no host sync. */
+bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
+                        const uint64_t *b_pool, bn_stream stream);
+
+/* Ragged add: plan built with na == nb required (nb ignored); carry_out[p] in plan order
+ * of the host descriptor array (NOT the sorted order).  May be NULL. */
+bn_status bn_plan_add_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, bn_plan **plan);
+bn_status bn_add_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
+                        const uint64_t *b_pool, uint64_t *carry_out, bn_stream stream);
+
+/* ------------------------------------------------------------ HIP graphs ---- */
+
+typedef struct bn_graph bn_graph;
+
+/* Capture one bn_mul_ragged call into an instantiated HIP graph (pointers are baked in).
+ * The workspace must already be large enough (it is reserved here, before capture). */
+bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool,
+                                      const uint64_t *a_pool, const uint64_t *b_pool,
+                                      bn_stream stream, bn_graph **graph);
+/* Same for a uniform add/sub/mul batch (op: 0 add, 1 sub, 2 mul). */
+bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_t *a, const uint64_t *b,
+                                 size_t na, size_t nb, size_t npairs, uint64_t *carry_out, int form,
+                                 bn_stream stream, bn_graph **graph);
+bn_status bn_graph_launch(bn_graph *graph, bn_stream stream);
+bn_status bn_graph_destroy(bn_graph *graph);
+
+/* ------------------------------------------------------------ tuning ---- */
+
+/* Named integer parameters of the context (see bn_param_names()):
+ *   "addsub.rows", "addsub.waves"      tile shape of the add/sub scan
+ *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
+ *   "mul.mad_cols", "mfma.chunk"       product-kernel tile parameters
+ *   "watchdog.spin_limit"              look-back wait bound (iterations)
+ * Returns BN_EINVAL for an unknown key or an out-of-range value. */
+bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t value);
+bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *value);
+const char *bn_param_names(void);
+
+/* Time the candidate tile shapes and the mad/MFMA crossover on this device (scratch
+ * operands allocated internally), store the winners in the context and, if
+ * out_json != NULL, write them as a JSON object.  Synchronous; takes seconds. */
+bn_status bn_autotune(bn_ctx *ctx, const char *out_json);
+
+/* Load parameters written by bn_autotune (flat JSON object of "key": integer). */
+bn_status bn_load_tuning(bn_ctx *ctx, const char *json_path);
+
+/* Library version string. */
+const char *bn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BN_H_ */

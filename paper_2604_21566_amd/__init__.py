@@ -1,1 +1,314 @@
-"""MI355X-native large-number add / sub / mul (placeholder; binding added next)."""
+"""MI355X (gfx950) large-number add / sub / mul -- Python binding of libbn.so.
+
+A thin ctypes layer over the C ABI declared in ``include/bn.h``: every function
+has the C name, converts its arguments (torch device tensors -> device pointers,
+torch streams -> hipStream_t) and calls the library.  All arithmetic runs in the
+library's HIP kernels; there is no fallback path.  If ``libbn.so`` has not been
+built, every call raises ``BnLibraryMissing``.
+
+Operands are contiguous torch tensors of dtype int64 or uint64 on a ROCm device,
+holding little-endian 64-bit limbs (limb 0 least significant).  PyTorch is used
+for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbn.so")
+
+BN_OK = 0
+BN_EINVAL = -1
+BN_EALIAS = -2
+BN_ERANGE = -3
+BN_ENOMEM = -4
+BN_EHIP = -5
+BN_EUNSUPPORTED = -6
+BN_ECAPTURE = -7
+BN_EWATCHDOG = -8
+
+BN_MUL_AUTO = 0
+BN_MUL_MAD = 1
+BN_MUL_MFMA = 2
+
+FORMS = {"auto": BN_MUL_AUTO, "mad": BN_MUL_MAD, "mfma": BN_MUL_MFMA}
+
+
+class BnLibraryMissing(RuntimeError):
+    pass
+
+
+class BnError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {bn_strerror(status)} ({status})")
+
+
+class bn_pair(ctypes.Structure):
+    _fields_ = [("a_off", ctypes.c_uint64), ("b_off", ctypes.c_uint64), ("r_off", ctypes.c_uint64),
+                ("na", ctypes.c_uint32), ("nb", ctypes.c_uint32)]
+
+
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_i = ctypes.c_int
+_PROTOS = {
+    "bn_create": (_i, [ctypes.POINTER(_vp), _i]),
+    "bn_destroy": (_i, [_vp]),
+    "bn_strerror": (ctypes.c_char_p, [_i]),
+    "bn_version": (ctypes.c_char_p, []),
+    "bn_reserve": (_i, [_vp, _sz]),
+    "bn_workspace_size": (_sz, [_vp, _i, _sz, _sz, _sz, _i]),
+    "bn_check": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "bn_add": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "bn_sub": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "bn_add_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
+    "bn_sub_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
+    "bn_mul": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _i, _vp]),
+    "bn_mul_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _sz, _i, _vp]),
+    "bn_plan_mul_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, _i, ctypes.POINTER(_vp)]),
+    "bn_plan_add_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, ctypes.POINTER(_vp)]),
+    "bn_plan_destroy": (_i, [_vp]),
+    "bn_mul_ragged": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "bn_add_ragged": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bn_graph_capture_mul_ragged": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "bn_graph_capture_batch": (_i, [_vp, _i, _vp, _vp, _vp, _sz, _sz, _sz, _vp, _i, _vp, ctypes.POINTER(_vp)]),
+    "bn_graph_launch": (_i, [_vp, _vp]),
+    "bn_graph_destroy": (_i, [_vp]),
+    "bn_set_param": (_i, [_vp, ctypes.c_char_p, ctypes.c_int64]),
+    "bn_get_param": (_i, [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
+    "bn_param_names": (ctypes.c_char_p, []),
+    "bn_autotune": (_i, [_vp, ctypes.c_char_p]),
+    "bn_load_tuning": (_i, [_vp, ctypes.c_char_p]),
+}
+EXPORTED = tuple(_PROTOS)
+
+_lib = None
+
+
+def lib():
+    """The loaded libbn.so (raises BnLibraryMissing if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise BnLibraryMissing(f"{LIB_PATH} not built; run __graft_entry__.build() or "
+                                   "python paper_2604_21566_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ck(st: int, what: str):
+    if st != BN_OK:
+        raise BnError(st, what)
+
+
+def bn_strerror(st: int) -> str:
+    try:
+        return lib().bn_strerror(st).decode()
+    except BnLibraryMissing:
+        return f"status {st}"
+
+
+def bn_version() -> str:
+    return lib().bn_version().decode()
+
+
+# ------------------------------------------------------------------ marshalling ----
+def _ptr(t, what: str):
+    """Device pointer of a contiguous int64/uint64 torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: tensor must live on the GPU")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"{what}: limbs must be int64/uint64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    return t.data_ptr() if t.numel() else None
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ context ----
+def bn_create(device: int = 0):
+    ctx = _vp()
+    _ck(lib().bn_create(ctypes.byref(ctx), device), "bn_create")
+    return ctx
+
+
+def bn_destroy(ctx):
+    _ck(lib().bn_destroy(ctx), "bn_destroy")
+
+
+def bn_reserve(ctx, nbytes: int):
+    _ck(lib().bn_reserve(ctx, nbytes), "bn_reserve")
+
+
+def bn_workspace_size(ctx, op: int, na: int, nb: int, npairs: int, form: int = BN_MUL_AUTO) -> int:
+    return lib().bn_workspace_size(ctx, op, na, nb, npairs, form)
+
+
+def bn_check(ctx, stream=None):
+    """Synchronise the stream, read and clear the device error latch.
+    Returns (status, flags): status is BN_OK or BN_EWATCHDOG."""
+    flags = ctypes.c_uint32(0)
+    st = lib().bn_check(ctx, _stream(stream), ctypes.byref(flags))
+    if st not in (BN_OK, BN_EWATCHDOG):
+        _ck(st, "bn_check")
+    return st, flags.value
+
+
+def bn_set_param(ctx, key: str, value: int):
+    _ck(lib().bn_set_param(ctx, key.encode(), int(value)), f"bn_set_param({key})")
+
+
+def bn_get_param(ctx, key: str) -> int:
+    v = ctypes.c_int64(0)
+    _ck(lib().bn_get_param(ctx, key.encode(), ctypes.byref(v)), f"bn_get_param({key})")
+    return v.value
+
+
+def bn_param_names():
+    return lib().bn_param_names().decode().split(",")
+
+
+def bn_autotune(ctx, out_json: str | None = None):
+    _ck(lib().bn_autotune(ctx, out_json.encode() if out_json else None), "bn_autotune")
+
+
+def bn_load_tuning(ctx, path: str):
+    _ck(lib().bn_load_tuning(ctx, path.encode()), "bn_load_tuning")
+
+
+# ------------------------------------------------------------------ add / sub ----
+def bn_add(ctx, r, a, b, carry_out=None, stream=None):
+    """r = a + b (one pair, n = a.numel() limbs); carry_out: 1-limb tensor or None."""
+    _ck(lib().bn_add(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), a.numel(), _ptr(carry_out, "carry"),
+                     _stream(stream)), "bn_add")
+
+
+def bn_sub(ctx, r, a, b, borrow_out=None, stream=None):
+    _ck(lib().bn_sub(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), a.numel(), _ptr(borrow_out, "borrow"),
+                     _stream(stream)), "bn_sub")
+
+
+def bn_add_n_batch(ctx, r, a, b, n: int, npairs: int, carry_out=None, stream=None):
+    _ck(lib().bn_add_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(carry_out, "carry"),
+                             _stream(stream)), "bn_add_n_batch")
+
+
+def bn_sub_n_batch(ctx, r, a, b, n: int, npairs: int, borrow_out=None, stream=None):
+    _ck(lib().bn_sub_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(borrow_out, "borrow"),
+                             _stream(stream)), "bn_sub_n_batch")
+
+
+# ------------------------------------------------------------------ multiply ----
+def _form(form):
+    return FORMS[form] if isinstance(form, str) else int(form)
+
+
+def bn_mul(ctx, r, a, b, form=BN_MUL_AUTO, stream=None):
+    _ck(lib().bn_mul(ctx, _ptr(r, "r"), _ptr(a, "a"), a.numel(), _ptr(b, "b"), b.numel(), _form(form),
+                     _stream(stream)), "bn_mul")
+
+
+def bn_mul_n_batch(ctx, r, a, b, na: int, nb: int, npairs: int, form=BN_MUL_AUTO, stream=None):
+    _ck(lib().bn_mul_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), na, nb, npairs, _form(form),
+                             _stream(stream)), "bn_mul_n_batch")
+
+
+# ------------------------------------------------------------------ ragged ----
+def _pairs(desc):
+    """desc: array-like [npairs, 5] of (a_off, b_off, r_off, na, nb)."""
+    d = np.asarray(desc, dtype=np.uint64).reshape(-1, 5)
+    arr = (bn_pair * len(d))()
+    for i, (ao, bo, ro, na, nb) in enumerate(d.tolist()):
+        arr[i] = bn_pair(ao, bo, ro, na, nb)
+    return arr, len(d)
+
+
+def bn_plan_mul_ragged(ctx, desc, form=BN_MUL_AUTO):
+    arr, n = _pairs(desc)
+    plan = _vp()
+    _ck(lib().bn_plan_mul_ragged(ctx, arr, n, _form(form), ctypes.byref(plan)), "bn_plan_mul_ragged")
+    return plan
+
+
+def bn_plan_add_ragged(ctx, desc):
+    arr, n = _pairs(desc)
+    plan = _vp()
+    _ck(lib().bn_plan_add_ragged(ctx, arr, n, ctypes.byref(plan)), "bn_plan_add_ragged")
+    return plan
+
+
+def bn_plan_destroy(plan):
+    _ck(lib().bn_plan_destroy(plan), "bn_plan_destroy")
+
+
+def bn_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, stream=None):
+    _ck(lib().bn_mul_ragged(ctx, plan, _ptr(r_pool, "r"), _ptr(a_pool, "a"), _ptr(b_pool, "b"), _stream(stream)),
+        "bn_mul_ragged")
+
+
+def bn_add_ragged(ctx, plan, r_pool, a_pool, b_pool, carry_out=None, stream=None):
+    _ck(lib().bn_add_ragged(ctx, plan, _ptr(r_pool, "r"), _ptr(a_pool, "a"), _ptr(b_pool, "b"),
+                            _ptr(carry_out, "carry"), _stream(stream)), "bn_add_ragged")
+
+
+# ------------------------------------------------------------------ graphs ----
+def bn_graph_capture_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, stream):
+    g = _vp()
+    _ck(lib().bn_graph_capture_mul_ragged(ctx, plan, _ptr(r_pool, "r"), _ptr(a_pool, "a"), _ptr(b_pool, "b"),
+                                          _stream(stream), ctypes.byref(g)), "bn_graph_capture_mul_ragged")
+    return g
+
+
+def bn_graph_capture_batch(ctx, op: int, r, a, b, na: int, nb: int, npairs: int, carry_out=None,
+                           form=BN_MUL_AUTO, stream=None):
+    g = _vp()
+    _ck(lib().bn_graph_capture_batch(ctx, op, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), na, nb, npairs,
+                                     _ptr(carry_out, "carry"), _form(form), _stream(stream), ctypes.byref(g)),
+        "bn_graph_capture_batch")
+    return g
+
+
+def bn_graph_launch(graph, stream=None):
+    _ck(lib().bn_graph_launch(graph, _stream(stream)), "bn_graph_launch")
+
+
+def bn_graph_destroy(graph):
+    _ck(lib().bn_graph_destroy(graph), "bn_graph_destroy")
+
+
+# ------------------------------------------------------------------ helpers ----
+def to_device(x: np.ndarray, device="cuda"):
+    """numpy uint64 limbs -> torch int64 device tensor (same bits)."""
+    import torch
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    return torch.from_numpy(x.view(np.int64)).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    """torch int64/uint64 device tensor -> numpy uint64 limbs."""
+    import torch
+    if t.dtype == torch.uint64:
+        t = t.view(torch.int64)
+    return t.detach().cpu().numpy().view(np.uint64)

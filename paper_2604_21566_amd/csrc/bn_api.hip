@@ -1,0 +1,442 @@
+// bn_api.hip -- the C ABI: contexts, argument validation, workspace, dispatch,
+// parameters, HIP-graph capture.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <functional>
+#include <string>
+
+#include "bn_internal.h"
+
+#define BN_VERSION_STRING "bn-mi355x 0.1.0 (gfx950)"
+
+bool flat_scan_shape_ok(int waves, int rows);
+
+bn_status bn_launch_status() { return hipGetLastError() == hipSuccess ? BN_OK : BN_EHIP; }
+
+bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s) {
+    if (buf.bytes >= bytes) return BN_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return BN_EHIP;
+    if (cs != hipStreamCaptureStatusNone) return BN_ECAPTURE;
+    size_t want = std::max(bytes, buf.bytes + buf.bytes / 2);
+    want = (want + 65535) & ~(size_t)65535;
+    if (buf.ptr) {
+        if (hipDeviceSynchronize() != hipSuccess) return BN_EHIP;
+        (void)hipFree(buf.ptr);
+        buf.ptr = nullptr;
+        buf.bytes = 0;
+    }
+    if (hipMalloc(&buf.ptr, want) != hipSuccess) {
+        buf.ptr = nullptr;
+        return BN_ENOMEM;
+    }
+    // status words must start below every epoch in use (epoch >= 1)
+    if (hipMemset(buf.ptr, 0, want) != hipSuccess) return BN_EHIP;
+    buf.bytes = want;
+    return BN_OK;
+}
+
+// ------------------------------------------------------------------ helpers ----
+static bool overlaps(const void *x, size_t xbytes, const void *y, size_t ybytes) {
+    const uintptr_t a0 = (uintptr_t)x, a1 = a0 + xbytes, b0 = (uintptr_t)y, b1 = b0 + ybytes;
+    return xbytes && ybytes && a0 < b1 && b0 < a1;
+}
+
+static bool mul_overflow(size_t a, size_t b, size_t *out) { return __builtin_mul_overflow(a, b, out); }
+
+static bn_status check_ptr(const void *p, size_t limbs) {
+    if (limbs == 0) return BN_OK;
+    if (!p) return BN_EINVAL;
+    if ((uintptr_t)p & 7u) return BN_EINVAL;
+    return BN_OK;
+}
+
+static inline hipStream_t S(bn_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// ------------------------------------------------------------------ context ----
+extern "C" {
+
+const char *bn_version(void) { return BN_VERSION_STRING; }
+
+const char *bn_strerror(bn_status s) {
+    switch (s) {
+        case BN_OK: return "ok";
+        case BN_EINVAL: return "invalid argument";
+        case BN_EALIAS: return "output overlaps an input";
+        case BN_ERANGE: return "size out of range";
+        case BN_ENOMEM: return "device allocation failed";
+        case BN_EHIP: return "HIP runtime error";
+        case BN_EUNSUPPORTED: return "unsupported device or feature";
+        case BN_ECAPTURE: return "workspace must grow during stream capture (call bn_reserve first)";
+        case BN_EWATCHDOG: return "look-back watchdog fired";
+        default: return "unknown status";
+    }
+}
+
+bn_status bn_create(bn_ctx **out, int device) {
+    if (!out) return BN_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return BN_EUNSUPPORTED;
+    if (device < 0 || device >= ndev) return BN_EINVAL;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return BN_EHIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BN_EUNSUPPORTED;
+    DeviceGuard g(device);
+    bn_ctx *ctx = new bn_ctx();
+    ctx->device = device;
+    ctx->num_cu = prop.multiProcessorCount;
+    if (hipMalloc(&ctx->ctl, sizeof(ScanCtl)) != hipSuccess) {
+        delete ctx;
+        return BN_ENOMEM;
+    }
+    ScanCtl init{};
+    init.epoch = 1;
+    if (hipMemcpy(ctx->ctl, &init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(ctx->ctl);
+        delete ctx;
+        return BN_EHIP;
+    }
+    *out = ctx;
+    return BN_OK;
+}
+
+bn_status bn_destroy(bn_ctx *ctx) {
+    if (!ctx) return BN_OK;
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->status.ptr) (void)hipFree(ctx->status.ptr);
+    if (ctx->work.ptr) (void)hipFree(ctx->work.ptr);
+    if (ctx->ctl) (void)hipFree(ctx->ctl);
+    delete ctx;
+    return BN_OK;
+}
+
+bn_status bn_reserve(bn_ctx *ctx, size_t bytes) {
+    if (!ctx) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    return bn_ensure(ctx, ctx->work, bytes, nullptr);
+}
+
+size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form) {
+    if (!ctx) return 0;
+    if (op == 0) return 0;  // add/sub only use the status array, sized by bn_reserve_status internally
+    return mul_workspace_bytes(ctx, na, nb, npairs, form);
+}
+
+bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags) {
+    if (!ctx) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (hipStreamSynchronize(S(stream)) != hipSuccess) return BN_EHIP;
+    u64 err = 0;
+    if (hipMemcpy(&err, &ctx->ctl->err, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) return BN_EHIP;
+    const u64 zero = 0;
+    if (hipMemcpy(&ctx->ctl->err, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return BN_EHIP;
+    if (flags) *flags = (uint32_t)err;
+    return (err & 1u) ? BN_EWATCHDOG : BN_OK;
+}
+
+// --------------------------------------------------------------- add / sub ----
+static bn_status addsub(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                        size_t npairs, uint64_t *carry, bn_stream stream) {
+    if (!ctx) return BN_EINVAL;
+    size_t N;
+    if (mul_overflow(n, npairs, &N) || N > BN_MAX_LIMBS) return BN_ERANGE;
+    bn_status st;
+    if ((st = check_ptr(r, N)) || (st = check_ptr(a, N)) || (st = check_ptr(b, N))) return st;
+    if (carry && ((uintptr_t)carry & 7u)) return BN_EINVAL;
+    const size_t bytes = N * 8;
+    if ((r != a && overlaps(r, bytes, a, bytes)) || (r != b && overlaps(r, bytes, b, bytes))) return BN_EALIAS;
+    if (carry && (overlaps(carry, npairs * 8, r, bytes) || overlaps(carry, npairs * 8, a, bytes) ||
+                  overlaps(carry, npairs * 8, b, bytes)))
+        return BN_EALIAS;
+    DeviceGuard g(ctx->device);
+    return launch_flat_scan(ctx, sub, r, a, b, n, npairs, carry, S(stream));
+}
+
+bn_status bn_add(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, uint64_t *carry_out,
+                 bn_stream stream) {
+    return addsub(ctx, false, r, a, b, n, 1, carry_out, stream);
+}
+
+bn_status bn_sub(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, uint64_t *borrow_out,
+                 bn_stream stream) {
+    return addsub(ctx, true, r, a, b, n, 1, borrow_out, stream);
+}
+
+bn_status bn_add_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                         uint64_t *carry_out, bn_stream stream) {
+    return addsub(ctx, false, r, a, b, n, npairs, carry_out, stream);
+}
+
+bn_status bn_sub_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                         uint64_t *borrow_out, bn_stream stream) {
+    return addsub(ctx, true, r, a, b, n, npairs, borrow_out, stream);
+}
+
+// ---------------------------------------------------------------- multiply ----
+static bn_status mul_args(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na, size_t nb,
+                          size_t npairs, int form) {
+    if (!ctx) return BN_EINVAL;
+    if (form != BN_MUL_AUTO && form != BN_MUL_MAD && form != BN_MUL_MFMA) return BN_EINVAL;
+    if (na > BN_MAX_LIMBS || nb > BN_MAX_LIMBS) return BN_ERANGE;
+    size_t A, B, R;
+    if (mul_overflow(na, npairs, &A) || mul_overflow(nb, npairs, &B) || mul_overflow(na + nb, npairs, &R) ||
+        R > 2 * BN_MAX_LIMBS)
+        return BN_ERANGE;
+    bn_status st;
+    if ((st = check_ptr(r, R)) || (st = check_ptr(a, A)) || (st = check_ptr(b, B))) return st;
+    if (overlaps(r, R * 8, a, A * 8) || overlaps(r, R * 8, b, B * 8)) return BN_EALIAS;
+    return BN_OK;
+}
+
+bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb, int form,
+                 bn_stream stream) {
+    bn_status st = mul_args(ctx, r, a, b, na, nb, 1, form);
+    if (st != BN_OK) return st;
+    DeviceGuard g(ctx->device);
+    return launch_mul_batch(ctx, r, a, b, na, nb, 1, form, S(stream));
+}
+
+bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na, size_t nb,
+                         size_t npairs, int form, bn_stream stream) {
+    bn_status st = mul_args(ctx, r, a, b, na, nb, npairs, form);
+    if (st != BN_OK) return st;
+    DeviceGuard g(ctx->device);
+    return launch_mul_batch(ctx, r, a, b, na, nb, npairs, form, S(stream));
+}
+
+// ------------------------------------------------------------------ ragged ----
+bn_status bn_plan_mul_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, int form, bn_plan **plan) {
+    if (!ctx || !plan || (npairs && !host_pairs)) return BN_EINVAL;
+    if (form != BN_MUL_AUTO && form != BN_MUL_MAD && form != BN_MUL_MFMA) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    return plan_mul_ragged(ctx, host_pairs, npairs, form, plan);
+}
+
+bn_status bn_plan_add_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, bn_plan **plan) {
+    if (!ctx || !plan || (npairs && !host_pairs)) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    return plan_add_ragged(ctx, host_pairs, npairs, plan);
+}
+
+bn_status bn_plan_destroy(bn_plan *plan) {
+    if (!plan) return BN_OK;
+    DeviceGuard g(plan->device);
+    (void)hipDeviceSynchronize();
+    if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_counter) (void)hipFree(plan->d_counter);
+    delete plan;
+    return BN_OK;
+}
+
+bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
+                        const uint64_t *b_pool, bn_stream stream) {
+    if (!ctx || !plan || plan->op != 0) return BN_EINVAL;
+    if (plan->npairs && (!r_pool || !a_pool || !b_pool)) return BN_EINVAL;
+    if (((uintptr_t)r_pool | (uintptr_t)a_pool | (uintptr_t)b_pool) & 7u) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    return launch_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, S(stream));
+}
+
+bn_status bn_add_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
+                        const uint64_t *b_pool, uint64_t *carry_out, bn_stream stream) {
+    if (!ctx || !plan || plan->op != 1) return BN_EINVAL;
+    if (plan->npairs && (!r_pool || !a_pool || !b_pool)) return BN_EINVAL;
+    if (((uintptr_t)r_pool | (uintptr_t)a_pool | (uintptr_t)b_pool | (uintptr_t)carry_out) & 7u) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    return launch_add_ragged(ctx, plan, r_pool, a_pool, b_pool, carry_out, S(stream));
+}
+
+// ------------------------------------------------------------------ graphs ----
+static bn_status capture(bn_stream stream, bn_graph **out, const std::function<bn_status()> &body);
+
+bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
+                                      const uint64_t *b_pool, bn_stream stream, bn_graph **graph) {
+    if (!ctx || !plan || !graph || !stream) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    // large items use the batched pipeline: reserve its workspace before capture
+    size_t need = 0, status = 0;
+    for (const RItem &it : plan->large) {
+        need = std::max(need, mul_workspace_bytes(ctx, it.na, it.nb, 1, (int)it.form));
+        status = std::max(status, flat_scan_status_bytes(ctx, (u64)it.na + it.nb));
+    }
+    bn_status st;
+    if ((st = bn_ensure(ctx, ctx->work, need, nullptr)) != BN_OK) return st;
+    if ((st = bn_ensure(ctx, ctx->status, status, nullptr)) != BN_OK) return st;
+    return capture(stream, graph, [&]() { return bn_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, stream); });
+}
+
+bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na,
+                                 size_t nb, size_t npairs, uint64_t *carry_out, int form, bn_stream stream,
+                                 bn_graph **graph) {
+    if (!ctx || !graph || !stream || op < 0 || op > 2) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    bn_status st;
+    if (op == 2) {
+        if ((st = mul_args(ctx, r, a, b, na, nb, npairs, form)) != BN_OK) return st;
+        if ((st = bn_ensure(ctx, ctx->work, mul_workspace_bytes(ctx, na, nb, npairs, form), nullptr)) != BN_OK)
+            return st;
+        if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)(na + nb) * npairs), nullptr)) !=
+            BN_OK)
+            return st;
+        return capture(stream, graph,
+                       [&]() { return bn_mul_n_batch(ctx, r, a, b, na, nb, npairs, form, stream); });
+    }
+    if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)na * npairs), nullptr)) != BN_OK)
+        return st;
+    return capture(stream, graph, [&]() {
+        return op == 0 ? bn_add_n_batch(ctx, r, a, b, na, npairs, carry_out, stream)
+                       : bn_sub_n_batch(ctx, r, a, b, na, npairs, carry_out, stream);
+    });
+}
+
+bn_status bn_graph_launch(bn_graph *graph, bn_stream stream) {
+    if (!graph || !graph->exec) return BN_EINVAL;
+    return hipGraphLaunch(graph->exec, S(stream)) == hipSuccess ? BN_OK : BN_EHIP;
+}
+
+bn_status bn_graph_destroy(bn_graph *graph) {
+    if (!graph) return BN_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return BN_OK;
+}
+
+// ------------------------------------------------------------------ params ----
+static const char *kParamNames =
+    "addsub.waves,addsub.rows,addsub.small_waves,addsub.small_rows,addsub.small_limit,"
+    "mul.crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,watchdog.spin_limit,debug.flags";
+
+const char *bn_param_names(void) { return kParamNames; }
+
+bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
+    if (!ctx || !key) return BN_EINVAL;
+    Tuning &t = ctx->tune;
+    const std::string k(key);
+    if (k == "addsub.waves" || k == "addsub.rows") {
+        const int w = k == "addsub.waves" ? (int)v : t.addsub_waves;
+        const int r = k == "addsub.rows" ? (int)v : t.addsub_rows;
+        if (!flat_scan_shape_ok(w, r)) return BN_EINVAL;
+        t.addsub_waves = w;
+        t.addsub_rows = r;
+    } else if (k == "addsub.small_waves" || k == "addsub.small_rows") {
+        const int w = k == "addsub.small_waves" ? (int)v : t.small_addsub_waves;
+        const int r = k == "addsub.small_rows" ? (int)v : t.small_addsub_rows;
+        if (!flat_scan_shape_ok(w, r)) return BN_EINVAL;
+        t.small_addsub_waves = w;
+        t.small_addsub_rows = r;
+    } else if (k == "addsub.small_limit") {
+        if (v < 0) return BN_EINVAL;
+        t.small_addsub_limit = v;
+    } else if (k == "mul.crossover_limbs") {
+        if (v < 1) return BN_EINVAL;
+        t.mul_crossover_limbs = v;
+    } else if (k == "mul.mad_xchunk") {
+        if (v < 64 || v > (1 << 20) || (v % 8)) return BN_EINVAL;
+        t.mad_xchunk = (int)v;
+    } else if (k == "mul.mfma_chunk") {
+        if (v < 16 || v > 4095) return BN_EINVAL;  // int32 accumulator bound: 4095 steps of 32 products <= 2^14
+        t.mfma_chunk = (int)v;
+    } else if (k == "watchdog.spin_limit") {
+        if (v < 0 || v > 0xffffffffll) return BN_EINVAL;
+        t.spin_limit = (u32)v;
+    } else if (k == "debug.flags") {
+        if (v < 0 || v > 1) return BN_EINVAL;
+        t.debug_flags = (u32)v;
+    } else {
+        return BN_EINVAL;
+    }
+    return BN_OK;
+}
+
+bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
+    if (!ctx || !key || !v) return BN_EINVAL;
+    const Tuning &t = ctx->tune;
+    const std::string k(key);
+    if (k == "addsub.waves") *v = t.addsub_waves;
+    else if (k == "addsub.rows") *v = t.addsub_rows;
+    else if (k == "addsub.small_waves") *v = t.small_addsub_waves;
+    else if (k == "addsub.small_rows") *v = t.small_addsub_rows;
+    else if (k == "addsub.small_limit") *v = t.small_addsub_limit;
+    else if (k == "mul.crossover_limbs") *v = t.mul_crossover_limbs;
+    else if (k == "mul.mad_xchunk") *v = t.mad_xchunk;
+    else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;
+    else if (k == "watchdog.spin_limit") *v = t.spin_limit;
+    else if (k == "debug.flags") *v = t.debug_flags;
+    else return BN_EINVAL;
+    return BN_OK;
+}
+
+bn_status bn_load_tuning(bn_ctx *ctx, const char *path) {
+    if (!ctx || !path) return BN_EINVAL;
+    FILE *f = fopen(path, "rb");
+    if (!f) return BN_EINVAL;
+    std::string s;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, got);
+    fclose(f);
+    // flat object of "key": integer pairs
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) return BN_EINVAL;
+        const std::string key = s.substr(i + 1, j - i - 1);
+        size_t c = s.find(':', j);
+        if (c == std::string::npos) return BN_EINVAL;
+        ++c;
+        while (c < s.size() && (s[c] == ' ' || s[c] == '\t' || s[c] == '\n' || s[c] == '\r')) ++c;
+        char *end = nullptr;
+        const long long v = strtoll(s.c_str() + c, &end, 10);
+        if (end == s.c_str() + c) {
+            // non-integer value (e.g. a string annotation): skip it
+            i = s.find_first_of(",}", c);
+            if (i == std::string::npos) break;
+            continue;
+        }
+        bn_status st = bn_set_param(ctx, key.c_str(), v);
+        if (st != BN_OK && key.find('.') != std::string::npos) return st;
+        i = (size_t)(end - s.c_str());
+    }
+    return BN_OK;
+}
+
+}  // extern "C"
+
+static bn_status capture(bn_stream stream, bn_graph **out, const std::function<bn_status()> &body) {
+    hipStream_t s = S(stream);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return BN_EHIP;
+    bn_status st = body();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != BN_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess || !graph) return BN_EHIP;
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return BN_EHIP;
+    }
+    bn_graph *g = new bn_graph();
+    g->graph = graph;
+    g->exec = exec;
+    *out = g;
+    return BN_OK;
+}

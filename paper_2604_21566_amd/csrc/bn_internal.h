@@ -1,0 +1,117 @@
+// Internal declarations shared by the library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bn.h"
+
+#include <vector>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+#define BN_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return BN_EHIP;          \
+    } while (0)
+
+// Device-side control block of the decoupled look-back (one per context).
+//   ticket : next tile id to hand out (forward-progress order, reset by the last WG)
+//   done   : WGs finished in the current launch (reset by the last WG)
+//   epoch  : tags status words; bumped by the last WG so stale words never match
+//   err    : sticky error latch (bit 0 = watchdog), cleared by bn_check
+struct ScanCtl {
+    u64 ticket;
+    u64 done;
+    u64 epoch;
+    u64 err;
+    u64 pad[4];
+};
+
+// Tile-shape selector for the flat scan kernel.
+struct ScanShape {
+    int waves;  // waves per workgroup (1, 4 or 8)
+    int rows;   // 128-limb rows per wave (1, 2, 4, 8 or 16)
+};
+
+struct Tuning {
+    int addsub_waves = 4;
+    int addsub_rows = 8;
+    int small_addsub_waves = 1;   // used when the whole batch is tiny
+    int small_addsub_rows = 1;
+    i64 small_addsub_limit = 1 << 16;  // N (total limbs) at or below which the small shape is used
+    i64 mul_crossover_limbs = 256;     // BN_MUL_AUTO: MFMA when min(na, nb) >= this
+    int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
+    int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
+    int mfma_chunk = 1024;             // d-steps per MFMA work item (<= overflow bound)
+    u32 spin_limit = 1u << 24;         // look-back wait bound
+    u32 debug_flags = 0;               // bit 0: first tile never publishes (watchdog test)
+};
+
+// Workspace buffer that grows on demand (never while the stream is being captured).
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct bn_ctx {
+    int device = 0;
+    int num_cu = 256;           // compute units (sizes persistent grids)
+    ScanCtl *ctl = nullptr;     // device control block
+    DevBuf status;              // look-back status words
+    DevBuf work;                // mul column accumulators / folded limbs
+    Tuning tune;
+};
+
+// One pair of a ragged batch as the device sees it.
+struct RItem {
+    u64 a_off, b_off, r_off;
+    u32 na, nb;
+    u32 form;   // BN_MUL_MAD / BN_MUL_MFMA (mul) or unused (add)
+    u32 index;  // position in the caller's descriptor array
+};
+
+struct bn_plan {
+    int op = 0;                    // 0 = mul ragged, 1 = add ragged
+    int device = 0;
+    size_t npairs = 0;
+    u32 nsmall = 0;                // items run by the persistent kernel (sorted by work, largest first)
+    RItem *d_items = nullptr;      // device copy of the small items
+    u32 *d_counter = nullptr;      // {next item, finished waves}; reset by the last wave
+    std::vector<RItem> large;      // mul items too big for one wave: one batched launch each
+    u32 nmad = 0, nmfma = 0;       // items per form
+    u64 work = 0;                  // sum of na * nb (mul) or n (add)
+};
+
+struct bn_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// ---- internal helpers (bn_api.hip) ----
+bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s);
+bn_status bn_launch_status();
+
+// ---- add/sub (k_addsub.hip) ----
+// Flat segmented add/sub over N = n * npairs limbs; a segment (pair) starts every n limbs.
+bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
+                           u64 *carry, hipStream_t s);
+size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 N);
+bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s);
+
+// ---- mul (k_mul_*.hip) ----
+bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 na, u64 nb, u64 npairs,
+                           int form, hipStream_t s);
+size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form);
+int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form);
+
+// ---- ragged (k_ragged.hip) ----
+bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int form, bn_plan **plan);
+bn_status plan_add_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, bn_plan **plan);
+bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *plan, u64 *r, const u64 *a, const u64 *b, hipStream_t s);
+bn_status launch_add_ragged(bn_ctx *ctx, const bn_plan *plan, u64 *r, const u64 *a, const u64 *b, u64 *carry,
+                            hipStream_t s);

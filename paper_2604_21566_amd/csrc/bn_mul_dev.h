@@ -1,0 +1,302 @@
+// bn_mul_dev.h -- device building blocks of the two multiplication forms.
+//
+// Both forms follow DoT multiplication (Sec. 3.2, Algorithm 2, "vertical and
+// crosswise"): every cross product A_i * B_j is independent and lands in output
+// column i + j (Theorem 2); the column sums are formed first and the carries are
+// resolved once at the end.  What differs from the paper is the digit size and the
+// unit that forms the products:
+//   * mad form  : 32-bit digits, v_mad_u64_u32 with a carry-out into a 96-bit
+//                 column accumulator (the paper's IFMA lo/hi products become one
+//                 32x32->64 multiply-add per digit pair);
+//   * MFMA form : 8-bit digits (the byte view of the limb array, as the paper
+//                 splits 64-bit limbs to fit its multiplier), the digit
+//                 convolution written as a block-Toeplitz matrix product on
+//                 v_mfma_i32_32x32x32_i8 with int32 accumulation.
+// The deferred carry pass (Algorithm 2, phase 5) is: fold each limb's column sums
+// into V_j = lo_j + 2^64 hi_j, then r = sum_j lo_j X^j + sum_j hi_j X^(j+1), i.e.
+// one big-integer addition whose carries are single bits (g/p scan).
+#pragma once
+
+#include "bn_internal.h"
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned __int128 u128;
+
+#define BN_DPP_WAVE_SHR1 0x138
+
+// lo:hi (96-bit) += x * y, using the carry-out of v_mad_u64_u32.
+__device__ __forceinline__ void mac96(u64 &lo, u32 &hi, u32 x, u32 y) {
+    u64 cc;
+    asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+        "v_addc_co_u32 %2, %1, 0, %2, %1"
+        : "+v"(lo), "=&s"(cc), "+v"(hi)
+        : "v"(x), "v"(y));
+}
+
+// Wave-local LDS ordering point (all waves of a workgroup run independently).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ u32 bytesum64(u64 v) {
+    return __builtin_amdgcn_sad_u8((u32)v, 0u, __builtin_amdgcn_sad_u8((u32)(v >> 32), 0u, 0u));
+}
+
+// Deferred carry pass inside one wave.  Lane l owns limbs j = l*L + k (k < L) with
+// values V_j = lo[k] + 2^64 hi[k] (hi small).  Writes r[j] for j < P.  The sum of all
+// V_j X^j is the product, which fits P limbs, so the final carry is zero.
+template <int L>
+__device__ __forceinline__ void wave_normalise_store(const u64 (&lo)[L], const u64 (&hi)[L], u32 P, u64 *r) {
+    const int lane = threadIdx.x & 63;
+    u64 prev = __shfl_up(hi[L - 1], 1);
+    if (lane == 0) prev = 0;
+    u64 x[L];
+    bool g[L], p[L];
+    bool G = false, PP = true;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const u32 j = (u32)lane * L + k;
+        const u64 h = (k == 0) ? prev : hi[k - 1];
+        x[k] = lo[k] + h;
+        const bool v = j < P;
+        g[k] = v && (x[k] < h);
+        p[k] = v && (x[k] == ~0ull);
+        G = g[k] || (p[k] && G);
+        PP = PP && p[k];
+    }
+    const u64 Gm = __ballot(G), Pm = __ballot(PP);
+    const u64 C = ((Gm << 1) + Pm) ^ Pm;
+    bool c = (C >> lane) & 1ull;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const u32 j = (u32)lane * L + k;
+        if (j < P) r[j] = x[k] + (u64)c;
+        c = g[k] || (p[k] && c);
+    }
+}
+
+// ------------------------------------------------------------------ mad form ----
+// One wave computes one product of P = na + nb <= 64 L limbs.  Lane l owns the
+// 32-bit columns t = 2 L l + q (q < 2L).  All lanes step through the 32-bit digits
+// x of a together: alpha_x is wave-uniform; column t needs beta_{t-x}.  The beta
+// window of a lane slides down by one digit per step, so the new bottom element is
+// the neighbouring lane's top element: one DPP wave_shr:1 per step (lane 0 receives
+// beta at a negative index, i.e. 0).
+template <int L>
+__device__ void mul_item_mad(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
+                             u64 *__restrict__ r) {
+    constexpr int Q = 2 * L;
+    const int lane = threadIdx.x & 63;
+    const u32 *a32 = reinterpret_cast<const u32 *>(a);
+    const u32 *b32 = reinterpret_cast<const u32 *>(b);
+    const u32 nx = 2 * na, ny = 2 * nb;
+    const u32 t0 = (u32)lane * Q;
+    u32 R[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const u32 y = t0 + q;
+        R[q] = y < ny ? b32[y] : 0u;
+    }
+    u64 lo[Q];
+    u32 hi[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        lo[q] = 0;
+        hi[q] = 0;
+    }
+    for (u32 xb = 0; xb < nx; xb += Q) {
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const u32 x = xb + s;
+            const u32 al = x < nx ? a32[x] : 0u;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) mac96(lo[q], hi[q], al, R[(q - s + Q) % Q]);
+            const int k = (Q - 1 - s + Q) % Q;
+            R[k] = (u32)__builtin_amdgcn_update_dpp(0, (int)R[k], BN_DPP_WAVE_SHR1, 0xf, 0xf, true);
+        }
+    }
+    u64 vlo[L], vhi[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const u128 v = (u128)lo[2 * k] + ((u128)hi[2 * k] << 64) + ((u128)lo[2 * k + 1] << 32) +
+                       ((u128)hi[2 * k + 1] << 96);
+        vlo[k] = (u64)v;
+        vhi[k] = (u64)(v >> 64);
+    }
+    wave_normalise_store<L>(vlo, vhi, na + nb, r);
+}
+
+// ----------------------------------------------------------------- MFMA form ----
+// Digit convolution as block-Toeplitz products.  With 8-bit digits a_i, b_j and
+// output digit columns t = 32 W + rr (rr < 32):
+//     C[32 W + rr] = sum_d sum_k T_d[rr][k] * A_d[k][W]
+//     T_d[rr][k]   = b[32 (d-1) + rr + 1 + k]          (Toeplitz in rr - k)
+//     A_d[k][W]    = a[32 (W-d) + 31 - k]              (32-digit chunk W-d, reversed)
+// so one v_mfma_i32_32x32x32_i8 per (d, block of 32 W) forms 32x32 column sums.
+// The instruction multiplies signed int8, so digits enter as a' = a - 128 (byte
+// xor 0x80) and padding as signed 0; the exact unsigned column sum is restored in
+// the fold: C = C' + 128 (S_a + S_b) - 16384 cnt, with S_a, S_b the sums of the
+// unsigned digits that meet in the column and cnt the number of digit pairs.
+// |a' b'| <= 2^14, 32 products per step: an int32 accumulator stays exact for up
+// to 4095 steps; work items are cut into chunks of at most 4095 steps.
+//
+// Operand registers: lane (x = lane & 31, h = lane >> 5) supplies bytes k = 16 h .. 16 h + 15
+// of row x of T_d (A-operand) and of column x of A_d (B-operand).  Both operands
+// use the same (h, byte) -> k assignment, so the contraction pairs the right bytes
+// whatever order the hardware uses inside the K dimension.
+
+// T_d row fragment from a byte array staged in LDS (as 32-bit words).  `off` is the
+// byte offset of the row's first digit, 32 (d-1) + rr + 1 + 16 h relative to the
+// staging base; reads 5 aligned words and funnel-shifts them.
+__device__ __forceinline__ v4i toeplitz_frag(const u32 *__restrict__ lds_words, u32 off) {
+    const u32 q = off >> 2, s = off & 3u;
+    const u32 w0 = lds_words[q], w1 = lds_words[q + 1], w2 = lds_words[q + 2], w3 = lds_words[q + 3],
+              w4 = lds_words[q + 4];
+    v4i t;
+    t.x = (int)__builtin_amdgcn_alignbyte(w1, w0, s);
+    t.y = (int)__builtin_amdgcn_alignbyte(w2, w1, s);
+    t.z = (int)__builtin_amdgcn_alignbyte(w3, w2, s);
+    t.w = (int)__builtin_amdgcn_alignbyte(w4, w3, s);
+    return t;
+}
+
+// Accumulator element (reg g of lane l) -> (row rr, column x) of the 32x32 tile.
+__device__ __forceinline__ u32 acc_row(int g, int lane) { return (u32)((g & 3) + 4 * (lane >> 5) + 8 * (g >> 2)); }
+
+// Sum of the unsigned digits x in [0, X) of an operand, from a per-limb prefix table
+// lp[k] = sum of the digits of limbs < k.
+__device__ __forceinline__ i64 digit_prefix(const u64 *__restrict__ limbs, const u32 *__restrict__ lp, u64 x) {
+    const u64 k = x >> 3;
+    const u32 rem = (u32)(x & 7);
+    i64 s = lp[k];
+    if (rem) s += bytesum64(limbs[k] & ((1ull << (8 * rem)) - 1));
+    return s;
+}
+
+// Exact unsigned column sum from the signed-digit MFMA sum m of column t.
+__device__ __forceinline__ i64 column_fix(i64 m, u64 t, u64 nda, u64 ndb, const u64 *__restrict__ a,
+                                          const u32 *__restrict__ lpa, const u64 *__restrict__ b,
+                                          const u32 *__restrict__ lpb) {
+    const u64 ilo = t + 1 > ndb ? t + 1 - ndb : 0;
+    const u64 ihi = t < nda - 1 ? t : nda - 1;
+    if (ilo > ihi) return 0;
+    const i64 sa = digit_prefix(a, lpa, ihi + 1) - digit_prefix(a, lpa, ilo);
+    const i64 sb = digit_prefix(b, lpb, t - ilo + 1) - digit_prefix(b, lpb, t - ihi);
+    const i64 cnt = (i64)(ihi - ilo + 1);
+    return m + 128 * (sa + sb) - 16384 * cnt;
+}
+
+// ------------------------------------------------- small products, MFMA form ----
+constexpr u64 BN_XOR80 = 0x8080808080808080ull;
+
+// Per-limb digit-sum prefix of one operand (n <= 255 limbs) by one wave:
+// lp[k] = sum of the digits of limbs [0, k), k = 0..n.
+__device__ __forceinline__ void wave_prefix_digits(const u64 *__restrict__ limbs, u32 n, u32 *lp) {
+    const int lane = threadIdx.x & 63;
+    u32 s[4];
+    u32 tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const u32 m = 4 * lane + k;
+        s[k] = m < n ? bytesum64(limbs[m]) : 0u;
+        tot += s[k];
+    }
+    u32 v = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const u32 t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    u32 run = v - tot;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const u32 m = 4 * lane + k;
+        if (m <= n) lp[m] = run;
+        run += s[k];
+    }
+}
+
+// LDS words (u64) needed per wave by the small MFMA form.
+constexpr int SMALL_MFMA_LDS_U64 = 272 + 256 + 128 + 128;  // bz, aR, lpa (256 u32), lpb (256 u32)
+
+// One product of P = na + nb <= 256 limbs on the MFMA form, one wave.
+// lds: SMALL_MFMA_LDS_U64 words private to the wave.
+__device__ __noinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
+                                    u64 *__restrict__ r, u64 *lds) {
+    const int lane = threadIdx.x & 63;
+    const u32 x = lane & 31, h = lane >> 5;
+    const u32 nda = 8 * na, ndb = 8 * nb, P = na + nb;
+    const u32 nca = (na + 3) / 4;  // 32-digit chunks of a
+    u64 *bz = lds;                 // [0,4) zero pad, [4, 4+nb) b' limbs, then zeros
+    u64 *aR = lds + 272;           // reversed signed digits of a, 4*nca limbs
+    u32 *lpa = reinterpret_cast<u32 *>(lds + 528);
+    u32 *lpb = lpa + 256;
+    for (u32 k = lane; k < nb + 16; k += 64) bz[k] = (k >= 4 && k < 4 + nb) ? (b[k - 4] ^ BN_XOR80) : 0ull;
+    for (u32 k = lane; k < 4 * nca; k += 64) {
+        const u32 m = 4 * nca - 1 - k;
+        aR[k] = m < na ? __builtin_bswap64(a[m] ^ BN_XOR80) : 0ull;
+    }
+    wave_prefix_digits(a, na, lpa);
+    wave_prefix_digits(b, nb, lpb);
+    wave_sync();
+
+    const u32 dmax = (ndb + 30) / 32;
+    const bool two = P > 128;
+    const u32 *bz32 = reinterpret_cast<const u32 *>(bz);
+    v16i acc0 = {0}, acc1 = {0};
+    for (u32 d = 0; d <= dmax; ++d) {
+        const v4i T = toeplitz_frag(bz32, 32 * d + x + 1 + 16 * h);
+        {
+            const int c = (int)x - (int)d;
+            v4i A = {0, 0, 0, 0};
+            if (c >= 0 && c < (int)nca) A = *reinterpret_cast<const v4i *>(aR + 4 * nca - 4 * (c + 1) + 2 * h);
+            acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(T, A, acc0, 0, 0, 0);
+        }
+        if (two) {
+            const int c = 32 + (int)x - (int)d;
+            v4i A = {0, 0, 0, 0};
+            if (c >= 0 && c < (int)nca) A = *reinterpret_cast<const v4i *>(aR + 4 * nca - 4 * (c + 1) + 2 * h);
+            acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(T, A, acc1, 0, 0, 0);
+        }
+    }
+
+    // Limb j = 4 W + m holds digit columns t = 32 W + 8 m + u (u < 8); lane (x, h) has
+    // u = 4h .. 4h+3 of limbs 4 (32 blk + x) + m.  Each lane folds its half, then
+    // partners (lane xor 32) swap halves so that lane l ends up owning limbs 4l .. 4l+3.
+    u64 plo[2][4], phi[2][4];
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            u128 v = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int g = 4 * m + i;
+                const int raw = blk ? acc1[g] : acc0[g];
+                const u64 t = 32ull * (32 * blk + x) + 8 * m + 4 * h + i;
+                const i64 cf = (t < 8ull * P) ? column_fix(raw, t, nda, ndb, a, lpa, b, lpb) : 0;
+                v += (u128)(u64)cf << (8 * (4 * h + i));
+            }
+            plo[blk][m] = (u64)v;
+            phi[blk][m] = (u64)(v >> 64);
+        }
+    }
+    u64 vlo[4], vhi[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const u64 slo = h ? plo[0][m] : plo[1][m];
+        const u64 shi = h ? phi[0][m] : phi[1][m];
+        const u64 rlo = __shfl_xor(slo, 32);
+        const u64 rhi = __shfl_xor(shi, 32);
+        const u64 klo = h ? plo[1][m] : plo[0][m];
+        const u64 khi = h ? phi[1][m] : phi[0][m];
+        const u128 s = (((u128)khi << 64) | klo) + (((u128)rhi << 64) | rlo);
+        vlo[m] = (u64)s;
+        vhi[m] = (u64)(s >> 64);
+    }
+    wave_normalise_store<4>(vlo, vhi, P, r);
+}
+

@@ -1,0 +1,348 @@
+// k_addsub.hip -- flat segmented add/sub as one generate/propagate prefix scan.
+//
+// DoT (Sec. 3.1, Algorithm 1) separates the limb-parallel work (phase 1: raw limb
+// sums; phase 2: carry detection via Lemma 1) from carry resolution (phases 3-4).
+// On CDNA4 the resolution is restated as a prefix scan over (generate, propagate)
+// flags with three levels:
+//   * inside a wave: one __ballot per flag gives 64-bit masks G and P, and the
+//     Kogge-Stone style integer addition that phase 4 applies to its w-bit masks
+//     resolves all 64 lanes at once: C = (((G << 1) | cin) + P) xor P is the
+//     carry-into-lane mask (valid because a limb never both generates and
+//     propagates);
+//   * across the waves of a workgroup: their (g, p) aggregates through LDS;
+//   * across workgroups: decoupled look-back over per-tile status words, in place
+//     of Algorithm 1's sequential chunk-to-chunk carry (c_out of one chunk is the
+//     c_in of the next).
+// A batch of independent pairs is one flat array cut into segments of n limbs: a
+// segment start kills propagation into its first limb and masks its carry-in, so
+// the same kernel serves batched pairs, one huge pair and the normalise step of
+// multiplication.
+//
+// Tile layout: a workgroup of WAVES waves owns WAVES*ROWS*128 consecutive limbs;
+// wave w owns ROWS consecutive 128-limb rows; in a row, lane l holds limbs
+// 2l and 2l+1 (one 16-byte load per operand), so every load instruction of a wave
+// reads one contiguous 1 KiB block.
+#include "bn_internal.h"
+
+namespace {
+
+constexpr u64 ST_A = 1;   // tile aggregate ready, tile propagates its carry-in (carry-out unknown)
+constexpr u64 ST_I0 = 2;  // tile carry-out known: 0
+constexpr u64 ST_I1 = 3;  // tile carry-out known: 1
+
+__device__ __forceinline__ u64 ld_relaxed(const u64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_relaxed(u64 *p, u64 v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Raw limb result and its generate / propagate flags (phases 1-2).
+//   add: s = x + y mod 2^64, generate = [s < x] (Lemma 1), propagate = [s == 2^64 - 1]
+//   sub: s = x - y mod 2^64, generate = [x < y],            propagate = [s == 0]
+// In both cases generate and propagate are never both set.
+template <bool SUB>
+__device__ __forceinline__ void limb_gp(u64 x, u64 y, u64 &s, bool &g, bool &p) {
+    if (SUB) {
+        s = x - y;
+        g = x < y;
+        p = (s == 0);
+    } else {
+        s = x + y;
+        g = s < x;
+        p = (s == ~0ull);
+    }
+}
+
+// Carry resolution of one 64-lane row from its generate mask G, propagate mask P
+// and the carry into lane 0.  Returns the carry-into-lane mask; cout receives the
+// carry out of lane 63.
+__device__ __forceinline__ u64 row_resolve(u64 G, u64 P, u64 cin, u64 &cout) {
+    const u64 X = (G << 1) | cin;
+    const u64 T = X + P;
+    const u64 C = T ^ P;
+    cout = (G >> 63) | ((P >> 63) & (C >> 63));
+    return C;
+}
+
+__device__ __forceinline__ void divmod_u64(u64 x, u64 n, int nshift, u64 &q, u64 &r) {
+    if (nshift >= 0) {
+        q = x >> nshift;
+        r = x & (n - 1);
+    } else if (((x | n) >> 32) == 0) {
+        const u32 qq = (u32)x / (u32)n;
+        q = qq;
+        r = (u32)x - qq * (u32)n;
+    } else {
+        q = x / n;
+        r = x - q * n;
+    }
+}
+
+// Wave-wide decoupled look-back: find the carry into tile t.  Lane l reads the
+// status of tile t-1-(window offset)-l; the nearest predecessor that is not an
+// all-propagate aggregate decides: a known carry-out ends the walk, an unpublished
+// tile means wait.  Tiles below index 0 count as "carry-out 0".
+__device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64 *err) {
+    const int lane = threadIdx.x & 63;
+    i64 base = (i64)t - 1;
+    u32 spins = 0;
+    while (true) {
+        const i64 idx = base - lane;
+        u64 st = (epoch << 2) | ST_I0;
+        if (idx >= 0) st = ld_relaxed(status + idx);
+        const u32 state = ((st >> 2) == epoch) ? (u32)(st & 3) : 0u;
+        const u64 notA = __ballot(state != ST_A);
+        if (notA == 0) {
+            base -= 64;
+            continue;
+        }
+        const int first = __ffsll((unsigned long long)notA) - 1;
+        const u32 sf = __shfl(state, first);
+        if (sf != 0) return sf & 1u;
+        if (++spins > spin_limit) {
+            if (lane == 0) __hip_atomic_fetch_or(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <bool SUB, int WAVES, int ROWS, bool VEC>
+__global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, const u64 *__restrict__ a,
+                                                          const u64 *__restrict__ b, u64 N, u64 n, int nshift,
+                                                          u64 step_mod, u64 step_div, u64 *__restrict__ carry,
+                                                          ScanCtl *__restrict__ ctl, u64 *__restrict__ status,
+                                                          u64 nwg, u32 spin_limit, u32 dbg) {
+    __shared__ u64 sh_tile, sh_epoch;
+    __shared__ u32 sh_g[WAVES], sh_p[WAVES], sh_cin[WAVES];
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        sh_tile = __hip_atomic_fetch_add(&ctl->ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh_epoch = ld_relaxed(&ctl->epoch);
+    }
+    __syncthreads();
+    const u64 t = sh_tile;
+    const u64 epoch = sh_epoch;
+    constexpr u64 TL = (u64)WAVES * ROWS * 128;
+    const u64 idx0 = t * TL + (u64)w * ROWS * 128 + 2 * (u64)lane;
+
+    // ---- phase 1: loads (all rows issued before any use) ----
+    u64 x0[ROWS], x1[ROWS], y0[ROWS], y1[ROWS];
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+        const u64 idx = idx0 + (u64)j * 128;
+        if (VEC && idx + 1 < N) {
+            const ulong2 va = *reinterpret_cast<const ulong2 *>(a + idx);
+            const ulong2 vb = *reinterpret_cast<const ulong2 *>(b + idx);
+            x0[j] = va.x;
+            x1[j] = va.y;
+            y0[j] = vb.x;
+            y1[j] = vb.y;
+        } else {
+            x0[j] = idx < N ? a[idx] : 0;
+            y0[j] = idx < N ? b[idx] : 0;
+            x1[j] = idx + 1 < N ? a[idx + 1] : 0;
+            y1[j] = idx + 1 < N ? b[idx + 1] : 0;
+        }
+    }
+
+    u64 pos0, q0;
+    divmod_u64(idx0, n, nshift, q0, pos0);
+
+    // ---- phase 2: classify, ballot, wave aggregate with carry-in 0 ----
+    u64 Gm[ROWS], Pm[ROWS];
+    u32 fl[ROWS];  // bit0 g0, bit1 p0, bit2 g1, bit3 p1 (raw flags of the lane's two limbs)
+    u32 wg = 0, wp = 1;
+    {
+        u64 pos = pos0;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const u64 idx = idx0 + (u64)j * 128;
+            const bool v0 = idx < N, v1 = idx + 1 < N;
+            u64 s0, s1;
+            bool g0, p0, g1, p1;
+            limb_gp<SUB>(x0[j], y0[j], s0, g0, p0);
+            limb_gp<SUB>(x1[j], y1[j], s1, g1, p1);
+            g0 &= v0;
+            p0 &= v0;
+            g1 &= v1;
+            p1 &= v1;
+            x0[j] = s0;
+            x1[j] = s1;
+            fl[j] = (u32)g0 | ((u32)p0 << 1) | ((u32)g1 << 2) | ((u32)p1 << 3);
+            const bool st0 = (pos == 0);
+            const bool st1 = (pos + 1 == n);
+            const bool pp0 = p0 && !st0;  // a segment start does not pass a carry in
+            const bool pp1 = p1 && !st1;
+            const bool G = g1 || (pp1 && g0);
+            const bool P = pp0 && pp1;
+            Gm[j] = __ballot(G);
+            Pm[j] = __ballot(P);
+            u64 co;
+            row_resolve(Gm[j], Pm[j], wg, co);
+            wg = (u32)co;
+            wp &= (Pm[j] == ~0ull) ? 1u : 0u;
+            pos += step_mod;
+            if (pos >= n) pos -= n;
+        }
+    }
+    if (lane == 0) {
+        sh_g[w] = wg;
+        sh_p[w] = wp;
+    }
+    __syncthreads();
+
+    // ---- phase 3: tile aggregate, publish, look-back, per-wave carry-in ----
+    if (w == 0) {
+        u32 gt = 0, pt = 1;
+#pragma unroll
+        for (int i = 0; i < WAVES; ++i) {
+            gt = sh_g[i] | (sh_p[i] & gt);
+            pt &= sh_p[i];
+        }
+        const bool poison = (dbg & 1u) && t == 0;
+        if (lane == 0 && !poison) st_relaxed(status + t, (epoch << 2) | (pt ? ST_A : (gt ? ST_I1 : ST_I0)));
+        const u64 first_pos = __shfl(pos0, 0);
+        u32 cin = 0;
+        if (t > 0 && first_pos != 0) cin = lookback(status, t, epoch, spin_limit, &ctl->err);
+        if (lane == 0) {
+            if (pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
+            u32 c = cin;
+#pragma unroll
+            for (int i = 0; i < WAVES; ++i) {
+                sh_cin[i] = c;
+                c = sh_g[i] | (sh_p[i] & c);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: apply carries, store sums and per-segment carry-outs ----
+    {
+        u64 c = sh_cin[w];
+        u64 pos = pos0, q = q0;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const u64 idx = idx0 + (u64)j * 128;
+            u64 co;
+            const u64 C = row_resolve(Gm[j], Pm[j], c, co);
+            c = co;
+            const bool cb = (C >> lane) & 1ull;
+            const bool g0 = fl[j] & 1u, p0 = fl[j] & 2u, g1 = fl[j] & 4u, p1 = fl[j] & 8u;
+            const bool st0 = (pos == 0);
+            const bool st1 = (pos + 1 == n);
+            const bool en1 = (n == 1) || (pos + 2 == n);
+            const bool ci0 = cb && !st0;
+            const bool co0 = g0 || (p0 && ci0);
+            const bool ci1 = co0 && !st1;
+            const bool co1 = g1 || (p1 && ci1);
+            const u64 r0 = SUB ? x0[j] - (u64)ci0 : x0[j] + (u64)ci0;
+            const u64 r1 = SUB ? x1[j] - (u64)ci1 : x1[j] + (u64)ci1;
+            if (VEC && idx + 1 < N) {
+                *reinterpret_cast<ulong2 *>(r + idx) = make_ulong2(r0, r1);
+            } else {
+                if (idx < N) r[idx] = r0;
+                if (idx + 1 < N) r[idx + 1] = r1;
+            }
+            if (carry) {
+                if (idx < N && st1) carry[q] = co0;                        // limb idx ends a segment
+                if (idx + 1 < N && en1) carry[q + (st1 ? 1 : 0)] = co1;
+            }
+            pos += step_mod;
+            q += step_div;
+            if (pos >= n) {
+                pos -= n;
+                q += 1;
+            }
+        }
+    }
+
+    // ---- epilogue: the last workgroup to finish resets the ticket and bumps the epoch ----
+    if (threadIdx.x == 0) {
+        const u64 prev = __hip_atomic_fetch_add(&ctl->done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nwg - 1) {
+            st_relaxed(&ctl->done, 0);
+            st_relaxed(&ctl->ticket, 0);
+            st_relaxed(&ctl->epoch, epoch + 1);
+        }
+    }
+}
+
+__global__ void k_fill_u64(u64 *p, u64 count, u64 value) {
+    for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < count; i += (u64)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+typedef void (*scan_fn)(u64 *, const u64 *, const u64 *, u64, u64, int, u64, u64, u64 *, ScanCtl *, u64 *, u64,
+                        u32, u32);
+
+template <bool SUB, bool VEC>
+scan_fn pick(int waves, int rows) {
+#define BN_SHAPE(W, R) \
+    if (waves == W && rows == R) return k_flat_scan<SUB, W, R, VEC>;
+    BN_SHAPE(1, 1)
+    BN_SHAPE(1, 4)
+    BN_SHAPE(4, 1)
+    BN_SHAPE(4, 2)
+    BN_SHAPE(4, 4)
+    BN_SHAPE(4, 8)
+    BN_SHAPE(4, 16)
+    BN_SHAPE(8, 4)
+    BN_SHAPE(8, 8)
+#undef BN_SHAPE
+    return nullptr;
+}
+
+}  // namespace
+
+bool flat_scan_shape_ok(int waves, int rows) { return pick<false, true>(waves, rows) != nullptr; }
+
+static void flat_scan_shape(const bn_ctx *ctx, u64 N, int &waves, int &rows) {
+    if ((i64)N <= ctx->tune.small_addsub_limit) {
+        waves = ctx->tune.small_addsub_waves;
+        rows = ctx->tune.small_addsub_rows;
+    } else {
+        waves = ctx->tune.addsub_waves;
+        rows = ctx->tune.addsub_rows;
+    }
+}
+
+size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 N) {
+    int waves, rows;
+    flat_scan_shape(ctx, N, waves, rows);
+    const u64 TL = (u64)waves * rows * 128;
+    return (size_t)((N + TL - 1) / TL) * sizeof(u64);
+}
+
+bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s) {
+    if (count == 0) return BN_OK;
+    u64 blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((u32)blocks), dim3(256), 0, s, p, count, value);
+    return bn_launch_status();
+}
+
+bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *carry,
+                           hipStream_t s) {
+    const u64 N = n * npairs;
+    if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
+    int waves, rows;
+    flat_scan_shape(ctx, N, waves, rows);
+    const u64 TL = (u64)waves * rows * 128;
+    const u64 ntiles = (N + TL - 1) / TL;
+    bn_status st = bn_ensure(ctx, ctx->status, ntiles * sizeof(u64), s);
+    if (st != BN_OK) return st;
+    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)b) & 15u) == 0;
+    scan_fn f = sub ? (vec ? pick<true, true>(waves, rows) : pick<true, false>(waves, rows))
+                    : (vec ? pick<false, true>(waves, rows) : pick<false, false>(waves, rows));
+    if (!f) return BN_EINVAL;
+    int nshift = -1;
+    if ((n & (n - 1)) == 0) nshift = __builtin_ctzll(n);
+    hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, N, n, nshift, (u64)(128 % n),
+                       (u64)(128 / n), carry, ctx->ctl, (u64 *)ctx->status.ptr, ntiles, ctx->tune.spin_limit,
+                       ctx->tune.debug_flags);
+    return bn_launch_status();
+}

@@ -1,0 +1,211 @@
+// k_ragged.hip -- ragged batches: host-side plans and persistent work-queue kernels.
+//
+// A ragged batch holds pairs of uneven limb counts.  The plan sorts the pairs by
+// work (largest first) once on the host and uploads the list; one persistent launch
+// (a few waves per compute unit) then pulls pairs one at a time from an atomic
+// counter, so a long pair never leaves the rest of the grid idle.  The counter
+// resets itself (the last wave to finish clears it), so the launch can be captured
+// in a HIP graph and replayed.
+#include "bn_mul_dev.h"
+
+#include <algorithm>
+
+namespace {
+
+__device__ __forceinline__ u32 next_item(u32 *counter) {
+    u32 it = 0;
+    if ((threadIdx.x & 63) == 0) it = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __shfl(it, 0);
+}
+
+__device__ __forceinline__ void retire_wave(u32 *counter, u32 nwaves) {
+    if ((threadIdx.x & 63) == 0) {
+        const u32 prev = __hip_atomic_fetch_add(counter + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nwaves - 1) {
+            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(counter + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+constexpr int RAGGED_LDS_U64 = SMALL_MFMA_LDS_U64;
+
+__global__ __launch_bounds__(256) void k_mul_ragged(const RItem *__restrict__ items, u32 nitems,
+                                                    u32 *__restrict__ counter, u32 nwaves, u64 *__restrict__ r,
+                                                    const u64 *__restrict__ a, const u64 *__restrict__ b) {
+    __shared__ u64 lds[4 * RAGGED_LDS_U64];
+    const int w = threadIdx.x >> 6;
+    while (true) {
+        const u32 it = next_item(counter);
+        if (it >= nitems) break;
+        const RItem m = items[it];
+        const u64 *pa = a + m.a_off;
+        const u64 *pb = b + m.b_off;
+        u64 *pr = r + m.r_off;
+        const u32 P = m.na + m.nb;
+        if (m.form == BN_MUL_MFMA)
+            mul_item_mfma_small(pa, m.na, pb, m.nb, pr, lds + w * RAGGED_LDS_U64);
+        else if (P <= 64)
+            mul_item_mad<1>(pa, m.na, pb, m.nb, pr);
+        else if (P <= 128)
+            mul_item_mad<2>(pa, m.na, pb, m.nb, pr);
+        else
+            mul_item_mad<4>(pa, m.na, pb, m.nb, pr);
+        wave_sync();
+    }
+    retire_wave(counter, nwaves);
+}
+
+// Ragged add/sub: one wave per pair, walking the pair in rows of 128 limbs (lane l
+// holds limbs 2l, 2l+1 of a row); the carry crosses rows through the wave-uniform
+// carry-out of the row's ballot scan.
+template <bool SUB>
+__global__ __launch_bounds__(256) void k_add_ragged(const RItem *__restrict__ items, u32 nitems,
+                                                    u32 *__restrict__ counter, u32 nwaves, u64 *__restrict__ r,
+                                                    const u64 *__restrict__ a, const u64 *__restrict__ b,
+                                                    u64 *__restrict__ carry) {
+    const int lane = threadIdx.x & 63;
+    while (true) {
+        const u32 it = next_item(counter);
+        if (it >= nitems) break;
+        const RItem m = items[it];
+        const u64 n = m.na;
+        const u64 *pa = a + m.a_off, *pb = b + m.b_off;
+        u64 *pr = r + m.r_off;
+        u64 c = 0;
+        for (u64 base = 0; base < n; base += 128) {
+            const u64 i0 = base + 2 * (u64)lane, i1 = i0 + 1;
+            const bool v0 = i0 < n, v1 = i1 < n;
+            const u64 x0 = v0 ? pa[i0] : 0, y0 = v0 ? pb[i0] : 0;
+            const u64 x1 = v1 ? pa[i1] : 0, y1 = v1 ? pb[i1] : 0;
+            const u64 s0 = SUB ? x0 - y0 : x0 + y0;
+            const u64 s1 = SUB ? x1 - y1 : x1 + y1;
+            const bool g0 = v0 && (SUB ? x0 < y0 : s0 < x0);
+            const bool g1 = v1 && (SUB ? x1 < y1 : s1 < x1);
+            const bool p0 = v0 && (SUB ? s0 == 0 : s0 == ~0ull);
+            const bool p1 = v1 && (SUB ? s1 == 0 : s1 == ~0ull);
+            const u64 Gm = __ballot(g1 || (p1 && g0));
+            const u64 Pm = __ballot(p0 && p1);
+            const u64 X = (Gm << 1) | c;
+            const u64 T = X + Pm;
+            const u64 C = T ^ Pm;
+            const bool ci0 = (C >> lane) & 1ull;
+            const bool co0 = g0 || (p0 && ci0);
+            const bool co1 = g1 || (p1 && co0);
+            if (v0) pr[i0] = SUB ? s0 - (u64)ci0 : s0 + (u64)ci0;
+            if (v1) pr[i1] = SUB ? s1 - (u64)co0 : s1 + (u64)co0;
+            if (carry && v0 && i0 == n - 1) carry[m.index] = co0;
+            if (carry && v1 && i1 == n - 1) carry[m.index] = co1;
+            c = (Gm >> 63) | ((Pm >> 63) & (C >> 63));
+        }
+        if (carry && n == 0 && lane == 0) carry[m.index] = 0;
+    }
+    retire_wave(counter, nwaves);
+}
+
+u32 persistent_blocks(const bn_ctx *ctx, u32 nitems) {
+    const u32 want = (u32)std::max(1, ctx->num_cu) * 4;  // 4 workgroups (16 waves) per CU
+    const u32 need = (nitems + 3) / 4;
+    return std::max<u32>(1, std::min(want, need));
+}
+
+bn_status upload_plan(bn_ctx *ctx, bn_plan *pl, std::vector<RItem> &small) {
+    pl->nsmall = (u32)small.size();
+    if (hipSetDevice(ctx->device) != hipSuccess) return BN_EHIP;
+    if (!small.empty()) {
+        if (hipMalloc(&pl->d_items, small.size() * sizeof(RItem)) != hipSuccess) return BN_ENOMEM;
+        if (hipMemcpy(pl->d_items, small.data(), small.size() * sizeof(RItem), hipMemcpyHostToDevice) != hipSuccess)
+            return BN_EHIP;
+    }
+    if (hipMalloc(&pl->d_counter, 2 * sizeof(u32)) != hipSuccess) return BN_ENOMEM;
+    if (hipMemset(pl->d_counter, 0, 2 * sizeof(u32)) != hipSuccess) return BN_EHIP;
+    if (hipDeviceSynchronize() != hipSuccess) return BN_EHIP;
+    return BN_OK;
+}
+
+}  // namespace
+
+bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int form, bn_plan **out) {
+    if (npairs > 0xffffffffull) return BN_ERANGE;
+    bn_plan *pl = new bn_plan();
+    pl->op = 0;
+    pl->device = ctx->device;
+    pl->npairs = npairs;
+    std::vector<RItem> small;
+    small.reserve(npairs);
+    for (size_t i = 0; i < npairs; ++i) {
+        const bn_pair &p = pairs[i];
+        if (p.na == 0 || p.nb == 0 || p.na > (1u << 20) || p.nb > (1u << 20)) {
+            delete pl;
+            return BN_ERANGE;
+        }
+        RItem it{p.a_off, p.b_off, p.r_off, p.na, p.nb, 0, (u32)i};
+        it.form = (u32)mul_pick_form(ctx, p.na, p.nb, form);
+        (it.form == BN_MUL_MFMA ? pl->nmfma : pl->nmad)++;
+        pl->work += (u64)p.na * p.nb;
+        if ((u64)p.na + p.nb <= 256)
+            small.push_back(it);
+        else
+            pl->large.push_back(it);
+    }
+    std::stable_sort(small.begin(), small.end(),
+                     [](const RItem &x, const RItem &y) { return (u64)x.na * x.nb > (u64)y.na * y.nb; });
+    bn_status st = upload_plan(ctx, pl, small);
+    if (st != BN_OK) {
+        bn_plan_destroy(pl);
+        return st;
+    }
+    *out = pl;
+    return BN_OK;
+}
+
+bn_status plan_add_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, bn_plan **out) {
+    if (npairs > 0xffffffffull) return BN_ERANGE;
+    bn_plan *pl = new bn_plan();
+    pl->op = 1;
+    pl->device = ctx->device;
+    pl->npairs = npairs;
+    std::vector<RItem> items;
+    items.reserve(npairs);
+    for (size_t i = 0; i < npairs; ++i) {
+        const bn_pair &p = pairs[i];
+        if ((u64)p.na > BN_MAX_LIMBS) {
+            delete pl;
+            return BN_ERANGE;
+        }
+        items.push_back(RItem{p.a_off, p.b_off, p.r_off, p.na, p.na, 0, (u32)i});
+        pl->work += p.na;
+    }
+    std::stable_sort(items.begin(), items.end(), [](const RItem &x, const RItem &y) { return x.na > y.na; });
+    bn_status st = upload_plan(ctx, pl, items);
+    if (st != BN_OK) {
+        bn_plan_destroy(pl);
+        return st;
+    }
+    *out = pl;
+    return BN_OK;
+}
+
+bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, hipStream_t s) {
+    if (pl->nsmall) {
+        const u32 blocks = persistent_blocks(ctx, pl->nsmall);
+        hipLaunchKernelGGL(k_mul_ragged, dim3(blocks), dim3(256), 0, s, pl->d_items, pl->nsmall, pl->d_counter,
+                           blocks * 4, r, a, b);
+        bn_status st = bn_launch_status();
+        if (st != BN_OK) return st;
+    }
+    for (const RItem &it : pl->large) {
+        bn_status st = launch_mul_batch(ctx, r + it.r_off, a + it.a_off, b + it.b_off, it.na, it.nb, 1, (int)it.form, s);
+        if (st != BN_OK) return st;
+    }
+    return BN_OK;
+}
+
+bn_status launch_add_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, u64 *carry,
+                            hipStream_t s) {
+    if (!pl->nsmall) return BN_OK;
+    const u32 blocks = persistent_blocks(ctx, pl->nsmall);
+    hipLaunchKernelGGL(k_add_ragged<false>, dim3(blocks), dim3(256), 0, s, pl->d_items, pl->nsmall, pl->d_counter,
+                       blocks * 4, r, a, b, carry);
+    return bn_launch_status();
+}

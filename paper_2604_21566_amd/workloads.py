@@ -166,9 +166,10 @@ def c2(op: str = "add", npairs: int = 1 << 20, n: int = 64, seed: int = 0):
     if na and n >= 2:
         top = n - 1 if op == "add" else n - 2      # sub keeps the top limb free to order a >= b
         top = max(top, 1)
-        s = (limbs(g, na) % np.uint64(max(1, top))).astype(np.int64)          # s in [0, top-1]
+        lmin_all = min(16, top)                                                 # runs of >= 16 limbs when n allows
+        s = (limbs(g, na) % np.uint64(max(1, top - lmin_all + 1))).astype(np.int64)  # s in [0, top-lmin]
         room = top - s                                                          # run may reach limb `top`
-        lmin = np.minimum(16, room)
+        lmin = np.minimum(lmin_all, room)
         lrange = np.maximum(room - lmin + 1, 1).astype(np.uint64)
         ln = lmin + (limbs(g, na) % lrange).astype(np.int64)
         idx = np.arange(n)[None, :]

@@ -1,0 +1,203 @@
+"""GPU add/sub parity against the CPU oracle, bit-exact, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_21566_amd as bn
+from conftest import announce
+from paper_2604_21566_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+D = bn.to_device
+H = bn.to_host
+
+
+def _run_batch(ctx, op, a, b, n, npairs, offset=0):
+    """Run the GPU batch op; `offset` shifts the operands by that many limbs inside
+    larger buffers (8-byte aligned but not 16-byte aligned when odd)."""
+    N = n * npairs
+    ta = D(np.concatenate([np.zeros(offset, np.uint64), a]))[offset:]
+    tb = D(np.concatenate([np.zeros(offset, np.uint64), b]))[offset:]
+    tr = torch.empty(N + offset, dtype=torch.int64, device="cuda")[offset:]
+    tc = torch.full((max(npairs, 1),), -1, dtype=torch.int64, device="cuda")
+    f = bn.bn_add_n_batch if op == "add" else bn.bn_sub_n_batch
+    f(ctx, tr, ta, tb, n, npairs, tc)
+    torch.cuda.synchronize()
+    return H(tr), H(tc)[:npairs]
+
+
+def _check(ctx, op, a, b, n, npairs, offset=0):
+    announce(op, f"n={n}", f"npairs={npairs}", f"offset={offset}")
+    r, c = _run_batch(ctx, op, a, b, n, npairs, offset)
+    ref = oracle.add_batch if op == "add" else oracle.sub_batch
+    rr, rc = ref(a, b, n)
+    assert (r == rr).all(), f"{op} n={n} npairs={npairs}: first bad limb {np.argmax(r != rr)}"
+    assert (c == rc).all(), f"{op} n={n} npairs={npairs}: first bad carry {np.argmax(c != rc)}"
+
+
+SHAPES = [(1, 1), (1, 1000), (2, 700), (3, 333), (4, 1088), (5, 211), (7, 100), (63, 77), (64, 130),
+          (65, 65), (127, 9), (128, 40), (129, 33), (1000, 17), (4095, 3), (4096, 5), (4097, 4),
+          (100000, 2), (262145, 1)]
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("n,npairs", SHAPES)
+def test_batch_random(bnctx, op, n, npairs):
+    g = np.random.default_rng(n * 7 + npairs)
+    a = g.integers(0, 2 ** 64 - 1, n * npairs, dtype=np.uint64, endpoint=True)
+    b = g.integers(0, 2 ** 64 - 1, n * npairs, dtype=np.uint64, endpoint=True)
+    _check(bnctx, op, a, b, n, npairs)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("n", [1, 2, 4, 9, 64, 200, 5000])
+def test_pathological(bnctx, op, n):
+    pa, pb = wl.pathological(n, 4, seed=n)
+    _check(bnctx, op, pa.reshape(-1), pb.reshape(-1), n, pa.shape[0])
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("n,npairs", [(4, 1088), (64, 300), (129, 50), (5000, 3)])
+def test_unaligned_operands(bnctx, op, n, npairs):
+    g = np.random.default_rng(n)
+    pa, pb = wl.pathological(n, 2, seed=3)
+    a = np.concatenate([pa.reshape(-1), g.integers(0, 2 ** 63, n * (npairs - pa.shape[0]), dtype=np.uint64)])
+    b = np.concatenate([pb.reshape(-1), g.integers(0, 2 ** 63, n * (npairs - pb.shape[0]), dtype=np.uint64)])
+    _check(bnctx, op, a, b, n, npairs, offset=1)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+def test_c1(bnctx, op):
+    a, b = wl.c1(op)
+    _check(bnctx, op, a, b, 4, 1088)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+def test_c2_reduced(bnctx, op):
+    a, b = wl.c2(op, npairs=1 << 14)
+    _check(bnctx, op, a, b, 64, 1 << 14)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+def test_c2_full(bnctx, op):
+    a, b = wl.c2(op)
+    _check(bnctx, op, a, b, 64, 1 << 20)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("worst", [False, True])
+def test_c3_full(bnctx, op, worst):
+    a, b = wl.c3(op, worst=worst)
+    _check(bnctx, op, a, b, a.size, 1)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("waves,rows", [(1, 1), (1, 4), (4, 1), (4, 2), (4, 4), (4, 8), (4, 16), (8, 4), (8, 8)])
+def test_every_tile_shape(bnctx, op, waves, rows):
+    old = (bn.bn_get_param(bnctx, "addsub.waves"), bn.bn_get_param(bnctx, "addsub.rows"),
+           bn.bn_get_param(bnctx, "addsub.small_limit"))
+    try:
+        bn.bn_set_param(bnctx, "addsub.small_limit", 0)
+        bn.bn_set_param(bnctx, "addsub.waves", waves)
+        bn.bn_set_param(bnctx, "addsub.rows", rows)
+        a, b = wl.c3(op, n=300007)
+        _check(bnctx, op, a, b, a.size, 1)
+        pa, pb = wl.pathological(333, 3, seed=5)
+        _check(bnctx, op, pa.reshape(-1), pb.reshape(-1), 333, pa.shape[0])
+        aw, bw = wl.c3(op, n=70001, worst=True)
+        _check(bnctx, op, aw, bw, aw.size, 1)
+    finally:
+        bn.bn_set_param(bnctx, "addsub.waves", old[0])
+        bn.bn_set_param(bnctx, "addsub.rows", old[1])
+        bn.bn_set_param(bnctx, "addsub.small_limit", old[2])
+
+
+def test_in_place_and_single_pair_api(bnctx):
+    announce("in-place add/sub")
+    g = np.random.default_rng(2)
+    a = g.integers(0, 2 ** 64 - 1, 10007, dtype=np.uint64, endpoint=True)
+    b = g.integers(0, 2 ** 64 - 1, 10007, dtype=np.uint64, endpoint=True)
+    ta, tb = D(a), D(b)
+    c = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bn.bn_add(bnctx, ta, ta, tb, c)          # r == a
+    r, cc = oracle.add(a, b)
+    assert (H(ta) == r).all() and int(H(c)[0]) == cc
+    bn.bn_sub(bnctx, tb, ta, tb, c)          # r == b: (a + b) - b
+    d, br = oracle.sub(r, b)
+    assert (H(tb) == d).all() and int(H(c)[0]) == br
+
+
+def test_empty_and_errors(bnctx):
+    announce("empty sizes and argument errors")
+    z = torch.empty(0, dtype=torch.int64, device="cuda")
+    c = torch.full((3,), 7, dtype=torch.int64, device="cuda")
+    bn.bn_add_n_batch(bnctx, z, z, z, 0, 3, c)      # n = 0: carries are 0
+    torch.cuda.synchronize()
+    assert (H(c) == 0).all()
+    bn.bn_add_n_batch(bnctx, z, z, z, 5, 0, None)   # no pairs
+    t = torch.zeros(16, dtype=torch.int64, device="cuda")
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_add_n_batch(bnctx, t[1:9], t[0:8], t[8:16], 8, 1)   # partial overlap r/a
+    assert e.value.status == bn.BN_EALIAS
+    L = bn.lib()
+    assert L.bn_add(bnctx, t.data_ptr() + 4, t.data_ptr(), t.data_ptr(), 1, None, None) == bn.BN_EINVAL
+    assert L.bn_add(bnctx, None, t.data_ptr(), t.data_ptr(), 1, None, None) == bn.BN_EINVAL
+    assert L.bn_add_n_batch(bnctx, t.data_ptr(), t.data_ptr(), t.data_ptr(), 1 << 40, 1 << 40, None,
+                            None) == bn.BN_ERANGE
+    with pytest.raises(bn.BnError):
+        bn.bn_set_param(bnctx, "addsub.rows", 3)
+    with pytest.raises(bn.BnError):
+        bn.bn_set_param(bnctx, "mul.mfma_chunk", 4096)      # beyond the int32 accumulator bound
+
+
+def test_graph_replay_matches_eager(bnctx):
+    announce("graph capture + replay of a batched add")
+    n, npairs = 64, 5000
+    a, b = wl.c2("add", npairs=npairs)
+    ta, tb = D(a), D(b)
+    tr = torch.empty_like(ta)
+    tc = torch.empty(npairs, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    g = bn.bn_graph_capture_batch(bnctx, 0, tr, ta, tb, n, 0, npairs, tc, stream=s)
+    rr, rc = oracle.add_batch(a, b, n)
+    try:
+        for rep in range(4):
+            tr.zero_()
+            tc.zero_()
+            torch.cuda.synchronize()
+            bn.bn_graph_launch(g, s)
+            s.synchronize()
+            assert (H(tr) == rr).all() and (H(tc) == rc).all(), f"replay {rep}"
+            # eager work on the same context between replays
+            bn.bn_sub_n_batch(bnctx, tr, ta, tb, n, npairs, tc)
+            torch.cuda.synchronize()
+    finally:
+        bn.bn_graph_destroy(g)
+
+
+def test_watchdog_latch_forced_from_host(bnctx):
+    """A tile that never publishes (debug flag) makes its successor's look-back hit a tiny
+    spin limit: the kernel still exits and the latch reports it."""
+    announce("watchdog latch")
+    old = bn.bn_get_param(bnctx, "watchdog.spin_limit")
+    old_lim = bn.bn_get_param(bnctx, "addsub.small_limit")
+    try:
+        bn.bn_set_param(bnctx, "addsub.small_limit", 0)
+        bn.bn_set_param(bnctx, "watchdog.spin_limit", 64)
+        bn.bn_set_param(bnctx, "debug.flags", 1)
+        a, b = wl.c3("add", n=1 << 16, worst=True)
+        ta, tb = D(a), D(b)
+        tr = torch.empty_like(ta)
+        bn.bn_add(bnctx, tr, ta, tb)
+        st, flags = bn.bn_check(bnctx)
+        assert st == bn.BN_EWATCHDOG and flags & 1
+        st, flags = bn.bn_check(bnctx)   # the latch was cleared
+        assert st == bn.BN_OK and flags == 0
+    finally:
+        bn.bn_set_param(bnctx, "debug.flags", 0)
+        bn.bn_set_param(bnctx, "watchdog.spin_limit", old)
+        bn.bn_set_param(bnctx, "addsub.small_limit", old_lim)
+    # and the context still computes correctly afterwards
+    a, b = wl.c3("add", n=1 << 16)
+    _check(bnctx, "add", a, b, a.size, 1)

@@ -1,0 +1,232 @@
+"""GPU multiplication parity (mad and MFMA forms) against the CPU oracle, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_21566_amd as bn
+from _bigint import to_int
+from conftest import announce
+from paper_2604_21566_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+D = bn.to_device
+H = bn.to_host
+MAX = 2 ** 64 - 1
+
+
+def _rand(g, n):
+    return g.integers(0, MAX, n, dtype=np.uint64, endpoint=True)
+
+
+def _mul_batch(ctx, a, b, na, nb, npairs, form):
+    announce("mul", form, f"na={na}", f"nb={nb}", f"npairs={npairs}")
+    ta, tb = D(a), D(b)
+    tr = torch.full((npairs * (na + nb),), -1, dtype=torch.int64, device="cuda")
+    bn.bn_mul_n_batch(ctx, tr, ta, tb, na, nb, npairs, form)
+    torch.cuda.synchronize()
+    return H(tr)
+
+
+def _check(ctx, a, b, na, nb, npairs, form):
+    r = _mul_batch(ctx, a, b, na, nb, npairs, form)
+    rr = oracle.mul_batch(a, b, na, nb, npairs)
+    bad = np.nonzero(r != rr)[0]
+    assert bad.size == 0, f"{form} na={na} nb={nb}: {bad.size} bad limbs, first at {bad[0]}"
+
+
+SMALL = [(1, 1), (1, 2), (2, 1), (3, 5), (4, 4), (5, 5), (8, 8), (13, 29), (31, 33), (32, 32), (63, 1),
+         (64, 64), (100, 28), (37, 91), (127, 1), (1, 255), (255, 1), (128, 128), (120, 136)]
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+@pytest.mark.parametrize("na,nb", SMALL)
+def test_small_random(bnctx, form, na, nb):
+    g = np.random.default_rng(na * 1000 + nb)
+    npairs = 37
+    _check(bnctx, _rand(g, na * npairs), _rand(g, nb * npairs), na, nb, npairs, form)
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+@pytest.mark.parametrize("n", [1, 4, 16, 100, 128])
+def test_small_pathological(bnctx, form, n):
+    pa, pb = wl.pathological(n, 2, seed=n)
+    _check(bnctx, pa.reshape(-1), pb.reshape(-1), n, n, pa.shape[0], form)
+
+
+LARGE = [(129, 128), (300, 1), (1, 300), (257, 3), (3, 257), (500, 500), (1000, 999), (1024, 1024),
+         (4099, 1031), (1031, 4099), (4096, 4096)]
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+@pytest.mark.parametrize("na,nb", LARGE)
+def test_large_random(bnctx, form, na, nb):
+    g = np.random.default_rng(na * 7919 + nb)
+    npairs = 3
+    _check(bnctx, _rand(g, na * npairs), _rand(g, nb * npairs), na, nb, npairs, form)
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+@pytest.mark.parametrize("n", [300, 2048])
+def test_large_pathological(bnctx, form, n):
+    pa, pb = wl.pathological(n, 1, seed=n)
+    _check(bnctx, pa.reshape(-1), pb.reshape(-1), n, n, pa.shape[0], form)
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+def test_c1(bnctx, form):
+    a, b = wl.c1("mul")
+    _check(bnctx, a, b, 4, 4, 1088, form)
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+def test_c5_reduced(bnctx, form):
+    a, b = wl.c5(npairs=3, n=16384)
+    _check(bnctx, a, b, 16384, 16384, 3, form)
+
+
+def _residues_ok(a, b, r, n, npairs):
+    for p in range(npairs):
+        A = to_int(a[p * n:(p + 1) * n])
+        B = to_int(b[p * n:(p + 1) * n])
+        R = to_int(r[p * 2 * n:(p + 1) * 2 * n])
+        for q in (65537, 998244353, (1 << 61) - 1, (1 << 64) - 1):
+            if (A % q) * (B % q) % q != R % q:
+                return p
+    return -1
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+def test_c5_full(bnctx, form):
+    """64 pairs x 16384 limbs: sampled pairs against the oracle, every pair by residues."""
+    n, npairs = 16384, 64
+    a, b = wl.c5()
+    r = _mul_batch(bnctx, a, b, n, n, npairs, form)
+    for p in (0, 1, 2, 63):
+        rr = oracle.mul(a[p * n:(p + 1) * n], b[p * n:(p + 1) * n])
+        assert (r[p * 2 * n:(p + 1) * 2 * n] == rr).all(), f"pair {p}"
+    assert _residues_ok(a, b, r, n, npairs) == -1
+
+
+def _ragged_inputs(npairs, seed=0):
+    a, b, desc, rsz = wl.c4(npairs=npairs, seed=seed)
+    return a, b, desc, rsz
+
+
+@pytest.mark.parametrize("form", ["auto", "mad", "mfma"])
+def test_ragged_c4_reduced(bnctx, form):
+    a, b, desc, rsz = _ragged_inputs(3000, seed=1)
+    announce("ragged mul", form, "npairs=3000")
+    plan = bn.bn_plan_mul_ragged(bnctx, desc, form)
+    try:
+        ta, tb = D(a), D(b)
+        tr = torch.full((rsz,), -1, dtype=torch.int64, device="cuda")
+        bn.bn_mul_ragged(bnctx, plan, tr, ta, tb)
+        torch.cuda.synchronize()
+        rr = oracle.mul_ragged(a, b, desc, rsz)
+        assert (H(tr) == rr).all()
+    finally:
+        bn.bn_plan_destroy(plan)
+
+
+def test_ragged_unsorted_sparse_and_large_items(bnctx):
+    """Pairs in arbitrary pool positions, including ones beyond the one-wave limit."""
+    announce("ragged mul: mixed sizes")
+    g = np.random.default_rng(4)
+    sizes = [(1, 1), (300, 20), (4, 4), (128, 128), (1, 255), (700, 900), (33, 2), (2, 33), (256, 1)]
+    a_off = b_off = r_off = 0
+    desc, A, B = [], [], []
+    for na, nb in sizes:
+        gap = int(g.integers(0, 3))
+        a_off += gap
+        b_off += gap
+        r_off += gap
+        desc.append((a_off, b_off, r_off, na, nb))
+        a_off += na
+        b_off += nb
+        r_off += na + nb
+    a = _rand(g, a_off)
+    b = _rand(g, b_off)
+    desc = np.array(desc, np.uint64)
+    for form in ("mad", "mfma", "auto"):
+        plan = bn.bn_plan_mul_ragged(bnctx, desc, form)
+        try:
+            tr = torch.zeros(r_off, dtype=torch.int64, device="cuda")
+            bn.bn_mul_ragged(bnctx, plan, tr, D(a), D(b))
+            torch.cuda.synchronize()
+            rr = oracle.mul_ragged(a, b, desc, r_off)
+            assert (H(tr) == rr).all(), form
+        finally:
+            bn.bn_plan_destroy(plan)
+
+
+def test_ragged_c4_full_graph_replay(bnctx):
+    """2^16 ragged pairs in one persistent launch captured in a HIP graph, replayed with
+    eager work in between; every replay equals the oracle."""
+    a, b, desc, rsz = _ragged_inputs(1 << 16)
+    rr = oracle.mul_ragged(a, b, desc, rsz)
+    ta, tb = D(a), D(b)
+    tr = torch.zeros(rsz, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    for form in ("mad", "mfma"):
+        announce("ragged mul graph", form)
+        plan = bn.bn_plan_mul_ragged(bnctx, desc, form)
+        g = bn.bn_graph_capture_mul_ragged(bnctx, plan, tr, ta, tb, s)
+        try:
+            for rep in range(3):
+                tr.fill_(-1)
+                torch.cuda.synchronize()
+                bn.bn_graph_launch(g, s)
+                s.synchronize()
+                assert (H(tr) == rr).all(), f"{form} replay {rep}"
+                bn.bn_mul_ragged(bnctx, plan, tr, ta, tb)   # eager, same plan
+                torch.cuda.synchronize()
+                assert (H(tr) == rr).all(), f"{form} eager {rep}"
+        finally:
+            bn.bn_graph_destroy(g)
+            bn.bn_plan_destroy(plan)
+
+
+def test_ragged_add(bnctx):
+    announce("ragged add")
+    g = np.random.default_rng(8)
+    ns = [1, 5, 128, 129, 1000, 3, 64, 0, 77]
+    desc, off = [], 0
+    for n in ns:
+        desc.append((off, off, off, n, n))
+        off += n
+    a, b = _rand(g, off), _rand(g, off)
+    pa, pb = wl.pathological(129, 1, seed=2)
+    a[5 + 1:5 + 1 + 129] = pa[0]
+    b[5 + 1:5 + 1 + 129] = pb[0]
+    desc = np.array(desc, np.uint64)
+    plan = bn.bn_plan_add_ragged(bnctx, desc)
+    try:
+        tr = torch.zeros(off, dtype=torch.int64, device="cuda")
+        tc = torch.full((len(ns),), -1, dtype=torch.int64, device="cuda")
+        bn.bn_add_ragged(bnctx, plan, tr, D(a), D(b), tc)
+        torch.cuda.synchronize()
+        r, c = H(tr), H(tc)
+        o = 0
+        for i, n in enumerate(ns):
+            rr, cc = oracle.add(a[o:o + n], b[o:o + n])
+            assert (r[o:o + n] == rr).all() and int(c[i]) == cc, i
+            o += n
+    finally:
+        bn.bn_plan_destroy(plan)
+
+
+def test_mul_errors(bnctx):
+    announce("mul argument errors")
+    t = torch.zeros(64, dtype=torch.int64, device="cuda")
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_mul(bnctx, t[0:8], t[4:8], t[8:12])     # r overlaps a
+    assert e.value.status == bn.BN_EALIAS
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_mul(bnctx, t[16:24], t[0:4], t[8:12], form=7)
+    assert e.value.status == bn.BN_EINVAL
+    z = torch.empty(0, dtype=torch.int64, device="cuda")
+    r = torch.full((5,), 3, dtype=torch.int64, device="cuda")
+    bn.bn_mul(bnctx, r, z, t[0:5])                     # 0 limbs x 5 limbs = 0 (5 limbs)
+    torch.cuda.synchronize()
+    assert (H(r) == 0).all()
