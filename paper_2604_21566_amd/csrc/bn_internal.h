@@ -34,7 +34,7 @@ struct ScanCtl {
 
 // Tile-shape selector for the flat scan kernel.
 struct ScanShape {
-    int waves;  // waves per workgroup (1, 4 or 8)
+    int waves;  // waves per workgroup (1, 2, 4 or 8)
     int rows;   // 128-limb rows per wave (1, 2, 4, 8 or 16)
 };
 

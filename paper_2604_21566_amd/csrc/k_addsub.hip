@@ -283,15 +283,12 @@ template <bool SUB, bool VEC>
 scan_fn pick(int waves, int rows) {
 #define BN_SHAPE(W, R) \
     if (waves == W && rows == R) return k_flat_scan<SUB, W, R, VEC>;
-    BN_SHAPE(1, 1)
-    BN_SHAPE(1, 4)
-    BN_SHAPE(4, 1)
-    BN_SHAPE(4, 2)
-    BN_SHAPE(4, 4)
-    BN_SHAPE(4, 8)
-    BN_SHAPE(4, 16)
-    BN_SHAPE(8, 4)
-    BN_SHAPE(8, 8)
+#define BN_ROWS(W) BN_SHAPE(W, 1) BN_SHAPE(W, 2) BN_SHAPE(W, 4) BN_SHAPE(W, 8) BN_SHAPE(W, 16)
+    BN_ROWS(1)
+    BN_ROWS(2)
+    BN_ROWS(4)
+    BN_ROWS(8)
+#undef BN_ROWS
 #undef BN_SHAPE
     return nullptr;
 }
