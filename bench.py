@@ -142,14 +142,13 @@ def main():
     avg_launch = float(np.mean(launch_ms))
     achieved = bytes_per_launch / (avg_launch * 1e-3) / 1e9
     traffic = measured_traffic(bytes_per_launch)
-    st, flags = bn.bn_check(ctx)
-    if st != bn.BN_OK:
-        log(f"device error latch set: {flags}")
+    workloads_latch = bn.bn_check(ctx)
     log(f"c2: step {ms_per_step:.4f} ms, kernel {avg_launch:.4f} ms, {achieved:.1f} GB/s")
     workloads = {"c2_addsub": {"GBps_add": bytes_per_launch / (np.mean(launch_ms[0::2]) * 1e-3) / 1e9,
                                "GBps_sub": bytes_per_launch / (np.mean(launch_ms[1::2]) * 1e-3) / 1e9,
                                "kernel_ms_mean": avg_launch, "kernel_ms_min": float(np.min(launch_ms)),
-                               "ci95_ms": float(1.96 * np.std(launch_ms) / np.sqrt(len(launch_ms)))}}
+                               "ci95_ms": float(1.96 * np.std(launch_ms) / np.sqrt(len(launch_ms))),
+                               "lookback_self_help_latch": workloads_latch}}
 
     # ------------------------------------------------------------ CPU oracle baseline (same workload)
     cpu = None
@@ -297,8 +296,7 @@ def extra_workloads(ctx, bn, wl, torch):
             crossover = None
         n *= 2
     res["crossover"] = {"sweep": sweep, "mfma_faster_from_limbs": crossover}
-    st, flags = bn.bn_check(ctx)
-    res["device_error_latch"] = flags
+    res["lookback_self_help_latch"] = bn.bn_check(ctx)
     return res
 
 

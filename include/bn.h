@@ -26,8 +26,8 @@
  *
  * Errors: every entry point returns a bn_status.  Argument errors are detected
  * synchronously and nothing is enqueued.  HIP launch errors map to BN_EHIP.
- * Asynchronous device-side conditions (the look-back watchdog) are latched in
- * the context and read with bn_check().  No C++ exception crosses the ABI.
+ * Device-side events worth knowing about (see bn_check) are latched in the
+ * context.  No C++ exception crosses the ABI.
  */
 #ifndef BN_H_
 #define BN_H_
@@ -48,7 +48,6 @@ typedef int bn_status;
 #define BN_EHIP (-5)          /* a HIP runtime call or kernel launch failed */
 #define BN_EUNSUPPORTED (-6)  /* no gfx950 device, or a feature not built */
 #define BN_ECAPTURE (-7)      /* workspace would have to grow while the stream is being captured */
-#define BN_EWATCHDOG (-8)     /* returned by bn_check: a look-back wait hit its spin limit */
 
 typedef struct bn_ctx bn_ctx;
 typedef void *bn_stream; /* hipStream_t */
@@ -77,9 +76,11 @@ bn_status bn_reserve(bn_ctx *ctx, size_t bytes);
  * For add/sub pass n, npairs (na = n); for mul pass na, nb, npairs, form. */
 size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form);
 
-/* Synchronise `stream`, then read and clear the context's device-side error latch.
- * *flags (may be NULL) receives the raw latch (bit 0: look-back watchdog).
- * Returns BN_EWATCHDOG if the watchdog fired since the last check, else BN_OK. */
+/* Synchronise `stream`, then read and clear the context's device-side latch.
+ * *flags (may be NULL) receives it: bit 0 = since the last check, some add/sub tile
+ * waited longer than "lookback.spin_limit" polls for a predecessor and computed
+ * that predecessor's carry from the operands itself (results are exact either way).
+ * Returns BN_OK, or BN_EHIP if the stream reported an error. */
 bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags);
 
 /* ------------------------------------------------------- add / subtract ---- */
@@ -173,7 +174,10 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "addsub.rows", "addsub.waves"      tile shape of the add/sub scan
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
  *   "mul.mad_cols", "mfma.chunk"       product-kernel tile parameters
- *   "watchdog.spin_limit"              look-back wait bound (iterations)
+ *   "lookback.spin_limit"              look-back polls before a tile computes an
+ *                                      unpublished predecessor's carry itself
+ *   "debug.flags"                      bit 0: tile 0 never publishes its status
+ *                                      (test hook for the self-computed look-back)
  * Returns BN_EINVAL for an unknown key or an out-of-range value. */
 bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t value);
 bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *value);

@@ -28,7 +28,6 @@ BN_ENOMEM = -4
 BN_EHIP = -5
 BN_EUNSUPPORTED = -6
 BN_ECAPTURE = -7
-BN_EWATCHDOG = -8
 
 BN_MUL_AUTO = 0
 BN_MUL_MAD = 1
@@ -166,14 +165,12 @@ def bn_workspace_size(ctx, op: int, na: int, nb: int, npairs: int, form: int = B
     return lib().bn_workspace_size(ctx, op, na, nb, npairs, form)
 
 
-def bn_check(ctx, stream=None):
-    """Synchronise the stream, read and clear the device error latch.
-    Returns (status, flags): status is BN_OK or BN_EWATCHDOG."""
+def bn_check(ctx, stream=None) -> int:
+    """Synchronise the stream, read and clear the device latch; returns its flags
+    (bit 0: a look-back computed an unpublished predecessor's carry itself)."""
     flags = ctypes.c_uint32(0)
-    st = lib().bn_check(ctx, _stream(stream), ctypes.byref(flags))
-    if st not in (BN_OK, BN_EWATCHDOG):
-        _ck(st, "bn_check")
-    return st, flags.value
+    _ck(lib().bn_check(ctx, _stream(stream), ctypes.byref(flags)), "bn_check")
+    return flags.value
 
 
 def bn_set_param(ctx, key: str, value: int):

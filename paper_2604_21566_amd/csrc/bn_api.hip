@@ -81,7 +81,6 @@ const char *bn_strerror(bn_status s) {
         case BN_EHIP: return "HIP runtime error";
         case BN_EUNSUPPORTED: return "unsupported device or feature";
         case BN_ECAPTURE: return "workspace must grow during stream capture (call bn_reserve first)";
-        case BN_EWATCHDOG: return "look-back watchdog fired";
         default: return "unknown status";
     }
 }
@@ -146,7 +145,7 @@ bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags) {
     const u64 zero = 0;
     if (hipMemcpy(&ctx->ctl->err, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return BN_EHIP;
     if (flags) *flags = (uint32_t)err;
-    return (err & 1u) ? BN_EWATCHDOG : BN_OK;
+    return BN_OK;
 }
 
 // --------------------------------------------------------------- add / sub ----
@@ -320,7 +319,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 // ------------------------------------------------------------------ params ----
 static const char *kParamNames =
     "addsub.waves,addsub.rows,addsub.small_waves,addsub.small_rows,addsub.small_limit,"
-    "mul.crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,watchdog.spin_limit,debug.flags";
+    "mul.crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,lookback.spin_limit,debug.flags";
 
 const char *bn_param_names(void) { return kParamNames; }
 
@@ -352,7 +351,7 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
     } else if (k == "mul.mfma_chunk") {
         if (v < 16 || v > 4095) return BN_EINVAL;  // int32 accumulator bound: 4095 steps of 32 products <= 2^14
         t.mfma_chunk = (int)v;
-    } else if (k == "watchdog.spin_limit") {
+    } else if (k == "lookback.spin_limit") {
         if (v < 0 || v > 0xffffffffll) return BN_EINVAL;
         t.spin_limit = (u32)v;
     } else if (k == "debug.flags") {
@@ -376,7 +375,7 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "mul.crossover_limbs") *v = t.mul_crossover_limbs;
     else if (k == "mul.mad_xchunk") *v = t.mad_xchunk;
     else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;
-    else if (k == "watchdog.spin_limit") *v = t.spin_limit;
+    else if (k == "lookback.spin_limit") *v = t.spin_limit;
     else if (k == "debug.flags") *v = t.debug_flags;
     else return BN_EINVAL;
     return BN_OK;

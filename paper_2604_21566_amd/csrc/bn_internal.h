@@ -20,16 +20,14 @@ typedef int64_t i64;
     } while (0)
 
 // Device-side control block of the decoupled look-back (one per context).
-//   ticket : next tile id to hand out (forward-progress order, reset by the last WG)
-//   done   : WGs finished in the current launch (reset by the last WG)
-//   epoch  : tags status words; bumped by the last WG so stale words never match
-//   err    : sticky error latch (bit 0 = watchdog), cleared by bn_check
+//   epoch : tags status words; bumped by a one-thread kernel after every chained
+//           scan, so status words of earlier launches never match
+//   err   : sticky latch read and cleared by bn_check (bit 0: a look-back computed
+//           a predecessor tile's aggregate itself instead of waiting for it)
 struct ScanCtl {
-    u64 ticket;
-    u64 done;
     u64 epoch;
     u64 err;
-    u64 pad[4];
+    u64 pad[6];
 };
 
 // Tile-shape selector for the flat scan kernel.
@@ -39,8 +37,8 @@ struct ScanShape {
 };
 
 struct Tuning {
-    int addsub_waves = 4;
-    int addsub_rows = 8;
+    int addsub_waves = 1;
+    int addsub_rows = 1;
     int small_addsub_waves = 1;   // used when the whole batch is tiny
     int small_addsub_rows = 1;
     i64 small_addsub_limit = 1 << 16;  // N (total limbs) at or below which the small shape is used
@@ -48,8 +46,8 @@ struct Tuning {
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
     int mfma_chunk = 1024;             // d-steps per MFMA work item (<= overflow bound)
-    u32 spin_limit = 1u << 24;         // look-back wait bound
-    u32 debug_flags = 0;               // bit 0: first tile never publishes (watchdog test)
+    u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
+    u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
 };
 
 // Workspace buffer that grows on demand (never while the stream is being captured).

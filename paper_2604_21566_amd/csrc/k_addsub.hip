@@ -79,11 +79,53 @@ __device__ __forceinline__ void divmod_u64(u64 x, u64 n, int nshift, u64 &q, u64
     }
 }
 
-// Wave-wide decoupled look-back: find the carry into tile t.  Lane l reads the
-// status of tile t-1-(window offset)-l; the nearest predecessor that is not an
-// all-propagate aggregate decides: a known carry-out ends the walk, an unpublished
-// tile means wait.  Tiles below index 0 count as "carry-out 0".
-__device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64 *err) {
+struct ScanGeom {
+    u64 N;         // total limbs
+    u64 n;         // segment (pair) length
+    int nshift;    // log2(n) if n is a power of two, else -1
+    u64 TL;        // limbs per tile
+};
+
+// (generate, propagate) aggregate of tile u computed from the operands by one
+// wave, 128 limbs per step.  Used when the tile has not published its status yet
+// (self-help), so the waiting tile never depends on another workgroup making progress.
+template <bool SUB>
+__device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G,
+                                         u64 u, u32 &g_out, u32 &p_out) {
+    const int lane = threadIdx.x & 63;
+    const u64 lo = u * G.TL;
+    const u64 hi = (lo + G.TL < G.N) ? lo + G.TL : G.N;
+    u32 g = 0, p = 1;
+    for (u64 base = lo; base < hi; base += 128) {
+        const u64 i0 = base + 2 * (u64)lane;
+        u64 q, pos;
+        divmod_u64(i0, G.n, G.nshift, q, pos);
+        bool g0 = false, p0 = false, g1 = false, p1 = false;
+        u64 s;
+        if (i0 < hi) limb_gp<SUB>(a[i0], b[i0], s, g0, p0);
+        if (i0 + 1 < hi) limb_gp<SUB>(a[i0 + 1], b[i0 + 1], s, g1, p1);
+        p0 = p0 && pos != 0;
+        p1 = p1 && pos + 1 != G.n;
+        const u64 Gm = __ballot(g1 || (p1 && g0));
+        const u64 Pm = __ballot(p0 && p1);
+        u64 co;
+        row_resolve(Gm, Pm, g, co);
+        g = (u32)co;
+        p &= (Pm == ~0ull) ? 1u : 0u;
+    }
+    g_out = g;
+    p_out = p;
+}
+
+// Wave-wide decoupled look-back for the carry into tile t.  Lane l reads the
+// status of the l-th nearest predecessor in the current window; the nearest one
+// that is not an all-propagate aggregate decides: a known carry-out ends the walk;
+// an unpublished tile is waited for up to `spin_limit` polls, after which the wave
+// computes that tile's aggregate from the operands itself and walks on.  Tiles
+// below index 0 count as "carry-out 0".
+template <bool SUB>
+__device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64 *latch,
+                        const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G) {
     const int lane = threadIdx.x & 63;
     i64 base = (i64)t - 1;
     u32 spins = 0;
@@ -100,48 +142,62 @@ __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64
         const int first = __ffsll((unsigned long long)notA) - 1;
         const u32 sf = __shfl(state, first);
         if (sf != 0) return sf & 1u;
-        if (++spins > spin_limit) {
-            if (lane == 0) __hip_atomic_fetch_or(err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return 0;
+        if (++spins <= spin_limit) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
         }
-        __builtin_amdgcn_s_sleep(1);
+        // self-help: the tiles between `first` and t are all-propagate, so the carry
+        // into t is the carry out of tile u
+        const u64 u = (u64)(base - first);
+        u32 gu, pu;
+        tile_aggregate_from_data<SUB>(a, b, G, u, gu, pu);
+        if (lane == 0) __hip_atomic_fetch_or(latch, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!pu) return gu;
+        base = (i64)u - 1;
+        spins = 0;
     }
 }
 
 template <bool SUB, int WAVES, int ROWS, bool VEC>
 __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, const u64 *__restrict__ a,
-                                                          const u64 *__restrict__ b, u64 N, u64 n, int nshift,
-                                                          u64 step_mod, u64 step_div, u64 *__restrict__ carry,
+                                                          const u64 *__restrict__ b, ScanGeom G, u64 step_mod,
+                                                          u64 step_div, u64 *__restrict__ carry,
                                                           ScanCtl *__restrict__ ctl, u64 *__restrict__ status,
-                                                          u64 nwg, u32 spin_limit, u32 dbg) {
-    __shared__ u64 sh_tile, sh_epoch;
+                                                          u32 spin_limit, u32 dbg, int chain) {
     __shared__ u32 sh_g[WAVES], sh_p[WAVES], sh_cin[WAVES];
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) {
-        sh_tile = __hip_atomic_fetch_add(&ctl->ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sh_epoch = ld_relaxed(&ctl->epoch);
-    }
-    __syncthreads();
-    const u64 t = sh_tile;
-    const u64 epoch = sh_epoch;
+    // Tile t is workgroup t.  chain == 0: every tile starts a segment (the tile
+    // length is a multiple of the segment length), so no tile needs its
+    // predecessor's carry and the look-back machinery is skipped.  chain == 1:
+    // tiles publish status words tagged with the launch epoch (a plain load: the
+    // epoch only changes between launches) and look back.
+    const u64 t = blockIdx.x;
+    const u64 epoch = chain ? ctl->epoch : 0;
     constexpr u64 TL = (u64)WAVES * ROWS * 128;
+    const u64 N = G.N, n = G.n;
     const u64 idx0 = t * TL + (u64)w * ROWS * 128 + 2 * (u64)lane;
 
     // ---- phase 1: loads (all rows issued before any use) ----
+    // A full tile (the common case) loads without per-row guards so that every
+    // load of the wave is in flight at once; only the last tile checks bounds.
+    const bool full = VEC && (t + 1) * TL <= N;
     u64 x0[ROWS], x1[ROWS], y0[ROWS], y1[ROWS];
+    if (full) {
 #pragma unroll
-    for (int j = 0; j < ROWS; ++j) {
-        const u64 idx = idx0 + (u64)j * 128;
-        if (VEC && idx + 1 < N) {
-            const ulong2 va = *reinterpret_cast<const ulong2 *>(a + idx);
-            const ulong2 vb = *reinterpret_cast<const ulong2 *>(b + idx);
+        for (int j = 0; j < ROWS; ++j) {
+            const ulong2 va = *reinterpret_cast<const ulong2 *>(a + idx0 + (u64)j * 128);
+            const ulong2 vb = *reinterpret_cast<const ulong2 *>(b + idx0 + (u64)j * 128);
             x0[j] = va.x;
             x1[j] = va.y;
             y0[j] = vb.x;
             y1[j] = vb.y;
-        } else {
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const u64 idx = idx0 + (u64)j * 128;
             x0[j] = idx < N ? a[idx] : 0;
             y0[j] = idx < N ? b[idx] : 0;
             x1[j] = idx + 1 < N ? a[idx + 1] : 0;
@@ -150,7 +206,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     }
 
     u64 pos0, q0;
-    divmod_u64(idx0, n, nshift, q0, pos0);
+    divmod_u64(idx0, n, G.nshift, q0, pos0);
 
     // ---- phase 2: classify, ballot, wave aggregate with carry-in 0 ----
     u64 Gm[ROWS], Pm[ROWS];
@@ -177,10 +233,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
             const bool st1 = (pos + 1 == n);
             const bool pp0 = p0 && !st0;  // a segment start does not pass a carry in
             const bool pp1 = p1 && !st1;
-            const bool G = g1 || (pp1 && g0);
-            const bool P = pp0 && pp1;
-            Gm[j] = __ballot(G);
-            Pm[j] = __ballot(P);
+            const bool Gl = g1 || (pp1 && g0);
+            const bool Pl = pp0 && pp1;
+            Gm[j] = __ballot(Gl);
+            Pm[j] = __ballot(Pl);
             u64 co;
             row_resolve(Gm[j], Pm[j], wg, co);
             wg = (u32)co;
@@ -197,19 +253,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
 
     // ---- phase 3: tile aggregate, publish, look-back, per-wave carry-in ----
     if (w == 0) {
-        u32 gt = 0, pt = 1;
-#pragma unroll
-        for (int i = 0; i < WAVES; ++i) {
-            gt = sh_g[i] | (sh_p[i] & gt);
-            pt &= sh_p[i];
-        }
-        const bool poison = (dbg & 1u) && t == 0;
-        if (lane == 0 && !poison) st_relaxed(status + t, (epoch << 2) | (pt ? ST_A : (gt ? ST_I1 : ST_I0)));
-        const u64 first_pos = __shfl(pos0, 0);
         u32 cin = 0;
-        if (t > 0 && first_pos != 0) cin = lookback(status, t, epoch, spin_limit, &ctl->err);
+        if (chain) {
+            u32 gt = 0, pt = 1;
+#pragma unroll
+            for (int i = 0; i < WAVES; ++i) {
+                gt = sh_g[i] | (sh_p[i] & gt);
+                pt &= sh_p[i];
+            }
+            const bool poison = (dbg & 1u) && t == 0;
+            if (lane == 0 && !poison) st_relaxed(status + t, (epoch << 2) | (pt ? ST_A : (gt ? ST_I1 : ST_I0)));
+            const u64 first_pos = __shfl(pos0, 0);
+            if (t > 0 && first_pos != 0) cin = lookback<SUB>(status, t, epoch, spin_limit, &ctl->err, a, b, G);
+            if (lane == 0 && pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
+        }
         if (lane == 0) {
-            if (pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
             u32 c = cin;
 #pragma unroll
             for (int i = 0; i < WAVES; ++i) {
@@ -241,7 +299,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
             const bool co1 = g1 || (p1 && ci1);
             const u64 r0 = SUB ? x0[j] - (u64)ci0 : x0[j] + (u64)ci0;
             const u64 r1 = SUB ? x1[j] - (u64)ci1 : x1[j] + (u64)ci1;
-            if (VEC && idx + 1 < N) {
+            if (full) {
                 *reinterpret_cast<ulong2 *>(r + idx) = make_ulong2(r0, r1);
             } else {
                 if (idx < N) r[idx] = r0;
@@ -259,25 +317,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
             }
         }
     }
-
-    // ---- epilogue: the last workgroup to finish resets the ticket and bumps the epoch ----
-    if (threadIdx.x == 0) {
-        const u64 prev = __hip_atomic_fetch_add(&ctl->done, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nwg - 1) {
-            st_relaxed(&ctl->done, 0);
-            st_relaxed(&ctl->ticket, 0);
-            st_relaxed(&ctl->epoch, epoch + 1);
-        }
-    }
 }
+
+// After a chained launch: move to a fresh epoch so that the next launch never
+// mistakes this launch's status words for its own.  Stream order puts it after
+// every workgroup of the scan.
+__global__ void k_bump_epoch(ScanCtl *ctl) { ctl->epoch += 1; }
 
 __global__ void k_fill_u64(u64 *p, u64 count, u64 value) {
     for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < count; i += (u64)gridDim.x * blockDim.x)
         p[i] = value;
 }
 
-typedef void (*scan_fn)(u64 *, const u64 *, const u64 *, u64, u64, int, u64, u64, u64 *, ScanCtl *, u64 *, u64,
-                        u32, u32);
+typedef void (*scan_fn)(u64 *, const u64 *, const u64 *, ScanGeom, u64, u64, u64 *, ScanCtl *, u64 *, u32, u32,
+                        int);
 
 template <bool SUB, bool VEC>
 scan_fn pick(int waves, int rows) {
@@ -330,16 +383,22 @@ bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
     flat_scan_shape(ctx, N, waves, rows);
     const u64 TL = (u64)waves * rows * 128;
     const u64 ntiles = (N + TL - 1) / TL;
-    bn_status st = bn_ensure(ctx, ctx->status, ntiles * sizeof(u64), s);
-    if (st != BN_OK) return st;
+    const int chain = (TL % n) != 0;
+    if (chain) {
+        bn_status st = bn_ensure(ctx, ctx->status, ntiles * sizeof(u64), s);
+        if (st != BN_OK) return st;
+    }
+    if (ntiles > 0x7fffffffull) return BN_ERANGE;
     const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)b) & 15u) == 0;
     scan_fn f = sub ? (vec ? pick<true, true>(waves, rows) : pick<true, false>(waves, rows))
                     : (vec ? pick<false, true>(waves, rows) : pick<false, false>(waves, rows));
     if (!f) return BN_EINVAL;
-    int nshift = -1;
-    if ((n & (n - 1)) == 0) nshift = __builtin_ctzll(n);
-    hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, N, n, nshift, (u64)(128 % n),
-                       (u64)(128 / n), carry, ctx->ctl, (u64 *)ctx->status.ptr, ntiles, ctx->tune.spin_limit,
-                       ctx->tune.debug_flags);
+    ScanGeom G{N, n, -1, TL};
+    if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
+    hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
+                       ctx->ctl, (u64 *)ctx->status.ptr, ctx->tune.spin_limit, ctx->tune.debug_flags, chain);
+    bn_status st = bn_launch_status();
+    if (st != BN_OK || !chain) return st;
+    hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, ctx->ctl);
     return bn_launch_status();
 }

@@ -20,7 +20,7 @@ __device__ __forceinline__ u32 next_item(u32 *counter) {
 
 __device__ __forceinline__ void retire_wave(u32 *counter, u32 nwaves) {
     if ((threadIdx.x & 63) == 0) {
-        const u32 prev = __hip_atomic_fetch_add(counter + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const u32 prev = __hip_atomic_fetch_add(counter + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == nwaves - 1) {
             __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(counter + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

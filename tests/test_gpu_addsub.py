@@ -176,28 +176,40 @@ def test_graph_replay_matches_eager(bnctx):
         bn.bn_graph_destroy(g)
 
 
-def test_watchdog_latch_forced_from_host(bnctx):
-    """A tile that never publishes (debug flag) makes its successor's look-back hit a tiny
-    spin limit: the kernel still exits and the latch reports it."""
-    announce("watchdog latch")
-    old = bn.bn_get_param(bnctx, "watchdog.spin_limit")
+def test_self_help_lookback_forced_from_host(bnctx):
+    """Tile 0 never publishes (debug flag): its successor polls a few times, then
+    computes tile 0's carry from the operands itself.  The kernel exits normally,
+    the result is exact, and the latch reports that the self-help path ran."""
+    announce("self-help look-back")
+    old = bn.bn_get_param(bnctx, "lookback.spin_limit")
     old_lim = bn.bn_get_param(bnctx, "addsub.small_limit")
     try:
         bn.bn_set_param(bnctx, "addsub.small_limit", 0)
-        bn.bn_set_param(bnctx, "watchdog.spin_limit", 64)
+        bn.bn_set_param(bnctx, "lookback.spin_limit", 16)
         bn.bn_set_param(bnctx, "debug.flags", 1)
-        a, b = wl.c3("add", n=1 << 16, worst=True)
-        ta, tb = D(a), D(b)
-        tr = torch.empty_like(ta)
-        bn.bn_add(bnctx, tr, ta, tb)
-        st, flags = bn.bn_check(bnctx)
-        assert st == bn.BN_EWATCHDOG and flags & 1
-        st, flags = bn.bn_check(bnctx)   # the latch was cleared
-        assert st == bn.BN_OK and flags == 0
+        bn.bn_check(bnctx)
+        for op, worst in (("add", True), ("sub", True), ("add", False)):
+            a, b = wl.c3(op, n=1 << 16, worst=worst)
+            _check(bnctx, op, a, b, a.size, 1)
+            assert bn.bn_check(bnctx) & 1
+        assert bn.bn_check(bnctx) == 0   # the latch was cleared
     finally:
         bn.bn_set_param(bnctx, "debug.flags", 0)
-        bn.bn_set_param(bnctx, "watchdog.spin_limit", old)
+        bn.bn_set_param(bnctx, "lookback.spin_limit", old)
         bn.bn_set_param(bnctx, "addsub.small_limit", old_lim)
-    # and the context still computes correctly afterwards
     a, b = wl.c3("add", n=1 << 16)
     _check(bnctx, "add", a, b, a.size, 1)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+def test_self_help_every_tile(bnctx, op):
+    """spin_limit 0: every waiting tile computes its predecessors itself."""
+    announce("self-help on every wait", op)
+    old = bn.bn_get_param(bnctx, "lookback.spin_limit")
+    try:
+        bn.bn_set_param(bnctx, "lookback.spin_limit", 0)
+        for worst in (False, True):
+            a, b = wl.c3(op, n=(1 << 18) + 77, worst=worst)
+            _check(bnctx, op, a, b, a.size, 1)
+    finally:
+        bn.bn_set_param(bnctx, "lookback.spin_limit", old)
