@@ -171,9 +171,14 @@ bn_status bn_graph_destroy(bn_graph *graph);
 /* ------------------------------------------------------------ tuning ---- */
 
 /* Named integer parameters of the context (see bn_param_names()):
- *   "addsub.rows", "addsub.waves"      tile shape of the add/sub scan
+ *   "addsub.batch_waves", "addsub.batch_rows"   add/sub tile shape when the tile length
+ *                                      is a multiple of the pair length (independent tiles)
+ *   "addsub.chain_waves", "addsub.chain_rows"   tile shape otherwise (look-back between tiles)
+ *                                      waves in {1,2,4,8}, rows of 128 limbs in {1,2,4,8,16}
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
- *   "mul.mad_cols", "mfma.chunk"       product-kernel tile parameters
+ *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
+ *   "mul.mfma_chunk"                   Toeplitz steps per large MFMA work item (<= 4095,
+ *                                      the int32 accumulator bound)
  *   "lookback.spin_limit"              look-back polls before a tile computes an
  *                                      unpublished predecessor's carry itself
  *   "debug.flags"                      bit 0: tile 0 never publishes its status

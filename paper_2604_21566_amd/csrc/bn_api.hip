@@ -271,7 +271,7 @@ bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t
     size_t need = 0, status = 0;
     for (const RItem &it : plan->large) {
         need = std::max(need, mul_workspace_bytes(ctx, it.na, it.nb, 1, (int)it.form));
-        status = std::max(status, flat_scan_status_bytes(ctx, (u64)it.na + it.nb));
+        status = std::max(status, flat_scan_status_bytes(ctx, (u64)it.na + it.nb, (u64)it.na + it.nb));
     }
     bn_status st;
     if ((st = bn_ensure(ctx, ctx->work, need, nullptr)) != BN_OK) return st;
@@ -289,13 +289,13 @@ bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_
         if ((st = mul_args(ctx, r, a, b, na, nb, npairs, form)) != BN_OK) return st;
         if ((st = bn_ensure(ctx, ctx->work, mul_workspace_bytes(ctx, na, nb, npairs, form), nullptr)) != BN_OK)
             return st;
-        if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)(na + nb) * npairs), nullptr)) !=
+        if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)(na + nb), (u64)(na + nb) * npairs), nullptr)) !=
             BN_OK)
             return st;
         return capture(stream, graph,
                        [&]() { return bn_mul_n_batch(ctx, r, a, b, na, nb, npairs, form, stream); });
     }
-    if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)na * npairs), nullptr)) != BN_OK)
+    if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)na, (u64)na * npairs), nullptr)) != BN_OK)
         return st;
     return capture(stream, graph, [&]() {
         return op == 0 ? bn_add_n_batch(ctx, r, a, b, na, npairs, carry_out, stream)
@@ -318,7 +318,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 
 // ------------------------------------------------------------------ params ----
 static const char *kParamNames =
-    "addsub.waves,addsub.rows,addsub.small_waves,addsub.small_rows,addsub.small_limit,"
+    "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,"
     "mul.crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,lookback.spin_limit,debug.flags";
 
 const char *bn_param_names(void) { return kParamNames; }
@@ -327,21 +327,18 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
     if (!ctx || !key) return BN_EINVAL;
     Tuning &t = ctx->tune;
     const std::string k(key);
-    if (k == "addsub.waves" || k == "addsub.rows") {
-        const int w = k == "addsub.waves" ? (int)v : t.addsub_waves;
-        const int r = k == "addsub.rows" ? (int)v : t.addsub_rows;
+    if (k == "addsub.batch_waves" || k == "addsub.batch_rows") {
+        const int w = k == "addsub.batch_waves" ? (int)v : t.batch_waves;
+        const int r = k == "addsub.batch_rows" ? (int)v : t.batch_rows;
         if (!flat_scan_shape_ok(w, r)) return BN_EINVAL;
-        t.addsub_waves = w;
-        t.addsub_rows = r;
-    } else if (k == "addsub.small_waves" || k == "addsub.small_rows") {
-        const int w = k == "addsub.small_waves" ? (int)v : t.small_addsub_waves;
-        const int r = k == "addsub.small_rows" ? (int)v : t.small_addsub_rows;
+        t.batch_waves = w;
+        t.batch_rows = r;
+    } else if (k == "addsub.chain_waves" || k == "addsub.chain_rows") {
+        const int w = k == "addsub.chain_waves" ? (int)v : t.chain_waves;
+        const int r = k == "addsub.chain_rows" ? (int)v : t.chain_rows;
         if (!flat_scan_shape_ok(w, r)) return BN_EINVAL;
-        t.small_addsub_waves = w;
-        t.small_addsub_rows = r;
-    } else if (k == "addsub.small_limit") {
-        if (v < 0) return BN_EINVAL;
-        t.small_addsub_limit = v;
+        t.chain_waves = w;
+        t.chain_rows = r;
     } else if (k == "mul.crossover_limbs") {
         if (v < 1) return BN_EINVAL;
         t.mul_crossover_limbs = v;
@@ -367,11 +364,10 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     if (!ctx || !key || !v) return BN_EINVAL;
     const Tuning &t = ctx->tune;
     const std::string k(key);
-    if (k == "addsub.waves") *v = t.addsub_waves;
-    else if (k == "addsub.rows") *v = t.addsub_rows;
-    else if (k == "addsub.small_waves") *v = t.small_addsub_waves;
-    else if (k == "addsub.small_rows") *v = t.small_addsub_rows;
-    else if (k == "addsub.small_limit") *v = t.small_addsub_limit;
+    if (k == "addsub.batch_waves") *v = t.batch_waves;
+    else if (k == "addsub.batch_rows") *v = t.batch_rows;
+    else if (k == "addsub.chain_waves") *v = t.chain_waves;
+    else if (k == "addsub.chain_rows") *v = t.chain_rows;
     else if (k == "mul.crossover_limbs") *v = t.mul_crossover_limbs;
     else if (k == "mul.mad_xchunk") *v = t.mad_xchunk;
     else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;

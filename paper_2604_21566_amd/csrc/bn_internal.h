@@ -37,11 +37,12 @@ struct ScanShape {
 };
 
 struct Tuning {
-    int addsub_waves = 1;
-    int addsub_rows = 1;
-    int small_addsub_waves = 1;   // used when the whole batch is tiny
-    int small_addsub_rows = 1;
-    i64 small_addsub_limit = 1 << 16;  // N (total limbs) at or below which the small shape is used
+    // add/sub tile shapes: "batch" is used when the tile length is a multiple of the
+    // pair length (tiles never depend on each other), "chain" otherwise (look-back)
+    int batch_waves = 1;
+    int batch_rows = 1;
+    int chain_waves = 4;
+    int chain_rows = 8;
     i64 mul_crossover_limbs = 256;     // BN_MUL_AUTO: MFMA when min(na, nb) >= this
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
@@ -98,7 +99,7 @@ bn_status bn_launch_status();
 // Flat segmented add/sub over N = n * npairs limbs; a segment (pair) starts every n limbs.
 bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                            u64 *carry, hipStream_t s);
-size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 N);
+size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N);
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s);
 
 // ---- mul (k_mul_*.hip) ----

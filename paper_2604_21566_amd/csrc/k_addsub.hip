@@ -350,19 +350,22 @@ scan_fn pick(int waves, int rows) {
 
 bool flat_scan_shape_ok(int waves, int rows) { return pick<false, true>(waves, rows) != nullptr; }
 
-static void flat_scan_shape(const bn_ctx *ctx, u64 N, int &waves, int &rows) {
-    if ((i64)N <= ctx->tune.small_addsub_limit) {
-        waves = ctx->tune.small_addsub_waves;
-        rows = ctx->tune.small_addsub_rows;
+// Shape for a launch over segments of n limbs: the independent-tile shape when its
+// tile length is a multiple of n, else the chained (look-back) shape.
+static void flat_scan_shape(const bn_ctx *ctx, u64 n, int &waves, int &rows) {
+    const u64 tl = (u64)ctx->tune.batch_waves * ctx->tune.batch_rows * 128;
+    if (n && tl % n == 0) {
+        waves = ctx->tune.batch_waves;
+        rows = ctx->tune.batch_rows;
     } else {
-        waves = ctx->tune.addsub_waves;
-        rows = ctx->tune.addsub_rows;
+        waves = ctx->tune.chain_waves;
+        rows = ctx->tune.chain_rows;
     }
 }
 
-size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 N) {
+size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N) {
     int waves, rows;
-    flat_scan_shape(ctx, N, waves, rows);
+    flat_scan_shape(ctx, n, waves, rows);
     const u64 TL = (u64)waves * rows * 128;
     return (size_t)((N + TL - 1) / TL) * sizeof(u64);
 }
@@ -380,7 +383,7 @@ bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
     const u64 N = n * npairs;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
     int waves, rows;
-    flat_scan_shape(ctx, N, waves, rows);
+    flat_scan_shape(ctx, n, waves, rows);
     const u64 TL = (u64)waves * rows * 128;
     const u64 ntiles = (N + TL - 1) / TL;
     const int chain = (TL % n) != 0;

@@ -75,22 +75,37 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
     Tuning &t = ctx->tune;
     std::string log;
 
-    // 1) add/sub tile shape on a large batch (64-limb pairs)
-    const int shapes[][2] = {{4, 2}, {4, 4}, {4, 8}, {4, 16}, {8, 4}, {8, 8}};
-    float best = 1e30f;
-    int bw = t.addsub_waves, br = t.addsub_rows;
-    for (auto &sh : shapes) {
-        t.addsub_waves = sh[0];
-        t.addsub_rows = sh[1];
-        const float ms = time_ms([&] { launch_flat_scan(ctx, false, r, a, b, 64, NBIG / 64, nullptr, nullptr); });
-        if (ms < best) {
-            best = ms;
-            bw = sh[0];
-            br = sh[1];
+    // 1) add/sub tile shapes: independent tiles (64-limb pairs) and chained tiles
+    //    (one operand pair spanning the whole array)
+    const int shapes[][2] = {{1, 1}, {1, 2}, {2, 1}, {4, 1}, {8, 1}, {8, 2}, {2, 8}, {4, 4}, {4, 8}, {8, 4}};
+    for (int mode = 0; mode < 2; ++mode) {
+        float best = 1e30f;
+        int bw = 1, br = 1;
+        for (auto &sh : shapes) {
+            if (mode == 0) {
+                t.batch_waves = sh[0];
+                t.batch_rows = sh[1];
+            } else {
+                t.chain_waves = sh[0];
+                t.chain_rows = sh[1];
+            }
+            const u64 n = mode == 0 ? 64 : NBIG;
+            const float ms =
+                time_ms([&] { launch_flat_scan(ctx, false, r, a, b, n, NBIG / n, nullptr, nullptr); });
+            if (ms < best) {
+                best = ms;
+                bw = sh[0];
+                br = sh[1];
+            }
+        }
+        if (mode == 0) {
+            t.batch_waves = bw;
+            t.batch_rows = br;
+        } else {
+            t.chain_waves = bw;
+            t.chain_rows = br;
         }
     }
-    t.addsub_waves = bw;
-    t.addsub_rows = br;
 
     // 2) mad vs MFMA crossover: square products, equal total work per size
     i64 crossover = -1;
@@ -122,7 +137,8 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         FILE *f = fopen(out_json, "w");
         if (!f) return BN_EINVAL;
         fprintf(f, "{\n%s", log.c_str());
-        fprintf(f, "    \"addsub.waves\": %d,\n    \"addsub.rows\": %d,\n", t.addsub_waves, t.addsub_rows);
+        fprintf(f, "    \"addsub.batch_waves\": %d,\n    \"addsub.batch_rows\": %d,\n", t.batch_waves, t.batch_rows);
+        fprintf(f, "    \"addsub.chain_waves\": %d,\n    \"addsub.chain_rows\": %d,\n", t.chain_waves, t.chain_rows);
         fprintf(f, "    \"mul.crossover_limbs\": %lld,\n", (long long)t.mul_crossover_limbs);
         fprintf(f, "    \"mul.mad_xchunk\": %d,\n    \"mul.mfma_chunk\": %d\n}\n", t.mad_xchunk, t.mfma_chunk);
         fclose(f);

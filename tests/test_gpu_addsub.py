@@ -95,22 +95,22 @@ def test_c3_full(bnctx, op, worst):
 @pytest.mark.parametrize("op", ["add", "sub"])
 @pytest.mark.parametrize("waves,rows", [(w, r) for w in (1, 2, 4, 8) for r in (1, 2, 4, 8, 16)])
 def test_every_tile_shape(bnctx, op, waves, rows):
-    old = (bn.bn_get_param(bnctx, "addsub.waves"), bn.bn_get_param(bnctx, "addsub.rows"),
-           bn.bn_get_param(bnctx, "addsub.small_limit"))
+    keys = ("addsub.batch_waves", "addsub.batch_rows", "addsub.chain_waves", "addsub.chain_rows")
+    old = {k: bn.bn_get_param(bnctx, k) for k in keys}
     try:
-        bn.bn_set_param(bnctx, "addsub.small_limit", 0)
-        bn.bn_set_param(bnctx, "addsub.waves", waves)
-        bn.bn_set_param(bnctx, "addsub.rows", rows)
+        for k, v in zip(keys, (waves, rows, waves, rows)):
+            bn.bn_set_param(bnctx, k, v)
         a, b = wl.c3(op, n=300007)
         _check(bnctx, op, a, b, a.size, 1)
         pa, pb = wl.pathological(333, 3, seed=5)
         _check(bnctx, op, pa.reshape(-1), pb.reshape(-1), 333, pa.shape[0])
+        pa, pb = wl.pathological(64, 3, seed=6)
+        _check(bnctx, op, pa.reshape(-1), pb.reshape(-1), 64, pa.shape[0])
         aw, bw = wl.c3(op, n=70001, worst=True)
         _check(bnctx, op, aw, bw, aw.size, 1)
     finally:
-        bn.bn_set_param(bnctx, "addsub.waves", old[0])
-        bn.bn_set_param(bnctx, "addsub.rows", old[1])
-        bn.bn_set_param(bnctx, "addsub.small_limit", old[2])
+        for k, v in old.items():
+            bn.bn_set_param(bnctx, k, v)
 
 
 def test_in_place_and_single_pair_api(bnctx):
@@ -146,7 +146,7 @@ def test_empty_and_errors(bnctx):
     assert L.bn_add_n_batch(bnctx, t.data_ptr(), t.data_ptr(), t.data_ptr(), 1 << 40, 1 << 40, None,
                             None) == bn.BN_ERANGE
     with pytest.raises(bn.BnError):
-        bn.bn_set_param(bnctx, "addsub.rows", 3)
+        bn.bn_set_param(bnctx, "addsub.chain_rows", 3)
     with pytest.raises(bn.BnError):
         bn.bn_set_param(bnctx, "mul.mfma_chunk", 4096)      # beyond the int32 accumulator bound
 
@@ -182,9 +182,7 @@ def test_self_help_lookback_forced_from_host(bnctx):
     the result is exact, and the latch reports that the self-help path ran."""
     announce("self-help look-back")
     old = bn.bn_get_param(bnctx, "lookback.spin_limit")
-    old_lim = bn.bn_get_param(bnctx, "addsub.small_limit")
     try:
-        bn.bn_set_param(bnctx, "addsub.small_limit", 0)
         bn.bn_set_param(bnctx, "lookback.spin_limit", 16)
         bn.bn_set_param(bnctx, "debug.flags", 1)
         bn.bn_check(bnctx)
@@ -196,7 +194,6 @@ def test_self_help_lookback_forced_from_host(bnctx):
     finally:
         bn.bn_set_param(bnctx, "debug.flags", 0)
         bn.bn_set_param(bnctx, "lookback.spin_limit", old)
-        bn.bn_set_param(bnctx, "addsub.small_limit", old_lim)
     a, b = wl.c3("add", n=1 << 16)
     _check(bnctx, "add", a, b, a.size, 1)
 
