@@ -141,8 +141,10 @@ bn_status bn_plan_mul_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npai
                              bn_plan **plan);
 bn_status bn_plan_destroy(bn_plan *plan);
 
-/* Run a planned ragged multiply: one persistent kernel pulls pairs from an atomic
- * work counter until the list is exhausted.  No allocation, no host sync. */
+/* Run a planned ragged multiply: one persistent launch per form (mad, MFMA); wave k
+ * of W resident waves takes pairs k, k+W, ... of the work-sorted list.  Pairs with
+ * na + nb > 256 run through the batched path, one call each.  No allocation
+ * (beyond the batched path's workspace, reserved by graph capture), no host sync. */
 bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
                         const uint64_t *b_pool, bn_stream stream);
 
@@ -177,8 +179,9 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *                                      waves in {1,2,4,8}, rows of 128 limbs in {1,2,4,8,16}
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
- *   "mul.mfma_chunk"                   Toeplitz steps per large MFMA work item (<= 4095,
- *                                      the int32 accumulator bound)
+ *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large
+ *                                      MFMA kernel (<= 2047: 64 digit products of at most
+ *                                      2^14 per step keep an int32 round sum exact)
  *   "lookback.spin_limit"              look-back polls before a tile computes an
  *                                      unpublished predecessor's carry itself
  *   "debug.flags"                      bit 0: tile 0 never publishes its status

@@ -237,7 +237,6 @@ bn_status bn_plan_destroy(bn_plan *plan) {
     DeviceGuard g(plan->device);
     (void)hipDeviceSynchronize();
     if (plan->d_items) (void)hipFree(plan->d_items);
-    if (plan->d_counter) (void)hipFree(plan->d_counter);
     delete plan;
     return BN_OK;
 }
@@ -346,7 +345,7 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
         if (v < 64 || v > (1 << 20) || (v % 8)) return BN_EINVAL;
         t.mad_xchunk = (int)v;
     } else if (k == "mul.mfma_chunk") {
-        if (v < 16 || v > 4095) return BN_EINVAL;  // int32 accumulator bound: 4095 steps of 32 products <= 2^14
+        if (v < 16 || v > 2047) return BN_EINVAL;  // int32 bound: 2047 steps of 64 digit products <= 2^14
         t.mfma_chunk = (int)v;
     } else if (k == "lookback.spin_limit") {
         if (v < 0 || v > 0xffffffffll) return BN_EINVAL;

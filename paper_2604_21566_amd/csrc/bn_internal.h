@@ -46,7 +46,7 @@ struct Tuning {
     i64 mul_crossover_limbs = 256;     // BN_MUL_AUTO: MFMA when min(na, nb) >= this
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
-    int mfma_chunk = 1024;             // d-steps per MFMA work item (<= overflow bound)
+    int mfma_chunk = 128;              // Toeplitz steps staged in LDS per round (<= 2047, int32 bound)
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
 };
@@ -78,9 +78,9 @@ struct bn_plan {
     int op = 0;                    // 0 = mul ragged, 1 = add ragged
     int device = 0;
     size_t npairs = 0;
-    u32 nsmall = 0;                // items run by the persistent kernel (sorted by work, largest first)
-    RItem *d_items = nullptr;      // device copy of the small items
-    u32 *d_counter = nullptr;      // {next item, finished waves}; reset by the last wave
+    u32 nsmall = 0;                // items run by the persistent kernels
+    u32 nsmall_mad = 0;            // of which mad form (they come first in d_items)
+    RItem *d_items = nullptr;      // device copy of the small items, each form sorted by work
     std::vector<RItem> large;      // mul items too big for one wave: one batched launch each
     u32 nmad = 0, nmfma = 0;       // items per form
     u64 work = 0;                  // sum of na * nb (mul) or n (add)

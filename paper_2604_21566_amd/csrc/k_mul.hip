@@ -113,10 +113,8 @@ __global__ void k_fold_mad(const u64 *__restrict__ colLo, const u64 *__restrict_
 }
 
 // ---------------------------------------------------------- large: MFMA form ----
-constexpr int AR_PAD = 128;  // zero limbs on each side of the reversed digit array (32 chunks)
-
-// Per pair: digit prefix tables of a and b, and the reversed signed digits of a with
-// zero padding.  One workgroup per pair.
+// Per pair: per-limb digit-sum prefix tables of a and b (for the unsigned-sum
+// corrections of the fold).  One workgroup per pair.
 __device__ void block_prefix_digits(const u64 *__restrict__ limbs, u64 n, u32 *__restrict__ lp, u32 *sh) {
     const u32 tid = threadIdx.x, nt = blockDim.x;
     const u64 per = (n + nt - 1) / nt;
@@ -145,129 +143,221 @@ __device__ void block_prefix_digits(const u64 *__restrict__ limbs, u64 n, u32 *_
 }
 
 __global__ __launch_bounds__(256) void k_mfma_prep(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                   u64 nb, u32 *__restrict__ lpa, u32 *__restrict__ lpb,
-                                                   u64 *__restrict__ aR) {
+                                                   u64 nb, u32 *__restrict__ lpa, u32 *__restrict__ lpb) {
     __shared__ u32 sh[256];
     const u64 p = blockIdx.x;
-    const u64 *pa = a + p * na, *pb = b + p * nb;
-    block_prefix_digits(pa, na, lpa + p * (na + 1), sh);
-    block_prefix_digits(pb, nb, lpb + p * (nb + 1), sh);
-    const u64 nca = (na + 3) / 4;
-    const u64 len = 4 * nca + 2 * AR_PAD;
-    u64 *dst = aR + p * len;
-    for (u64 k = threadIdx.x; k < len; k += blockDim.x) {
-        u64 v = 0;
-        if (k >= (u64)AR_PAD && k < AR_PAD + 4 * nca) {
-            const u64 m = 4 * nca - 1 - (k - AR_PAD);
-            if (m < na) v = __builtin_bswap64(pa[m] ^ XOR80);
-        }
-        dst[k] = v;
-    }
+    block_prefix_digits(a + p * na, na, lpa + p * (na + 1), sh);
+    block_prefix_digits(b + p * nb, nb, lpb + p * (nb + 1), sh);
 }
 
-// Work item (one workgroup of 4 waves): W-blocks [4 NW g, 4 NW (g+1)) (each 32 output
-// groups of 32 digit columns) x Toeplitz steps d in [k D, (k+1) D).  The b digits of
-// the step range are staged once in LDS and shared by all waves; each wave builds
-// the Toeplitz fragment once per step and uses it for its NW blocks.
-template <int NW>
-__global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ b, const u64 *__restrict__ aR, u64 na,
-                                                        u64 nb, u64 nchunks, u32 D, u64 *__restrict__ col) {
-    extern __shared__ u64 bz[];
+// k-th group in decreasing-work order when work over groups [0, n) is symmetric and
+// unimodal about the centre (true for the columns of a product): centre first, then
+// alternately outwards.
+__device__ __forceinline__ u32 middle_out(u32 k, u32 n) {
+    if (n & 1) {
+        const u32 c = (n - 1) / 2;
+        if (k == 0) return c;
+        return (k & 1) ? c - (k + 1) / 2 : c + k / 2;
+    }
+    const u32 m = n / 2 - 1;
+    return (k & 1) ? m + (k + 1) / 2 : m - k / 2;
+}
+
+// Exact unsigned column sum from the MFMA sum `raw` of signed digits.  When the
+// accumulation was plain int32 (wide == false) the register holds the true sum M
+// modulo 2^32; M lies in [-16256 cnt, 16384 cnt], an interval narrower than 2^32
+// for cnt <= 131586, so M is recovered exactly.
+__device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u64 nda, u64 ndb, const u64 *__restrict__ a,
+                                            const u32 *__restrict__ lpa, const u64 *__restrict__ b,
+                                            const u32 *__restrict__ lpb) {
+    const u64 ilo = t + 1 > ndb ? t + 1 - ndb : 0;
+    const u64 ihi = t < nda - 1 ? t : nda - 1;
+    if (ilo > ihi) return 0;
+    const i64 cnt = (i64)(ihi - ilo + 1);
+    i64 m = raw;
+    if (!wide) {
+        m = (i64)(int)(u32)raw;
+        if (m < -16256 * cnt) m += (i64)1 << 32;
+    }
+    const i64 sa = digit_prefix(a, lpa, ihi + 1) - digit_prefix(a, lpa, ilo);
+    const i64 sb = digit_prefix(b, lpb, t - ilo + 1) - digit_prefix(b, lpb, t - ihi);
+    return m + 128 * (sa + sb) - 16384 * cnt;
+}
+
+constexpr int AZ_SLOT_U64 = 10;  // one 64-digit chunk per 80-byte LDS slot: ds_read_b128 without bank conflicts
+
+// Large products on the MFMA form.  Output digit columns are grouped 64 at a time
+// (t = 64 W + r, r < 64), the Toeplitz step consumes 64 digits of b:
+//     C[64 W + r] = sum_d sum_k T_d[r][k] A_d[k][W],
+//     T_d[r][k] = b'[64 (d-1) + r + 1 + k],   A_d[k][W] = a'[64 (W-d) + 63 - k].
+// A W-block (32 W = 256 output limbs, 64 rows = two 32-row M-blocks) takes four
+// 32x32x32 MFMAs per step; the three distinct Toeplitz fragments (rows + K-slice
+// offsets 0, 32, 64) are shared by the wave's NW blocks and the third becomes the
+// first of the next step.  A workgroup (4 waves, 4 NW blocks) covers the whole
+// contraction range of its blocks, staging D steps of b digits and the matching
+// window of a chunks (byte-reversed) in LDS per round, so there is no split of the
+// contraction, no atomics and no workspace zeroing.  Accumulation is int32; when
+// a column can hold more than 131586 digit products (wide) each round is widened
+// into int64 registers, otherwise the epilogue decodes the int32 sum exactly.  The
+// epilogue folds the 64 columns of each W into 8 limb values and writes lo and
+// shifted hi for the final carry pass.  Workgroups are ordered by decreasing work.
+template <int NW, bool WIDE>
+__global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
+                                                        u64 nb, u64 npairs, const u32 *__restrict__ lpa,
+                                                        const u32 *__restrict__ lpb, u32 D, u32 ngroups,
+                                                        u64 *__restrict__ LO, u64 *__restrict__ HS) {
+    extern __shared__ u64 lds[];
+    u64 *bz = lds;                     // 8 (D + 3) words of signed b digits
+    u64 *az = lds + 8 * ((u64)D + 3);  // (128 NW + D) chunk slots of reversed signed a digits
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const u32 x = lane & 31, h = lane >> 5;
-    const u64 pair = blockIdx.y;
-    const u64 g = blockIdx.x / nchunks, kc = blockIdx.x % nchunks;
-    const i64 nca = (i64)((na + 3) / 4);
-    const i64 ndb = 8 * (i64)nb;
-    const i64 dmax = (ndb + 30) / 32;
-    const i64 d0 = (i64)kc * D;
-    const i64 d1 = std::min<i64>(d0 + D, dmax + 1);
+    const u64 pair = blockIdx.x % npairs;
+    const u32 g = middle_out((u32)(blockIdx.x / npairs), ngroups);
     const i64 P = (i64)(na + nb);
-    const i64 nWb = (8 * P + 1023) / 1024;  // W-blocks holding output columns
-    const i64 wbFirst = (i64)g * 4 * NW;
-    const i64 wbLast = std::min<i64>(wbFirst + 4 * NW, nWb) - 1;
-    // union of useful steps over the group's blocks: d in [32 Wb - nca + 1, 32 Wb + 31]
-    const i64 ulo = std::max<i64>(d0, 32 * wbFirst - nca + 1);
-    const i64 uhi = std::min<i64>(d1 - 1, 32 * wbLast + 31);
-    if (ulo > uhi) return;
+    const i64 nca = (i64)((na + 7) / 8);
+    const i64 dmax = (8 * (i64)nb + 62) / 64;
+    const i64 nWb = (P + 255) / 256;
+    const i64 wb0 = (i64)g * 4 * NW;
+    const i64 W0g = 32 * wb0, Wend = W0g + 128 * NW - 1;
+    const u64 *pa = a + pair * na, *pb = b + pair * nb;
 
-    const u64 *pb = b + pair * nb;
-    const u32 nst = 4 * (D + 3);
-    for (u32 k = threadIdx.x; k < nst; k += blockDim.x) {
-        const i64 m = 4 * (d0 - 1) + (i64)k;
-        bz[k] = (m >= 0 && m < (i64)nb) ? (pb[m] ^ XOR80) : 0ull;
-    }
-    __syncthreads();
-
-    const u64 *ar = aR + pair * (4 * (u64)nca + 2 * AR_PAD) + AR_PAD;
-    const u32 *bz32 = reinterpret_cast<const u32 *>(bz);
-    v16i acc[NW];
     i64 blo[NW], bhi[NW];
     i64 wlo = INT64_MAX, whi = INT64_MIN;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-        acc[i] = v16i{0};
-        const i64 wb = wbFirst + (i64)wave * NW + i;
-        blo[i] = std::max<i64>(d0, 32 * wb - nca + 1);
-        bhi[i] = (wb < nWb) ? std::min<i64>(d1 - 1, 32 * wb + 31) : INT64_MIN;
+        const i64 wb = wb0 + (i64)wave * NW + i;
+        blo[i] = 1;
+        bhi[i] = 0;
+        if (wb < nWb) {
+            blo[i] = std::max<i64>(0, 32 * wb - nca + 1);
+            bhi[i] = std::min<i64>(dmax, 32 * wb + 31);
+        }
         if (blo[i] <= bhi[i]) {
             wlo = std::min(wlo, blo[i]);
             whi = std::max(whi, bhi[i]);
         }
     }
-    for (i64 d = wlo; d <= whi; ++d) {
-        const v4i T = toeplitz_frag(bz32, (u32)(32 * (d - d0)) + x + 1 + 16 * h);
-#pragma unroll
-        for (int i = 0; i < NW; ++i) {
-            if (d >= blo[i] && d <= bhi[i]) {
-                const i64 wb = wbFirst + (i64)wave * NW + i;
-                const i64 c = 32 * wb + (i64)x - d;  // in [-31, nca + 30]
-                const v4i A = *reinterpret_cast<const v4i *>(ar + 4 * nca - 4 * (c + 1) + 2 * h);
-                acc[i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(T, A, acc[i], 0, 0, 0);
-            }
-        }
-    }
-    u64 *pc = col + pair * 8 * (u64)P;
+    const i64 lastb = std::min<i64>(wb0 + 4 * NW, nWb) - 1;
+    const i64 ulo = std::max<i64>(0, W0g - nca + 1);
+    const i64 uhi = std::min<i64>(dmax, 32 * lastb + 31);
+
+    v16i acc[NW][2];
+    i64 acc64[WIDE ? NW : 1][2][WIDE ? 16 : 1];
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
-        if (blo[i] > bhi[i]) continue;
-        const i64 wb = wbFirst + (i64)wave * NW + i;
+        acc[i][0] = v16i{0};
+        acc[i][1] = v16i{0};
+    }
+    if (WIDE) {
 #pragma unroll
-        for (int gg = 0; gg < 16; ++gg) {
-            const u64 t = 32ull * (u64)(32 * wb + x) + acc_row(gg, lane);
-            const int v = acc[i][gg];
-            if (t < 8ull * (u64)P && v != 0)
-                __hip_atomic_fetch_add(pc + t, (u64)(i64)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int i = 0; i < (WIDE ? NW : 1); ++i)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int gg = 0; gg < (WIDE ? 16 : 1); ++gg) acc64[i][mi][gg] = 0;
+    }
+    const u32 *bz32 = reinterpret_cast<const u32 *>(bz);
+
+    for (i64 d0 = ulo; d0 <= uhi; d0 += D) {
+        const i64 d1 = std::min<i64>(d0 + D - 1, uhi);
+        const i64 cbase = W0g - d1;
+        const i64 nslots = Wend - d0 - cbase + 1;
+        __syncthreads();
+        for (u32 k = threadIdx.x; k < 8 * (D + 3); k += 256) {
+            const i64 m = 8 * (d0 - 1) + (i64)k;
+            bz[k] = (m >= 0 && m < (i64)nb) ? (pb[m] ^ XOR80) : 0ull;
+        }
+        for (u32 k = threadIdx.x; k < 8 * nslots; k += 256) {
+            const i64 c = cbase + (i64)(k >> 3);
+            const i64 m = 8 * c + 7 - (i64)(k & 7);
+            az[AZ_SLOT_U64 * (k >> 3) + (k & 7)] = (m >= 0 && m < (i64)na) ? __builtin_bswap64(pa[m] ^ XOR80) : 0ull;
+        }
+        __syncthreads();
+        const i64 dlo = std::max(d0, wlo), dhi = std::min(d1, whi);
+        if (dlo <= dhi) {
+            v4i f0 = toeplitz_frag(bz32, (u32)(64 * (dlo - d0)) + x + 1 + 16 * h);
+            for (i64 d = dlo; d <= dhi; ++d) {
+                const u32 ob = (u32)(64 * (d - d0)) + x + 1 + 16 * h;
+                const v4i f1 = toeplitz_frag(bz32, ob + 32);
+                const v4i f2 = toeplitz_frag(bz32, ob + 64);
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    if (d >= blo[i] && d <= bhi[i]) {
+                        const i64 wb = wb0 + (i64)wave * NW + i;
+                        const i64 slot = 32 * wb + (i64)x - d - cbase;
+                        const u64 *sp = az + AZ_SLOT_U64 * slot;
+                        const v4i A0 = *reinterpret_cast<const v4i *>(sp + 2 * h);
+                        const v4i A1 = *reinterpret_cast<const v4i *>(sp + 4 + 2 * h);
+                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, A0, acc[i][0], 0, 0, 0);
+                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A0, acc[i][1], 0, 0, 0);
+                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A1, acc[i][0], 0, 0, 0);
+                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, A1, acc[i][1], 0, 0, 0);
+                    }
+                }
+                f0 = f2;
+            }
+        }
+        if (WIDE) {
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+#pragma unroll
+                for (int mi = 0; mi < 2; ++mi) {
+#pragma unroll
+                    for (int gg = 0; gg < 16; ++gg) acc64[WIDE ? i : 0][mi][WIDE ? gg : 0] += acc[i][mi][gg];
+                    acc[i][mi] = v16i{0};
+                }
         }
     }
-}
 
-// Signed-digit column sums (8-bit columns) -> exact unsigned sums -> per-limb lo/shifted hi.
-__global__ void k_fold_mfma(const u64 *__restrict__ col, const u64 *__restrict__ a, const u64 *__restrict__ b,
-                            const u32 *__restrict__ lpa, const u32 *__restrict__ lpb, u64 na, u64 nb, u64 total,
-                            u64 *__restrict__ LO, u64 *__restrict__ HS) {
-    const u64 P = na + nb;
-    for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
-        const u64 p = idx / P, j = idx - p * P;
-        const u64 *pa = a + p * na, *pb = b + p * nb;
-        const u32 *la = lpa + p * (na + 1), *lb = lpb + p * (nb + 1);
-        const u64 *pc = col + p * 8 * P;
-        u128 V = 0;
+    // ---- epilogue: exact column sums -> limb values -> lo / shifted hi ----
+    const u32 *la = lpa + pair * (na + 1), *lb = lpb + pair * (nb + 1);
+    const u64 nda = 8 * na, ndb = 8 * nb;
+    u64 *lo_out = LO + pair * (u64)P, *hs_out = HS + pair * (u64)P;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const u64 t = 8 * j + u;
-            const i64 cf = column_fix((i64)pc[t], t, 8 * na, 8 * nb, pa, la, pb, lb);
-            V += (u128)(u64)cf << (8 * u);
+    for (int i = 0; i < NW; ++i) {
+        const i64 wb = wb0 + (i64)wave * NW + i;
+        if (wb >= nWb) continue;
+        const u64 W = (u64)(32 * wb) + x;
+        u64 plo[2][4], phi[2][4];
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                u128 v = 0;
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) {
+                    const int gg = 4 * m + ii;
+                    const u64 t = 64 * W + 32 * mi + 8 * m + 4 * h + ii;
+                    const i64 raw = WIDE ? acc64[WIDE ? i : 0][mi][WIDE ? gg : 0] : (i64)acc[i][mi][gg];
+                    const i64 cf = column_exact(raw, WIDE, t, nda, ndb, pa, la, pb, lb);
+                    v += (u128)(u64)cf << (8 * (4 * h + ii));
+                }
+                plo[mi][m] = (u64)v;
+                phi[mi][m] = (u64)(v >> 64);
+            }
         }
-        LO[idx] = (u64)V;
-        if (j + 1 < P) HS[idx + 1] = (u64)(V >> 64);
-        if (j == 0) HS[idx] = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const u64 slo = h ? plo[0][m] : plo[1][m];
+            const u64 shi = h ? phi[0][m] : phi[1][m];
+            const u64 rlo = __shfl_xor(slo, 32);
+            const u64 rhi = __shfl_xor(shi, 32);
+            const u64 klo = h ? plo[1][m] : plo[0][m];
+            const u64 khi = h ? phi[1][m] : phi[0][m];
+            const u128 V = (((u128)khi << 64) | klo) + (((u128)rhi << 64) | rlo);
+            const u64 j = 8 * W + 4 * h + m;
+            if (j < (u64)P) {
+                lo_out[j] = (u64)V;
+                if (j + 1 < (u64)P) hs_out[j + 1] = (u64)(V >> 64);
+                if (j == 0) hs_out[0] = 0;
+            }
+        }
     }
 }
 
 // ---------------------------------------------------------------- workspace ----
 struct LargeLayout {
-    size_t colLo, colHi, col64, lpa, lpb, aR, LO, HS, total;
+    size_t colLo, colHi, lpa, lpb, LO, HS, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -282,14 +372,10 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form) {
         L.colHi = off;
         off = align256(off + npairs * 2 * P * 8);
     } else {
-        L.col64 = off;
-        off = align256(off + npairs * 8 * P * 8);
         L.lpa = off;
         off = align256(off + npairs * (na + 1) * 4);
         L.lpb = off;
         off = align256(off + npairs * (nb + 1) * 4);
-        L.aR = off;
-        off = align256(off + npairs * (4 * ((na + 3) / 4) + 2 * AR_PAD) * 8);
     }
     L.LO = off;
     off = align256(off + npairs * P * 8);
@@ -336,7 +422,7 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
                                (u32)nb, npairs);
         return bn_launch_status();
     }
-    if (npairs > 65535) return BN_ERANGE;  // grid.y
+    if (form == BN_MUL_MAD && npairs > 65535) return BN_ERANGE;  // grid.y of the mad product kernel
     const LargeLayout L = large_layout(na, nb, npairs, form);
     bn_status st = bn_ensure(ctx, ctx->work, L.total, s);
     if (st != BN_OK) return st;
@@ -362,27 +448,24 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         hipLaunchKernelGGL(k_fold_mad, dim3((u32)fold_blocks), dim3(256), 0, s, colLo, colHi, P, total, LO, HS);
         if ((st = bn_launch_status()) != BN_OK) return st;
     } else {
-        u64 *col = reinterpret_cast<u64 *>(ws + L.col64);
         u32 *lpa = reinterpret_cast<u32 *>(ws + L.lpa);
         u32 *lpb = reinterpret_cast<u32 *>(ws + L.lpb);
-        u64 *aR = reinterpret_cast<u64 *>(ws + L.aR);
-        if ((st = launch_fill_u64(col, npairs * 8 * P, 0, s)) != BN_OK) return st;
-        hipLaunchKernelGGL(k_mfma_prep, dim3((u32)npairs), dim3(256), 0, s, a, b, na, nb, lpa, lpb, aR);
+        hipLaunchKernelGGL(k_mfma_prep, dim3((u32)npairs), dim3(256), 0, s, a, b, na, nb, lpa, lpb);
         if ((st = bn_launch_status()) != BN_OK) return st;
         constexpr int NW = 2;
+        const bool wide = 8 * std::min(na, nb) > 131586;
         const u32 D = (u32)ctx->tune.mfma_chunk;
-        const u64 dmax = (8 * nb + 30) / 32;
-        const u64 nchunks = (dmax + 1 + D - 1) / D;
-        const u64 nWb = (8 * P + 1023) / 1024;
+        const u64 nWb = (P + 255) / 256;
         const u64 ngroups = (nWb + 4 * NW - 1) / (4 * NW);
-        const u64 blocks = ngroups * nchunks;
+        const u64 blocks = ngroups * npairs;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
-        const size_t lds = (size_t)4 * (D + 3) * 8;
-        hipLaunchKernelGGL((k_mul_large_mfma<NW>), dim3((u32)blocks, (u32)npairs), dim3(256), lds, s, b, aR, na, nb,
-                           nchunks, D, col);
-        if ((st = bn_launch_status()) != BN_OK) return st;
-        hipLaunchKernelGGL(k_fold_mfma, dim3((u32)fold_blocks), dim3(256), 0, s, col, a, b, lpa, lpb, na, nb, total,
-                           LO, HS);
+        const size_t lds = (size_t)64 * (D + 3) + (size_t)80 * (128 * NW + D);
+        if (wide)
+            hipLaunchKernelGGL((k_mul_large_mfma<NW, true>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb,
+                               npairs, lpa, lpb, D, (u32)ngroups, LO, HS);
+        else
+            hipLaunchKernelGGL((k_mul_large_mfma<NW, false>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb,
+                               npairs, lpa, lpb, D, (u32)ngroups, LO, HS);
         if ((st = bn_launch_status()) != BN_OK) return st;
     }
     // deferred carry pass: r = LO + HS (1-bit carries), segments of P limbs

@@ -1,73 +1,64 @@
-// k_ragged.hip -- ragged batches: host-side plans and persistent work-queue kernels.
+// k_ragged.hip -- ragged batches: host-side plans and persistent kernels.
 //
 // A ragged batch holds pairs of uneven limb counts.  The plan sorts the pairs by
-// work (largest first) once on the host and uploads the list; one persistent launch
-// (a few waves per compute unit) then pulls pairs one at a time from an atomic
-// counter, so a long pair never leaves the rest of the grid idle.  The counter
-// resets itself (the last wave to finish clears it), so the launch can be captured
-// in a HIP graph and replayed.
+// work (largest first) once on the host, splits them by multiplication form and
+// uploads the lists.  Each form runs as one persistent launch sized to the
+// resident wave count; wave k takes items k, k + W, k + 2W, ... of the sorted
+// list, so every wave gets a similar mix of large and small pairs without any
+// shared counter (same-address atomics serialise at about 10-30 ns each on this
+// part, which would cost more than the products of a 2^16-pair batch).  The
+// launches hold no state between calls, so they can be captured in a HIP graph
+// and replayed.
 #include "bn_mul_dev.h"
 
 #include <algorithm>
 
 namespace {
 
-__device__ __forceinline__ u32 next_item(u32 *counter) {
-    u32 it = 0;
-    if ((threadIdx.x & 63) == 0) it = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __shfl(it, 0);
-}
-
-__device__ __forceinline__ void retire_wave(u32 *counter, u32 nwaves) {
-    if ((threadIdx.x & 63) == 0) {
-        const u32 prev = __hip_atomic_fetch_add(counter + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nwaves - 1) {
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(counter + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-}
-
 constexpr int RAGGED_LDS_U64 = SMALL_MFMA_LDS_U64;
 
-__global__ __launch_bounds__(256) void k_mul_ragged(const RItem *__restrict__ items, u32 nitems,
-                                                    u32 *__restrict__ counter, u32 nwaves, u64 *__restrict__ r,
-                                                    const u64 *__restrict__ a, const u64 *__restrict__ b) {
-    __shared__ u64 lds[4 * RAGGED_LDS_U64];
-    const int w = threadIdx.x >> 6;
-    while (true) {
-        const u32 it = next_item(counter);
-        if (it >= nitems) break;
+__global__ __launch_bounds__(256) void k_mul_ragged_mad(const RItem *__restrict__ items, u32 nitems,
+                                                        u64 *__restrict__ r, const u64 *__restrict__ a,
+                                                        const u64 *__restrict__ b) {
+    const u32 W = gridDim.x * 4;
+    for (u32 it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += W) {
         const RItem m = items[it];
         const u64 *pa = a + m.a_off;
         const u64 *pb = b + m.b_off;
         u64 *pr = r + m.r_off;
         const u32 P = m.na + m.nb;
-        if (m.form == BN_MUL_MFMA)
-            mul_item_mfma_small(pa, m.na, pb, m.nb, pr, lds + w * RAGGED_LDS_U64);
-        else if (P <= 64)
+        if (P <= 64)
             mul_item_mad<1>(pa, m.na, pb, m.nb, pr);
         else if (P <= 128)
             mul_item_mad<2>(pa, m.na, pb, m.nb, pr);
         else
             mul_item_mad<4>(pa, m.na, pb, m.nb, pr);
-        wave_sync();
     }
-    retire_wave(counter, nwaves);
 }
 
-// Ragged add/sub: one wave per pair, walking the pair in rows of 128 limbs (lane l
+__global__ __launch_bounds__(256) void k_mul_ragged_mfma(const RItem *__restrict__ items, u32 nitems,
+                                                         u64 *__restrict__ r, const u64 *__restrict__ a,
+                                                         const u64 *__restrict__ b) {
+    __shared__ u64 lds[4 * RAGGED_LDS_U64];
+    const int w = threadIdx.x >> 6;
+    const u32 W = gridDim.x * 4;
+    for (u32 it = blockIdx.x * 4 + w; it < nitems; it += W) {
+        const RItem m = items[it];
+        mul_item_mfma_small(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
+        wave_sync();
+    }
+}
+
+// Ragged add: one wave per pair, walking the pair in rows of 128 limbs (lane l
 // holds limbs 2l, 2l+1 of a row); the carry crosses rows through the wave-uniform
 // carry-out of the row's ballot scan.
 template <bool SUB>
 __global__ __launch_bounds__(256) void k_add_ragged(const RItem *__restrict__ items, u32 nitems,
-                                                    u32 *__restrict__ counter, u32 nwaves, u64 *__restrict__ r,
-                                                    const u64 *__restrict__ a, const u64 *__restrict__ b,
-                                                    u64 *__restrict__ carry) {
+                                                    u64 *__restrict__ r, const u64 *__restrict__ a,
+                                                    const u64 *__restrict__ b, u64 *__restrict__ carry) {
     const int lane = threadIdx.x & 63;
-    while (true) {
-        const u32 it = next_item(counter);
-        if (it >= nitems) break;
+    const u32 W = gridDim.x * 4;
+    for (u32 it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += W) {
         const RItem m = items[it];
         const u64 n = m.na;
         const u64 *pa = a + m.a_off, *pb = b + m.b_off;
@@ -100,11 +91,12 @@ __global__ __launch_bounds__(256) void k_add_ragged(const RItem *__restrict__ it
         }
         if (carry && n == 0 && lane == 0) carry[m.index] = 0;
     }
-    retire_wave(counter, nwaves);
 }
 
-u32 persistent_blocks(const bn_ctx *ctx, u32 nitems) {
-    const u32 want = (u32)std::max(1, ctx->num_cu) * 4;  // 4 workgroups (16 waves) per CU
+// Persistent grid: as many 4-wave workgroups as stay resident (occupancy in waves
+// per SIMD, 4 SIMDs per CU), but no more than the items need.
+u32 persistent_blocks(const bn_ctx *ctx, u32 nitems, int waves_per_simd) {
+    const u32 want = (u32)std::max(1, ctx->num_cu) * (u32)waves_per_simd;
     const u32 need = (nitems + 3) / 4;
     return std::max<u32>(1, std::min(want, need));
 }
@@ -117,9 +109,6 @@ bn_status upload_plan(bn_ctx *ctx, bn_plan *pl, std::vector<RItem> &small) {
         if (hipMemcpy(pl->d_items, small.data(), small.size() * sizeof(RItem), hipMemcpyHostToDevice) != hipSuccess)
             return BN_EHIP;
     }
-    if (hipMalloc(&pl->d_counter, 2 * sizeof(u32)) != hipSuccess) return BN_ENOMEM;
-    if (hipMemset(pl->d_counter, 0, 2 * sizeof(u32)) != hipSuccess) return BN_EHIP;
-    if (hipDeviceSynchronize() != hipSuccess) return BN_EHIP;
     return BN_OK;
 }
 
@@ -148,8 +137,12 @@ bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int 
         else
             pl->large.push_back(it);
     }
-    std::stable_sort(small.begin(), small.end(),
-                     [](const RItem &x, const RItem &y) { return (u64)x.na * x.nb > (u64)y.na * y.nb; });
+    // mad items first, then MFMA items; each group by work, largest first
+    std::stable_sort(small.begin(), small.end(), [](const RItem &x, const RItem &y) {
+        if (x.form != y.form) return x.form == BN_MUL_MAD;
+        return (u64)x.na * x.nb > (u64)y.na * y.nb;
+    });
+    pl->nsmall_mad = (u32)std::count_if(small.begin(), small.end(), [](const RItem &x) { return x.form == BN_MUL_MAD; });
     bn_status st = upload_plan(ctx, pl, small);
     if (st != BN_OK) {
         bn_plan_destroy(pl);
@@ -187,10 +180,16 @@ bn_status plan_add_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, bn_p
 }
 
 bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, hipStream_t s) {
-    if (pl->nsmall) {
-        const u32 blocks = persistent_blocks(ctx, pl->nsmall);
-        hipLaunchKernelGGL(k_mul_ragged, dim3(blocks), dim3(256), 0, s, pl->d_items, pl->nsmall, pl->d_counter,
-                           blocks * 4, r, a, b);
+    const u32 nmad = pl->nsmall_mad, nmfma = pl->nsmall - pl->nsmall_mad;
+    if (nmad) {
+        hipLaunchKernelGGL(k_mul_ragged_mad, dim3(persistent_blocks(ctx, nmad, 8)), dim3(256), 0, s, pl->d_items, nmad,
+                           r, a, b);
+        bn_status st = bn_launch_status();
+        if (st != BN_OK) return st;
+    }
+    if (nmfma) {
+        hipLaunchKernelGGL(k_mul_ragged_mfma, dim3(persistent_blocks(ctx, nmfma, 2)), dim3(256), 0, s,
+                           pl->d_items + nmad, nmfma, r, a, b);
         bn_status st = bn_launch_status();
         if (st != BN_OK) return st;
     }
@@ -204,8 +203,7 @@ bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a
 bn_status launch_add_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, u64 *carry,
                             hipStream_t s) {
     if (!pl->nsmall) return BN_OK;
-    const u32 blocks = persistent_blocks(ctx, pl->nsmall);
-    hipLaunchKernelGGL(k_add_ragged<false>, dim3(blocks), dim3(256), 0, s, pl->d_items, pl->nsmall, pl->d_counter,
-                       blocks * 4, r, a, b, carry);
+    hipLaunchKernelGGL(k_add_ragged<false>, dim3(persistent_blocks(ctx, pl->nsmall, 8)), dim3(256), 0, s,
+                       pl->d_items, pl->nsmall, r, a, b, carry);
     return bn_launch_status();
 }

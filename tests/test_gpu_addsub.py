@@ -148,7 +148,7 @@ def test_empty_and_errors(bnctx):
     with pytest.raises(bn.BnError):
         bn.bn_set_param(bnctx, "addsub.chain_rows", 3)
     with pytest.raises(bn.BnError):
-        bn.bn_set_param(bnctx, "mul.mfma_chunk", 4096)      # beyond the int32 accumulator bound
+        bn.bn_set_param(bnctx, "mul.mfma_chunk", 2048)      # beyond the int32 accumulator bound
 
 
 def test_graph_replay_matches_eager(bnctx):
