@@ -1,0 +1,59 @@
+"""The in-library autotuner runs on the device, writes a table that a fresh context
+loads back, and results stay exact with the tuned parameters."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_21566_amd as bn
+from conftest import announce
+from paper_2604_21566_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("addsub.batch_waves", "addsub.batch_rows", "addsub.chain_waves", "addsub.chain_rows",
+        "mul.crossover_limbs", "mul.mad_xchunk", "mul.mfma_chunk")
+
+
+def test_autotune_roundtrip(tmp_path):
+    announce("autotune")
+    path = str(tmp_path / "tune.json")
+    ctx = bn.bn_create(0)
+    try:
+        bn.bn_autotune(ctx, path)
+        tuned = {k: bn.bn_get_param(ctx, k) for k in KEYS}
+    finally:
+        bn.bn_destroy(ctx)
+    table = json.load(open(path))
+    for k in KEYS:
+        assert table[k] == tuned[k]
+    ctx = bn.bn_create(0)
+    try:
+        bn.bn_load_tuning(ctx, path)
+        assert {k: bn.bn_get_param(ctx, k) for k in KEYS} == tuned
+        # exact results with the tuned table: batched add, one long add, AUTO multiply
+        a, b = wl.c2("add", npairs=3000)
+        ta, tb = bn.to_device(a), bn.to_device(b)
+        tr = torch.empty_like(ta)
+        tc = torch.empty(3000, dtype=torch.int64, device="cuda")
+        bn.bn_add_n_batch(ctx, tr, ta, tb, 64, 3000, tc)
+        a3, b3 = wl.c3("add", n=1 << 17)
+        t3 = torch.empty(a3.size, dtype=torch.int64, device="cuda")
+        bn.bn_add(ctx, t3, bn.to_device(a3), bn.to_device(b3))
+        g = np.random.default_rng(1)
+        for n in (16, 300, 2000):
+            x = g.integers(0, 2 ** 64 - 1, n * 2, dtype=np.uint64, endpoint=True)
+            y = g.integers(0, 2 ** 64 - 1, n * 2, dtype=np.uint64, endpoint=True)
+            r = torch.empty(4 * n, dtype=torch.int64, device="cuda")
+            bn.bn_mul_n_batch(ctx, r, bn.to_device(x), bn.to_device(y), n, n, 2, "auto")
+            torch.cuda.synchronize()
+            assert (bn.to_host(r) == oracle.mul_batch(x, y, n, n, 2)).all(), n
+        torch.cuda.synchronize()
+        rr, rc = oracle.add_batch(a, b, 64)
+        assert (bn.to_host(tr) == rr).all() and (bn.to_host(tc) == rc).all()
+        r3, _ = oracle.add(a3, b3)
+        assert (bn.to_host(t3) == r3).all()
+    finally:
+        bn.bn_destroy(ctx)
