@@ -25,14 +25,18 @@ typedef unsigned __int128 u128;
 
 #define BN_DPP_WAVE_SHR1 0x138
 
-// lo:hi (96-bit) += x * y, using the carry-out of v_mad_u64_u32.
+// lo:hi (96-bit) += x * y, using the carry-out of v_mad_u64_u32.  x is wave-uniform
+// and stays in an SGPR (one scalar source per VOP3 instruction).
 __device__ __forceinline__ void mac96(u64 &lo, u32 &hi, u32 x, u32 y) {
     u64 cc;
     asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
         "v_addc_co_u32 %2, %1, 0, %2, %1"
         : "+v"(lo), "=&s"(cc), "+v"(hi)
-        : "v"(x), "v"(y));
+        : "s"(x), "v"(y));
 }
+
+// Value of a wave-uniform step's operand held in lane k of v (k uniform).
+__device__ __forceinline__ u32 lane_value(u32 v, u32 k) { return (u32)__builtin_amdgcn_readlane((int)v, (int)k); }
 
 // Wave-local LDS ordering point (all waves of a workgroup run independently).
 __device__ __forceinline__ void wave_sync() {
@@ -88,6 +92,15 @@ __device__ __forceinline__ void wave_normalise_store(const u64 (&lo)[L], const u
 template <int L>
 __device__ void mul_item_mad(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
                              u64 *__restrict__ r) {
+    // the step loop runs over the digits of a: make a the shorter operand (a*b = b*a)
+    if (na > nb) {
+        const u64 *t = a;
+        a = b;
+        b = t;
+        const u32 tn = na;
+        na = nb;
+        nb = tn;
+    }
     constexpr int Q = 2 * L;
     const int lane = threadIdx.x & 63;
     const u32 *a32 = reinterpret_cast<const u32 *>(a);
@@ -107,15 +120,19 @@ __device__ void mul_item_mad(const u64 *__restrict__ a, u32 na, const u64 *__res
         lo[q] = 0;
         hi[q] = 0;
     }
-    for (u32 xb = 0; xb < nx; xb += Q) {
+    // 64 digits of a per coalesced load; each step broadcasts one of them (readlane).
+    // Steps past nx multiply by a zero digit, so they only cost time.
+    for (u32 xb = 0; xb < nx; xb += 64) {
+        const u32 areg = (xb + lane < nx) ? a32[xb + lane] : 0u;
+        for (u32 s0 = 0; s0 < 64 && xb + s0 < nx; s0 += 2 * Q) {
 #pragma unroll
-        for (int s = 0; s < Q; ++s) {
-            const u32 x = xb + s;
-            const u32 al = x < nx ? a32[x] : 0u;
+            for (int s = 0; s < 2 * Q; ++s) {
+                const u32 al = lane_value(areg, s0 + s);
 #pragma unroll
-            for (int q = 0; q < Q; ++q) mac96(lo[q], hi[q], al, R[(q - s + Q) % Q]);
-            const int k = (Q - 1 - s + Q) % Q;
-            R[k] = (u32)__builtin_amdgcn_update_dpp(0, (int)R[k], BN_DPP_WAVE_SHR1, 0xf, 0xf, true);
+                for (int q = 0; q < Q; ++q) mac96(lo[q], hi[q], al, R[(q - s + 2 * Q) % Q]);
+                const int k = (Q - 1 - s + 2 * Q) % Q;
+                R[k] = (u32)__builtin_amdgcn_update_dpp(0, (int)R[k], BN_DPP_WAVE_SHR1, 0xf, 0xf, true);
+            }
         }
     }
     u64 vlo[L], vhi[L];
@@ -226,6 +243,15 @@ constexpr int SMALL_MFMA_LDS_U64 = 272 + 256 + 128 + 128;  // bz, aR, lpa (256 u
 // lds: SMALL_MFMA_LDS_U64 words private to the wave.
 __device__ __noinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
                                     u64 *__restrict__ r, u64 *lds) {
+    // the Toeplitz steps run over the digits of b: make b the shorter operand
+    if (nb > na) {
+        const u64 *t = a;
+        a = b;
+        b = t;
+        const u32 tn = na;
+        na = nb;
+        nb = tn;
+    }
     const int lane = threadIdx.x & 63;
     const u32 x = lane & 31, h = lane >> 5;
     const u32 nda = 8 * na, ndb = 8 * nb, P = na + nb;

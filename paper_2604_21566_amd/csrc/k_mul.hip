@@ -70,17 +70,22 @@ __global__ __launch_bounds__(256) void k_mul_large_mad(const u64 *__restrict__ a
         lo[q] = 0;
         hi[q] = 0;
     }
-    for (i64 xb = xs; xb < xe; xb += Q) {
+    // 64 digits of a and the 64 lane-0 fill values of beta per coalesced load; each
+    // step broadcasts its pair with readlane.  Steps past xe use a zero digit.
+    for (i64 xb = xs; xb < xe; xb += 64) {
+        const u32 areg = (xb + lane < xe) ? a32[xb + lane] : 0u;
+        const i64 yf = T0 - xb - 1 - lane;  // fill for step xb + lane
+        const u32 freg = (yf >= 0 && yf < ny) ? b32[yf] : 0u;
+        for (u32 s0 = 0; s0 < 64 && xb + s0 < xe; s0 += Q) {
 #pragma unroll
-        for (int s = 0; s < Q; ++s) {
-            const i64 x = xb + s;
-            const u32 al = x < xe ? a32[x] : 0u;
+            for (int s = 0; s < Q; ++s) {
+                const u32 al = lane_value(areg, s0 + s);
 #pragma unroll
-            for (int q = 0; q < Q; ++q) mac96(lo[q], hi[q], al, R[(q - s + Q) % Q]);
-            const i64 yf = T0 - x - 1;
-            const u32 fill = (yf >= 0 && yf < ny) ? b32[yf] : 0u;
-            const int k = (Q - 1 - s + Q) % Q;
-            R[k] = (u32)__builtin_amdgcn_update_dpp((int)fill, (int)R[k], BN_DPP_WAVE_SHR1, 0xf, 0xf, false);
+                for (int q = 0; q < Q; ++q) mac96(lo[q], hi[q], al, R[(q - s + Q) % Q]);
+                const u32 fill = lane_value(freg, s0 + s);
+                const int k = (Q - 1 - s + Q) % Q;
+                R[k] = (u32)__builtin_amdgcn_update_dpp((int)fill, (int)R[k], BN_DPP_WAVE_SHR1, 0xf, 0xf, false);
+            }
         }
     }
     const u64 ncol = 2 * (na + nb);
