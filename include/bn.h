@@ -176,7 +176,8 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "addsub.batch_waves", "addsub.batch_rows"   add/sub tile shape when the tile length
  *                                      is a multiple of the pair length (independent tiles)
  *   "addsub.chain_waves", "addsub.chain_rows"   tile shape otherwise (look-back between tiles)
- *                                      waves in {1,2,4,8}, rows of 128 limbs in {1,2,4,8,16}
+ *                                      waves in {1,2,4,8}, rows of 128 limbs in {1,2,4,8,16},
+ *                                      except 8 waves x 16 rows
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
  *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large

@@ -24,6 +24,8 @@
 // reads one contiguous 1 KiB block.
 #include "bn_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 constexpr u64 ST_A = 1;   // tile aggregate ready, tile propagates its carry-in (carry-out unknown)
@@ -127,6 +129,14 @@ template <bool SUB>
 __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64 *latch,
                         const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G) {
     const int lane = threadIdx.x & 63;
+    // fast probe: the nearest predecessor usually knows its carry-out already
+    {
+        u64 st = 0;
+        if (lane == 0) st = ld_relaxed(status + t - 1);
+        st = __shfl(st, 0);
+        const u32 state = ((st >> 2) == epoch) ? (u32)(st & 3) : 0u;
+        if (state >= ST_I0) return state & 1u;
+    }
     i64 base = (i64)t - 1;
     u32 spins = 0;
     while (true) {
@@ -158,13 +168,14 @@ __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64
     }
 }
 
-template <bool SUB, int WAVES, int ROWS, bool VEC>
+template <bool SUB, int WAVES, int ROWS, bool VEC, bool CHAIN>
 __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, const u64 *__restrict__ a,
                                                           const u64 *__restrict__ b, ScanGeom G, u64 step_mod,
                                                           u64 step_div, u64 *__restrict__ carry,
                                                           ScanCtl *__restrict__ ctl, u64 *__restrict__ status,
-                                                          u32 spin_limit, u32 dbg, int chain) {
-    __shared__ u32 sh_g[WAVES], sh_p[WAVES], sh_cin[WAVES];
+                                                          u32 spin_limit, u32 dbg) {
+    constexpr bool chain = CHAIN;
+    __shared__ u32 sh_g[WAVES], sh_p[WAVES], sh_cin[WAVES], sh_cin_true[WAVES], sh_pt;
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -251,36 +262,29 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     }
     __syncthreads();
 
-    // ---- phase 3: tile aggregate, publish, look-back, per-wave carry-in ----
-    if (w == 0) {
-        u32 cin = 0;
-        if (chain) {
-            u32 gt = 0, pt = 1;
+    // ---- phase 3: carries into the waves assuming carry-in 0 into the tile; publish ----
+    // A tile that does not propagate knows its carry-out now (I0/I1); one that
+    // propagates publishes A and learns its carry-in by look-back in phase 5.
+    const bool poison = (dbg & 1u) && t == 0;
+    if (threadIdx.x == 0) {
+        u32 c = 0, pt = 1;
 #pragma unroll
-            for (int i = 0; i < WAVES; ++i) {
-                gt = sh_g[i] | (sh_p[i] & gt);
-                pt &= sh_p[i];
-            }
-            const bool poison = (dbg & 1u) && t == 0;
-            if (lane == 0 && !poison) st_relaxed(status + t, (epoch << 2) | (pt ? ST_A : (gt ? ST_I1 : ST_I0)));
-            const u64 first_pos = __shfl(pos0, 0);
-            if (t > 0 && first_pos != 0) cin = lookback<SUB>(status, t, epoch, spin_limit, &ctl->err, a, b, G);
-            if (lane == 0 && pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
+        for (int i = 0; i < WAVES; ++i) {
+            sh_cin[i] = c;
+            c = sh_g[i] | (sh_p[i] & c);
+            pt &= sh_p[i];
         }
-        if (lane == 0) {
-            u32 c = cin;
-#pragma unroll
-            for (int i = 0; i < WAVES; ++i) {
-                sh_cin[i] = c;
-                c = sh_g[i] | (sh_p[i] & c);
-            }
-        }
+        sh_pt = pt;
+        if (chain && !poison) st_relaxed(status + t, (epoch << 2) | (pt ? ST_A : (c ? ST_I1 : ST_I0)));
     }
     __syncthreads();
 
-    // ---- phase 4: apply carries, store sums and per-segment carry-outs ----
+    // ---- phase 4: apply the carries, store sums and per-segment carry-outs ----
+    // Stored optimistically: in a chained launch the tile's real carry-in is not
+    // known yet; phase 5 rewrites the few limbs it changes (DoT's rare fix-up).
+    const u32 c_assumed = sh_cin[w];
     {
-        u64 c = sh_cin[w];
+        u64 c = c_assumed;
         u64 pos = pos0, q = q0;
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
@@ -317,6 +321,65 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
             }
         }
     }
+    if (!chain) return;
+
+    // ---- phase 5: the tile's real carry-in (look-back), publish, repair ----
+    if (w == 0) {
+        u32 cin = 0;
+        const u64 first_pos = __shfl(pos0, 0);
+        if (t > 0 && first_pos != 0) cin = lookback<SUB>(status, t, epoch, spin_limit, &ctl->err, a, b, G);
+        if (lane == 0) {
+            if (sh_pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
+            u32 c = cin;
+#pragma unroll
+            for (int i = 0; i < WAVES; ++i) {
+                sh_cin_true[i] = c;
+                c = sh_g[i] | (sh_p[i] & c);
+            }
+        }
+    }
+    __syncthreads();  // also orders the optimistic stores before their rewrites
+    const u32 c_true = sh_cin_true[w];
+    if (c_true != c_assumed) {
+        // Replay the rows with both carries; lanes whose carry differs rewrite the
+        // limbs (and segment carry-outs) that change; stop once the chains agree.
+        u64 ca = c_assumed, ct = c_true;
+        u64 pos = pos0, q = q0;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const u64 idx = idx0 + (u64)j * 128;
+            u64 coa = ca, cot = ct;
+            u64 Ca = 0, Ct = 0;
+            if (ca != ct) {  // wave-uniform; once the chains agree every later row is unchanged
+                Ca = row_resolve(Gm[j], Pm[j], ca, coa);
+                Ct = row_resolve(Gm[j], Pm[j], ct, cot);
+            }
+            if (((Ca ^ Ct) >> lane) & 1ull) {
+                const bool g0 = fl[j] & 1u, p0 = fl[j] & 2u, g1 = fl[j] & 4u, p1 = fl[j] & 8u;
+                const bool st0 = (pos == 0);
+                const bool st1 = (pos + 1 == n);
+                const bool en1 = (n == 1) || (pos + 2 == n);
+                const bool ci0a = ((Ca >> lane) & 1ull) && !st0, ci0t = ((Ct >> lane) & 1ull) && !st0;
+                const bool co0a = g0 || (p0 && ci0a), co0t = g0 || (p0 && ci0t);
+                const bool ci1a = co0a && !st1, ci1t = co0t && !st1;
+                const bool co1a = g1 || (p1 && ci1a), co1t = g1 || (p1 && ci1t);
+                if (ci0a != ci0t && idx < N) r[idx] = SUB ? x0[j] - (u64)ci0t : x0[j] + (u64)ci0t;
+                if (ci1a != ci1t && idx + 1 < N) r[idx + 1] = SUB ? x1[j] - (u64)ci1t : x1[j] + (u64)ci1t;
+                if (carry) {
+                    if (idx < N && st1 && co0a != co0t) carry[q] = co0t;
+                    if (idx + 1 < N && en1 && co1a != co1t) carry[q + (st1 ? 1 : 0)] = co1t;
+                }
+            }
+            ca = coa;
+            ct = cot;
+            pos += step_mod;
+            q += step_div;
+            if (pos >= n) {
+                pos -= n;
+                q += 1;
+            }
+        }
+    }
 }
 
 // After a chained launch: move to a fresh epoch so that the next launch never
@@ -329,45 +392,61 @@ __global__ void k_fill_u64(u64 *p, u64 count, u64 value) {
         p[i] = value;
 }
 
-typedef void (*scan_fn)(u64 *, const u64 *, const u64 *, ScanGeom, u64, u64, u64 *, ScanCtl *, u64 *, u32, u32,
-                        int);
+typedef void (*scan_fn)(u64 *, const u64 *, const u64 *, ScanGeom, u64, u64, u64 *, ScanCtl *, u64 *, u32, u32);
 
-template <bool SUB, bool VEC>
+template <bool SUB, bool CHAIN>
 scan_fn pick(int waves, int rows) {
 #define BN_SHAPE(W, R) \
-    if (waves == W && rows == R) return k_flat_scan<SUB, W, R, VEC>;
-#define BN_ROWS(W) BN_SHAPE(W, 1) BN_SHAPE(W, 2) BN_SHAPE(W, 4) BN_SHAPE(W, 8) BN_SHAPE(W, 16)
+    if (waves == W && rows == R) return k_flat_scan<SUB, W, R, true, CHAIN>;
+#define BN_ROWS(W) BN_SHAPE(W, 1) BN_SHAPE(W, 2) BN_SHAPE(W, 4) BN_SHAPE(W, 8)
     BN_ROWS(1)
     BN_ROWS(2)
     BN_ROWS(4)
     BN_ROWS(8)
+    BN_SHAPE(1, 16)
+    BN_SHAPE(2, 16)
+    BN_SHAPE(4, 16)  // 8 x 16 would not fit the register file
 #undef BN_ROWS
 #undef BN_SHAPE
     return nullptr;
 }
 
+// Operands that are only 8-byte aligned take 8-byte loads and fixed shapes.
+constexpr int UNALIGNED_BATCH_WAVES = 1, UNALIGNED_BATCH_ROWS = 1;
+constexpr int UNALIGNED_CHAIN_WAVES = 4, UNALIGNED_CHAIN_ROWS = 4;
+
 }  // namespace
 
-bool flat_scan_shape_ok(int waves, int rows) { return pick<false, true>(waves, rows) != nullptr; }
+bool flat_scan_shape_ok(int waves, int rows) { return pick<false, false>(waves, rows) != nullptr; }
 
 // Shape for a launch over segments of n limbs: the independent-tile shape when its
 // tile length is a multiple of n, else the chained (look-back) shape.
-static void flat_scan_shape(const bn_ctx *ctx, u64 n, int &waves, int &rows) {
-    const u64 tl = (u64)ctx->tune.batch_waves * ctx->tune.batch_rows * 128;
-    if (n && tl % n == 0) {
-        waves = ctx->tune.batch_waves;
-        rows = ctx->tune.batch_rows;
+static void flat_scan_shape(const bn_ctx *ctx, u64 n, bool vec, int &waves, int &rows, bool &chain) {
+    const int bw = vec ? ctx->tune.batch_waves : UNALIGNED_BATCH_WAVES;
+    const int br = vec ? ctx->tune.batch_rows : UNALIGNED_BATCH_ROWS;
+    const u64 tl = (u64)bw * br * 128;
+    chain = !(n && tl % n == 0);
+    if (!chain) {
+        waves = bw;
+        rows = br;
     } else {
-        waves = ctx->tune.chain_waves;
-        rows = ctx->tune.chain_rows;
+        waves = vec ? ctx->tune.chain_waves : UNALIGNED_CHAIN_WAVES;
+        rows = vec ? ctx->tune.chain_rows : UNALIGNED_CHAIN_ROWS;
     }
 }
 
+// Status words needed by a launch over N limbs in segments of n (the larger count
+// of the aligned and the unaligned shape, so a reservation covers both).
 size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N) {
-    int waves, rows;
-    flat_scan_shape(ctx, n, waves, rows);
-    const u64 TL = (u64)waves * rows * 128;
-    return (size_t)((N + TL - 1) / TL) * sizeof(u64);
+    u64 tiles = 0;
+    for (int v = 0; v < 2; ++v) {
+        int waves = 1, rows = 1;
+        bool chain = false;
+        flat_scan_shape(ctx, n, v == 1, waves, rows, chain);
+        const u64 TL = (u64)waves * rows * 128;
+        tiles = std::max<u64>(tiles, (N + TL - 1) / TL);
+    }
+    return (size_t)tiles * sizeof(u64);
 }
 
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s) {
@@ -382,24 +461,32 @@ bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
                            hipStream_t s) {
     const u64 N = n * npairs;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
+    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)b) & 15u) == 0;
     int waves, rows;
-    flat_scan_shape(ctx, n, waves, rows);
+    bool chain;
+    flat_scan_shape(ctx, n, vec, waves, rows, chain);
     const u64 TL = (u64)waves * rows * 128;
     const u64 ntiles = (N + TL - 1) / TL;
-    const int chain = (TL % n) != 0;
     if (chain) {
         bn_status st = bn_ensure(ctx, ctx->status, ntiles * sizeof(u64), s);
         if (st != BN_OK) return st;
     }
     if (ntiles > 0x7fffffffull) return BN_ERANGE;
-    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)b) & 15u) == 0;
-    scan_fn f = sub ? (vec ? pick<true, true>(waves, rows) : pick<true, false>(waves, rows))
-                    : (vec ? pick<false, true>(waves, rows) : pick<false, false>(waves, rows));
+    scan_fn f = nullptr;
+    if (vec)
+        f = sub ? (chain ? pick<true, true>(waves, rows) : pick<true, false>(waves, rows))
+                : (chain ? pick<false, true>(waves, rows) : pick<false, false>(waves, rows));
+    else if (chain)
+        f = sub ? k_flat_scan<true, UNALIGNED_CHAIN_WAVES, UNALIGNED_CHAIN_ROWS, false, true>
+                : k_flat_scan<false, UNALIGNED_CHAIN_WAVES, UNALIGNED_CHAIN_ROWS, false, true>;
+    else
+        f = sub ? k_flat_scan<true, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false>
+                : k_flat_scan<false, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false>;
     if (!f) return BN_EINVAL;
     ScanGeom G{N, n, -1, TL};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
-                       ctx->ctl, (u64 *)ctx->status.ptr, ctx->tune.spin_limit, ctx->tune.debug_flags, chain);
+                       ctx->ctl, (u64 *)ctx->status.ptr, ctx->tune.spin_limit, ctx->tune.debug_flags);
     bn_status st = bn_launch_status();
     if (st != BN_OK || !chain) return st;
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, ctx->ctl);
