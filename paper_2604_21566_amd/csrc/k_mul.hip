@@ -199,25 +199,33 @@ constexpr int AZ_SLOT_U64 = 10;  // one 64-digit chunk per 80-byte LDS slot: ds_
 // 32x32x32 MFMAs per step; the three distinct Toeplitz fragments (rows + K-slice
 // offsets 0, 32, 64) are shared by the wave's NW blocks and the third becomes the
 // first of the next step.  A workgroup (4 waves, 4 NW blocks) covers the whole
-// contraction range of its blocks, staging D steps of b digits and the matching
-// window of a chunks (byte-reversed) in LDS per round, so there is no split of the
-// contraction, no atomics and no workspace zeroing.  Accumulation is int32; when
-// a column can hold more than 131586 digit products (wide) each round is widened
-// into int64 registers, otherwise the epilogue decodes the int32 sum exactly.  The
-// epilogue folds the 64 columns of each W into 8 limb values and writes lo and
-// shifted hi for the final carry pass.  Workgroups are ordered by decreasing work.
-template <int NW, bool WIDE>
+// contraction range of its blocks (or, SPLIT, one slice of it when there are too
+// few workgroups to fill the device), staging D steps of b digits and the matching
+// window of a chunks (byte-reversed) in LDS per round: no atomics and no
+// workspace zeroing in the unsplit case.  Accumulation is int32.  Unsplit launches
+// have at most 2047 steps, so a column holds at most 131008 digit products: its
+// register holds the true signed sum M modulo 2^32 and M lies in
+// [-16256 cnt, 16384 cnt], narrower than 2^32, so the epilogue decodes it exactly,
+// folds the 64 columns of each W into 8 limb values and writes lo and shifted hi.
+// Split launches keep every slice at most 2047 steps (2047 * 64 * 2^14 < 2^31, exact)
+// and add the slice sums into an int64 column workspace that a fold kernel reads.
+// Workgroups are ordered by decreasing work.
+template <int NW, bool SPLIT>
 __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
                                                         u64 nb, u64 npairs, const u32 *__restrict__ lpa,
                                                         const u32 *__restrict__ lpb, u32 D, u32 ngroups,
-                                                        u64 *__restrict__ LO, u64 *__restrict__ HS) {
+                                                        u32 nslices, u64 *__restrict__ LO, u64 *__restrict__ HS,
+                                                        u64 *__restrict__ col) {
     extern __shared__ u64 lds[];
     u64 *bz = lds;                     // 8 (D + 3) words of signed b digits
     u64 *az = lds + 8 * ((u64)D + 3);  // (128 NW + D) chunk slots of reversed signed a digits
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const u32 x = lane & 31, h = lane >> 5;
-    const u64 pair = blockIdx.x % npairs;
-    const u32 g = middle_out((u32)(blockIdx.x / npairs), ngroups);
+    // block -> (slice, group, pair); groups in decreasing-work order
+    const u64 slice = SPLIT ? blockIdx.x % nslices : 0;
+    const u64 bq = SPLIT ? blockIdx.x / nslices : blockIdx.x;
+    const u64 pair = bq % npairs;
+    const u32 g = middle_out((u32)(bq / npairs), ngroups);
     const i64 P = (i64)(na + nb);
     const i64 nca = (i64)((na + 7) / 8);
     const i64 dmax = (8 * (i64)nb + 62) / 64;
@@ -243,23 +251,20 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
         }
     }
     const i64 lastb = std::min<i64>(wb0 + 4 * NW, nWb) - 1;
-    const i64 ulo = std::max<i64>(0, W0g - nca + 1);
-    const i64 uhi = std::min<i64>(dmax, 32 * lastb + 31);
+    i64 ulo = std::max<i64>(0, W0g - nca + 1);
+    i64 uhi = std::min<i64>(dmax, 32 * lastb + 31);
+    if (SPLIT) {
+        // this workgroup's slice of the contraction range (at most 2047 steps: exact int32)
+        const i64 sl = (dmax + (i64)nslices) / (i64)nslices;
+        ulo = std::max<i64>(ulo, (i64)slice * sl);
+        uhi = std::min<i64>(uhi, (i64)slice * sl + sl - 1);
+    }
 
     v16i acc[NW][2];
-    i64 acc64[WIDE ? NW : 1][2][WIDE ? 16 : 1];
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
         acc[i][0] = v16i{0};
         acc[i][1] = v16i{0};
-    }
-    if (WIDE) {
-#pragma unroll
-        for (int i = 0; i < (WIDE ? NW : 1); ++i)
-#pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                for (int gg = 0; gg < (WIDE ? 16 : 1); ++gg) acc64[i][mi][gg] = 0;
     }
     const u32 *bz32 = reinterpret_cast<const u32 *>(bz);
 
@@ -302,18 +307,28 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
                 f0 = f2;
             }
         }
-        if (WIDE) {
-#pragma unroll
-            for (int i = 0; i < NW; ++i)
-#pragma unroll
-                for (int mi = 0; mi < 2; ++mi) {
-#pragma unroll
-                    for (int gg = 0; gg < 16; ++gg) acc64[WIDE ? i : 0][mi][WIDE ? gg : 0] += acc[i][mi][gg];
-                    acc[i][mi] = v16i{0};
-                }
-        }
     }
 
+    if (SPLIT) {
+        // partial column sums of this slice -> int64 column workspace (folded later)
+        if (ulo > uhi) return;
+        u64 *pc = col + pair * 8 * (u64)P;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const i64 wb = wb0 + (i64)wave * NW + i;
+            if (wb >= nWb) continue;
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int gg = 0; gg < 16; ++gg) {
+                    const u64 t = 64 * ((u64)(32 * wb) + x) + 32 * mi + acc_row(gg, lane);
+                    const int v = acc[i][mi][gg];
+                    if (v != 0 && t < 8 * (u64)P)
+                        __hip_atomic_fetch_add(pc + t, (u64)(i64)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+        }
+        return;
+    }
     // ---- epilogue: exact column sums -> limb values -> lo / shifted hi ----
     const u32 *la = lpa + pair * (na + 1), *lb = lpb + pair * (nb + 1);
     const u64 nda = 8 * na, ndb = 8 * nb;
@@ -333,8 +348,7 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
                 for (int ii = 0; ii < 4; ++ii) {
                     const int gg = 4 * m + ii;
                     const u64 t = 64 * W + 32 * mi + 8 * m + 4 * h + ii;
-                    const i64 raw = WIDE ? acc64[WIDE ? i : 0][mi][WIDE ? gg : 0] : (i64)acc[i][mi][gg];
-                    const i64 cf = column_exact(raw, WIDE, t, nda, ndb, pa, la, pb, lb);
+                    const i64 cf = column_exact((i64)acc[i][mi][gg], false, t, nda, ndb, pa, la, pb, lb);
                     v += (u128)(u64)cf << (8 * (4 * h + ii));
                 }
                 plo[mi][m] = (u64)v;
@@ -360,14 +374,37 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
     }
 }
 
+// Column sums from the split MFMA kernel -> exact unsigned sums -> limb lo / shifted hi.
+__global__ void k_fold_mfma_cols(const u64 *__restrict__ col, const u64 *__restrict__ a, const u64 *__restrict__ b,
+                                 const u32 *__restrict__ lpa, const u32 *__restrict__ lpb, u64 na, u64 nb, u64 total,
+                                 u64 *__restrict__ LO, u64 *__restrict__ HS) {
+    const u64 P = na + nb;
+    for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
+        const u64 p = idx / P, j = idx - p * P;
+        const u64 *pa = a + p * na, *pb = b + p * nb;
+        const u32 *la = lpa + p * (na + 1), *lb = lpb + p * (nb + 1);
+        const u64 *pc = col + p * 8 * P;
+        u128 V = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const u64 t = 8 * j + u;
+            const i64 cf = column_exact((i64)pc[t], true, t, 8 * na, 8 * nb, pa, la, pb, lb);
+            V += (u128)(u64)cf << (8 * u);
+        }
+        LO[idx] = (u64)V;
+        if (j + 1 < P) HS[idx + 1] = (u64)(V >> 64);
+        if (j == 0) HS[idx] = 0;
+    }
+}
+
 // ---------------------------------------------------------------- workspace ----
 struct LargeLayout {
-    size_t colLo, colHi, lpa, lpb, LO, HS, total;
+    size_t colLo, colHi, col64, lpa, lpb, LO, HS, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form) {
+static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, bool split) {
     LargeLayout L{};
     const u64 P = na + nb;
     size_t off = 0;
@@ -377,6 +414,10 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form) {
         L.colHi = off;
         off = align256(off + npairs * 2 * P * 8);
     } else {
+        if (split) {
+            L.col64 = off;
+            off = align256(off + npairs * 8 * P * 8);
+        }
         L.lpa = off;
         off = align256(off + npairs * (na + 1) * 4);
         L.lpb = off;
@@ -392,6 +433,27 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form) {
 
 }  // namespace
 
+// Contraction slices for the large MFMA kernel: enough workgroups to fill the device
+// (about four per CU), slices of at least 128 steps, and at most 2047 steps per slice.
+struct MfmaPlan {
+    u64 ngroups;
+    u32 nslices;
+};
+static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
+    constexpr int NW = 2;
+    const u64 P = na + nb;
+    const u64 nWb = (P + 255) / 256;
+    MfmaPlan mp{(nWb + 4 * NW - 1) / (4 * NW), 1};
+    const u64 steps = (8 * nb + 62) / 64 + 1;
+    const u64 blocks = mp.ngroups * npairs;
+    const u64 target = (u64)std::max(1, ctx->num_cu) * 4;
+    u64 S = 1;
+    if (blocks < target) S = std::min<u64>((target + blocks - 1) / blocks, (steps + 127) / 128);
+    S = std::max<u64>(S, (steps + 2046) / 2047);
+    mp.nslices = (u32)std::max<u64>(1, S);
+    return mp;
+}
+
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
     if (form != BN_MUL_AUTO) return form;
     return (i64)std::min(na, nb) >= ctx->tune.mul_crossover_limbs ? BN_MUL_MFMA : BN_MUL_MAD;
@@ -401,7 +463,7 @@ size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int fo
     if (na == 0 || nb == 0 || npairs == 0) return 0;
     form = mul_pick_form(ctx, na, nb, form);
     if (na + nb <= 256) return 0;
-    return large_layout(na, nb, npairs, form).total;
+    return large_layout(na, nb, npairs, form, form == BN_MUL_MFMA && mfma_plan(ctx, na, nb, npairs).nslices > 1).total;
 }
 
 bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 na, u64 nb, u64 npairs, int form,
@@ -428,7 +490,9 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         return bn_launch_status();
     }
     if (form == BN_MUL_MAD && npairs > 65535) return BN_ERANGE;  // grid.y of the mad product kernel
-    const LargeLayout L = large_layout(na, nb, npairs, form);
+    const MfmaPlan mp = mfma_plan(ctx, na, nb, npairs);
+    const bool split = form == BN_MUL_MFMA && mp.nslices > 1;
+    const LargeLayout L = large_layout(na, nb, npairs, form, split);
     bn_status st = bn_ensure(ctx, ctx->work, L.total, s);
     if (st != BN_OK) return st;
     char *ws = static_cast<char *>(ctx->work.ptr);
@@ -442,7 +506,15 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         if ((st = launch_fill_u64(colLo, (L.colHi - L.colLo) / 8 + npairs * 2 * P, 0, s)) != BN_OK) return st;
         constexpr int Q = 8;
         const u64 ncb = (2 * P + 64 * Q - 1) / (64 * Q);
-        const u32 XC = (u32)ctx->tune.mad_xchunk;
+        // digits of a per work item: the tuned slice, smaller when there are too few
+        // items to give every SIMD several waves
+        u32 XC = (u32)ctx->tune.mad_xchunk;
+        const u64 want = (u64)std::max(1, ctx->num_cu) * 32;
+        const u64 per_slice = ncb * npairs;
+        if (per_slice * ((2 * na + XC - 1) / XC) < want) {
+            const u64 nx_wanted = (want + per_slice - 1) / per_slice;
+            XC = (u32)std::max<u64>(256, ((2 * na + nx_wanted - 1) / nx_wanted + 63) / 64 * 64);
+        }
         const u64 nxc = (2 * na + XC - 1) / XC;
         const u64 nitems = ncb * nxc;
         const u64 blocks = (nitems + 3) / 4;
@@ -458,19 +530,22 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         hipLaunchKernelGGL(k_mfma_prep, dim3((u32)npairs), dim3(256), 0, s, a, b, na, nb, lpa, lpb);
         if ((st = bn_launch_status()) != BN_OK) return st;
         constexpr int NW = 2;
-        const bool wide = 8 * std::min(na, nb) > 131586;
         const u32 D = (u32)ctx->tune.mfma_chunk;
-        const u64 nWb = (P + 255) / 256;
-        const u64 ngroups = (nWb + 4 * NW - 1) / (4 * NW);
-        const u64 blocks = ngroups * npairs;
+        const u64 blocks = mp.ngroups * npairs * mp.nslices;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
         const size_t lds = (size_t)64 * (D + 3) + (size_t)80 * (128 * NW + D);
-        if (wide)
-            hipLaunchKernelGGL((k_mul_large_mfma<NW, true>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb,
-                               npairs, lpa, lpb, D, (u32)ngroups, LO, HS);
-        else
+        if (split) {
+            u64 *col = reinterpret_cast<u64 *>(ws + L.col64);
+            if ((st = launch_fill_u64(col, npairs * 8 * P, 0, s)) != BN_OK) return st;
+            hipLaunchKernelGGL((k_mul_large_mfma<NW, true>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb, npairs,
+                               lpa, lpb, D, (u32)mp.ngroups, mp.nslices, LO, HS, col);
+            if ((st = bn_launch_status()) != BN_OK) return st;
+            hipLaunchKernelGGL(k_fold_mfma_cols, dim3((u32)fold_blocks), dim3(256), 0, s, col, a, b, lpa, lpb, na, nb,
+                               total, LO, HS);
+        } else {
             hipLaunchKernelGGL((k_mul_large_mfma<NW, false>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb,
-                               npairs, lpa, lpb, D, (u32)ngroups, LO, HS);
+                               npairs, lpa, lpb, D, (u32)mp.ngroups, 1u, LO, HS, nullptr);
+        }
         if ((st = bn_launch_status()) != BN_OK) return st;
     }
     // deferred carry pass: r = LO + HS (1-bit carries), segments of P limbs

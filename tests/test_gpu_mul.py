@@ -230,3 +230,24 @@ def test_mul_errors(bnctx):
     bn.bn_mul(bnctx, r, z, t[0:5])                     # 0 limbs x 5 limbs = 0 (5 limbs)
     torch.cuda.synchronize()
     assert (H(r) == 0).all()
+
+
+@pytest.mark.parametrize("form", ["mfma", "mad"])
+def test_beyond_single_range_bound(bnctx, form):
+    """min(na, nb) > 16448 limbs: a column can hold more than 131586 digit products, so
+    the MFMA form must cut the contraction into slices of at most 2047 steps.  Includes
+    the zero x zero pair (every signed digit product is +2^14) and all-ones."""
+    n = 16500
+    g = np.random.default_rng(77)
+    a = np.concatenate([np.zeros(n, np.uint64), np.full(n, 2 ** 64 - 1, np.uint64), _rand(g, n)])
+    b = np.concatenate([np.zeros(n, np.uint64), np.full(n, 2 ** 64 - 1, np.uint64), _rand(g, n)])
+    _check(bnctx, a, b, n, n, 3, form)
+
+
+@pytest.mark.parametrize("form", ["mfma", "mad"])
+@pytest.mark.parametrize("na,nb", [(16384, 16384), (8192, 8192), (20000, 1000)])
+def test_single_large_pair(bnctx, form, na, nb):
+    """One pair: the launch has few column groups, so the contraction is split across
+    workgroups (MFMA) or into small slices (mad)."""
+    g = np.random.default_rng(na + nb)
+    _check(bnctx, _rand(g, na), _rand(g, nb), na, nb, 1, form)
