@@ -180,6 +180,24 @@ __device__ __forceinline__ v4i toeplitz_frag(const u32 *__restrict__ lds_words, 
     return t;
 }
 
+// The same fragment in two halves, so that the LDS reads of the next step can be
+// issued before the current step's MFMAs: load the five words, combine later.
+struct TWords {
+    u32 w0, w1, w2, w3, w4;
+};
+__device__ __forceinline__ TWords toeplitz_words(const u32 *__restrict__ lds_words, u32 off) {
+    const u32 q = off >> 2;
+    return TWords{lds_words[q], lds_words[q + 1], lds_words[q + 2], lds_words[q + 3], lds_words[q + 4]};
+}
+__device__ __forceinline__ v4i toeplitz_combine(const TWords &t, u32 s) {
+    v4i f;
+    f.x = (int)__builtin_amdgcn_alignbyte(t.w1, t.w0, s);
+    f.y = (int)__builtin_amdgcn_alignbyte(t.w2, t.w1, s);
+    f.z = (int)__builtin_amdgcn_alignbyte(t.w3, t.w2, s);
+    f.w = (int)__builtin_amdgcn_alignbyte(t.w4, t.w3, s);
+    return f;
+}
+
 // Accumulator element (reg g of lane l) -> (row rr, column x) of the 32x32 tile.
 __device__ __forceinline__ u32 acc_row(int g, int lane) { return (u32)((g & 3) + 4 * (lane >> 5) + 8 * (g >> 2)); }
 

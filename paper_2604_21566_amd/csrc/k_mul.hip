@@ -219,7 +219,8 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
     extern __shared__ u64 lds[];
     u64 *bz = lds;                     // 8 (D + 3) words of signed b digits
     u64 *az = lds + 8 * ((u64)D + 3);  // (128 NW + D) chunk slots of reversed signed a digits
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar branches below
     const u32 x = lane & 31, h = lane >> 5;
     // block -> (slice, group, pair); groups in decreasing-work order
     const u64 slice = SPLIT ? blockIdx.x % nslices : 0;
@@ -285,26 +286,53 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
         __syncthreads();
         const i64 dlo = std::max(d0, wlo), dhi = std::min(d1, whi);
         if (dlo <= dhi) {
-            v4i f0 = toeplitz_frag(bz32, (u32)(64 * (dlo - d0)) + x + 1 + 16 * h);
+            // Software-pipelined: the LDS reads of step d+1 are issued before the MFMAs
+            // of step d.  The byte shift is the same for every fragment of a lane.
+            const u32 sh = (x + 1) & 3u;
+            const u32 lane_off = x + 1 + 16 * h;
+            u32 ob = (u32)(64 * (dlo - d0)) + lane_off;
+            v4i f0 = toeplitz_combine(toeplitz_words(bz32, ob), sh);
+            v4i f1 = toeplitz_combine(toeplitz_words(bz32, ob + 32), sh);
+            v4i f2 = toeplitz_combine(toeplitz_words(bz32, ob + 64), sh);
+            v4i A0[NW], A1[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const i64 slot = 32 * (wb0 + (i64)wave * NW + i) + (i64)x - dlo - cbase;
+                const u64 *sp = az + AZ_SLOT_U64 * std::max<i64>(0, slot);
+                A0[i] = *reinterpret_cast<const v4i *>(sp + 2 * h);
+                A1[i] = *reinterpret_cast<const v4i *>(sp + 4 + 2 * h);
+            }
             for (i64 d = dlo; d <= dhi; ++d) {
-                const u32 ob = (u32)(64 * (d - d0)) + x + 1 + 16 * h;
-                const v4i f1 = toeplitz_frag(bz32, ob + 32);
-                const v4i f2 = toeplitz_frag(bz32, ob + 64);
+                // prefetch step d+1 (clamped to the last step: its loads stay in range)
+                const i64 dn = d < dhi ? d + 1 : d;
+                const u32 on = (u32)(64 * (dn - d0)) + lane_off;
+                const TWords t1 = toeplitz_words(bz32, on + 32);
+                const TWords t2 = toeplitz_words(bz32, on + 64);
+                v4i A0n[NW], A1n[NW];
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    const i64 slot = 32 * (wb0 + (i64)wave * NW + i) + (i64)x - dn - cbase;
+                    const u64 *sp = az + AZ_SLOT_U64 * std::max<i64>(0, slot);
+                    A0n[i] = *reinterpret_cast<const v4i *>(sp + 2 * h);
+                    A1n[i] = *reinterpret_cast<const v4i *>(sp + 4 + 2 * h);
+                }
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
                     if (d >= blo[i] && d <= bhi[i]) {
-                        const i64 wb = wb0 + (i64)wave * NW + i;
-                        const i64 slot = 32 * wb + (i64)x - d - cbase;
-                        const u64 *sp = az + AZ_SLOT_U64 * slot;
-                        const v4i A0 = *reinterpret_cast<const v4i *>(sp + 2 * h);
-                        const v4i A1 = *reinterpret_cast<const v4i *>(sp + 4 + 2 * h);
-                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, A0, acc[i][0], 0, 0, 0);
-                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A0, acc[i][1], 0, 0, 0);
-                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A1, acc[i][0], 0, 0, 0);
-                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, A1, acc[i][1], 0, 0, 0);
+                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, A0[i], acc[i][0], 0, 0, 0);
+                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A0[i], acc[i][1], 0, 0, 0);
+                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A1[i], acc[i][0], 0, 0, 0);
+                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, A1[i], acc[i][1], 0, 0, 0);
                     }
                 }
                 f0 = f2;
+                f1 = toeplitz_combine(t1, sh);
+                f2 = toeplitz_combine(t2, sh);
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    A0[i] = A0n[i];
+                    A1[i] = A1n[i];
+                }
             }
         }
     }
@@ -447,10 +475,16 @@ static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
     const u64 steps = (8 * nb + 62) / 64 + 1;
     const u64 blocks = mp.ngroups * npairs;
     const u64 target = (u64)std::max(1, ctx->num_cu) * 4;
+    // digit products in a column: at most the shorter operand's digit count
+    const u64 maxcnt = 8 * std::min(na, nb);
     u64 S = 1;
-    if (blocks < target) S = std::min<u64>((target + blocks - 1) / blocks, (steps + 127) / 128);
-    S = std::max<u64>(S, (steps + 2046) / 2047);
-    mp.nslices = (u32)std::max<u64>(1, S);
+    if (blocks < target) S = std::max<u64>(1, std::min<u64>((target + blocks - 1) / blocks, (steps + 127) / 128));
+    // a slice sum is added to the workspace as a plain int32: |sum| <= 2^14 cnt must stay
+    // below 2^31, so slices longer than 2047 steps need cnt <= 131071
+    if (S > 1 && maxcnt > 131071) S = std::max<u64>(S, (steps + 2046) / 2047);
+    // an unsplit launch decodes its int32 sums exactly while cnt <= 131586
+    if (S == 1 && maxcnt > 131586) S = std::max<u64>(2, (steps + 2046) / 2047);
+    mp.nslices = (u32)S;
     return mp;
 }
 
