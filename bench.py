@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tuning", default=None, help="tuning JSON written by bn_autotune")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 512 MiB device-to-device copy 3 times (the known-size reference "
+                         "for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this library has no multi-GPU path",
@@ -117,6 +120,10 @@ def main():
     def sub():
         bn.bn_sub_n_batch(ctx, tr, sa, sb, n, npairs, tc)
 
+    if args.calibrate:
+        for _ in range(3):
+            tr.copy_(ta)
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         add()
         sub()

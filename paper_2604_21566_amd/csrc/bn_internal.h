@@ -46,7 +46,7 @@ struct Tuning {
     i64 mul_crossover_limbs = 256;     // BN_MUL_AUTO: MFMA when min(na, nb) >= this
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
-    int mfma_chunk = 128;              // Toeplitz steps staged in LDS per round (<= 2047, int32 bound)
+    int mfma_chunk = 256;              // Toeplitz steps staged in LDS per round (<= 2047, int32 bound)
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
 };

@@ -316,14 +316,20 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
                     A0n[i] = *reinterpret_cast<const v4i *>(sp + 2 * h);
                     A1n[i] = *reinterpret_cast<const v4i *>(sp + 4 + 2 * h);
                 }
+                // Every block of the wave runs every step of the wave's range: outside a
+                // block's own range its a chunks are zero-padded in LDS, so those MFMAs
+                // add zero.  No branches around MFMAs (the compiler would copy the
+                // accumulators); independent accumulators sit between the two MFMAs that
+                // update the same one.
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
-                    if (d >= blo[i] && d <= bhi[i]) {
-                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, A0[i], acc[i][0], 0, 0, 0);
-                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A0[i], acc[i][1], 0, 0, 0);
-                        acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A1[i], acc[i][0], 0, 0, 0);
-                        acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, A1[i], acc[i][1], 0, 0, 0);
-                    }
+                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, A0[i], acc[i][0], 0, 0, 0);
+                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A0[i], acc[i][1], 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A1[i], acc[i][0], 0, 0, 0);
+                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, A1[i], acc[i][1], 0, 0, 0);
                 }
                 f0 = f2;
                 f1 = toeplitz_combine(t1, sh);
