@@ -118,41 +118,82 @@ __global__ void k_fold_mad(const u64 *__restrict__ colLo, const u64 *__restrict_
 }
 
 // ---------------------------------------------------------- large: MFMA form ----
-// Per pair: per-limb digit-sum prefix tables of a and b (for the unsigned-sum
-// corrections of the fold).  One workgroup per pair.
-__device__ void block_prefix_digits(const u64 *__restrict__ limbs, u64 n, u32 *__restrict__ lp, u32 *sh) {
-    const u32 tid = threadIdx.x, nt = blockDim.x;
-    const u64 per = (n + nt - 1) / nt;
-    const u64 lo = std::min<u64>(n, tid * per), hi = std::min<u64>(n, lo + per);
-    u32 s = 0;
-    for (u64 k = lo; k < hi; ++k) s += bytesum64(limbs[k]);
-    sh[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-        u32 run = 0;
-        for (u32 i = 0; i < nt; ++i) {
-            const u32 v = sh[i];
-            sh[i] = run;
-            run += v;
-        }
+// Per-limb digit-sum prefix tables lp[k] = sum of the digits of limbs [0, k) of every
+// operand of the batch (for the unsigned-sum corrections of the fold).  Two small
+// kernels over segments of PREP_SEG limbs: segment totals, then each segment adds
+// the totals before it and scans its own limbs in the workgroup.
+constexpr u32 PREP_SEG = 1024;  // limbs per segment: 256 threads x 4 limbs
+
+__device__ __forceinline__ const u64 *prep_operand(const u64 *a, const u64 *b, u64 na, u64 nb, u64 op_pair, u64 &n,
+                                                   u32 *lpa, u32 *lpb, u32 *&lp) {
+    const u64 pair = op_pair >> 1;
+    if (op_pair & 1) {
+        n = nb;
+        lp = lpb + pair * (nb + 1);
+        return b + pair * nb;
     }
-    __syncthreads();
-    u32 run = sh[tid];
-    for (u64 k = lo; k < hi; ++k) {
-        lp[k] = run;
-        run += bytesum64(limbs[k]);
-    }
-    if (hi == n && lo < hi) lp[n] = run;
-    if (n == 0 && tid == 0) lp[0] = 0;
-    __syncthreads();
+    n = na;
+    lp = lpa + pair * (na + 1);
+    return a + pair * na;
 }
 
-__global__ __launch_bounds__(256) void k_mfma_prep(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                   u64 nb, u32 *__restrict__ lpa, u32 *__restrict__ lpb) {
-    __shared__ u32 sh[256];
-    const u64 p = blockIdx.x;
-    block_prefix_digits(a + p * na, na, lpa + p * (na + 1), sh);
-    block_prefix_digits(b + p * nb, nb, lpb + p * (nb + 1), sh);
+__global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
+                                                     u64 nb, u32 *__restrict__ lpa, u32 *__restrict__ lpb,
+                                                     u32 *__restrict__ seg_tot, u32 nseg) {
+    __shared__ u32 sh[4];
+    u64 n;
+    u32 *lp;
+    const u64 *x = prep_operand(a, b, na, nb, blockIdx.y, n, lpa, lpb, lp);
+    const u64 base = (u64)blockIdx.x * PREP_SEG + 4 * (u64)threadIdx.x;
+    u32 sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) sum += bytesum64(x[base + k]);
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) seg_tot[(u64)blockIdx.y * nseg + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
+                                                   u64 nb, u32 *__restrict__ lpa, u32 *__restrict__ lpb,
+                                                   const u32 *__restrict__ seg_tot, u32 nseg) {
+    __shared__ u32 sh[4], shp[4];
+    u64 n;
+    u32 *lp;
+    const u64 *x = prep_operand(a, b, na, nb, blockIdx.y, n, lpa, lpb, lp);
+    const u64 seg0 = (u64)blockIdx.x * PREP_SEG;
+    if (seg0 >= n && !(n == 0 && blockIdx.x == 0)) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // digits of all earlier segments (strided over the workgroup, then reduced)
+    u32 pre = 0;
+    for (u32 s2 = threadIdx.x; s2 < blockIdx.x; s2 += 256) pre += seg_tot[(u64)blockIdx.y * nseg + s2];
+    for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
+    if (lane == 0) shp[w] = pre;
+    const u64 base = seg0 + 4 * (u64)threadIdx.x;
+    u32 v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < n ? bytesum64(x[base + k]) : 0u;
+        sum += v[k];
+    }
+    // exclusive scan of the per-thread sums over the workgroup
+    u32 inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const u32 t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    u32 run = shp[0] + shp[1] + shp[2] + shp[3] + inc - sum;
+    for (int i = 0; i < w; ++i) run += sh[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) lp[base + k] = run;
+        run += v[k];
+        if (base + k + 1 == n) lp[n] = run;
+    }
+    if (n == 0 && threadIdx.x == 0) lp[0] = 0;
 }
 
 // k-th group in decreasing-work order when work over groups [0, n) is symmetric and
@@ -433,7 +474,7 @@ __global__ void k_fold_mfma_cols(const u64 *__restrict__ col, const u64 *__restr
 
 // ---------------------------------------------------------------- workspace ----
 struct LargeLayout {
-    size_t colLo, colHi, col64, lpa, lpb, LO, HS, total;
+    size_t colLo, colHi, col64, lpa, lpb, seg, LO, HS, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -456,6 +497,8 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, bool split
         off = align256(off + npairs * (na + 1) * 4);
         L.lpb = off;
         off = align256(off + npairs * (nb + 1) * 4);
+        L.seg = off;
+        off = align256(off + npairs * 2 * ((std::max(na, nb) + PREP_SEG - 1) / PREP_SEG + 1) * 4);
     }
     L.LO = off;
     off = align256(off + npairs * P * 8);
@@ -544,7 +587,7 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         u64 *colLo = reinterpret_cast<u64 *>(ws + L.colLo);
         u64 *colHi = reinterpret_cast<u64 *>(ws + L.colHi);
         if ((st = launch_fill_u64(colLo, (L.colHi - L.colLo) / 8 + npairs * 2 * P, 0, s)) != BN_OK) return st;
-        constexpr int Q = 8;
+        constexpr int Q = 16;
         const u64 ncb = (2 * P + 64 * Q - 1) / (64 * Q);
         // digits of a per work item: the tuned slice, smaller when there are too few
         // items to give every SIMD several waves
@@ -567,7 +610,14 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
     } else {
         u32 *lpa = reinterpret_cast<u32 *>(ws + L.lpa);
         u32 *lpb = reinterpret_cast<u32 *>(ws + L.lpb);
-        hipLaunchKernelGGL(k_mfma_prep, dim3((u32)npairs), dim3(256), 0, s, a, b, na, nb, lpa, lpb);
+        u32 *seg = reinterpret_cast<u32 *>(ws + L.seg);
+        const u32 nseg = (u32)((std::max(na, nb) + PREP_SEG - 1) / PREP_SEG);
+        if (2 * npairs > 65535) return BN_ERANGE;
+        hipLaunchKernelGGL(k_prep_totals, dim3(nseg, (u32)(2 * npairs)), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
+                           nseg);
+        if ((st = bn_launch_status()) != BN_OK) return st;
+        hipLaunchKernelGGL(k_prep_scan, dim3(nseg, (u32)(2 * npairs)), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
+                           nseg);
         if ((st = bn_launch_status()) != BN_OK) return st;
         constexpr int NW = 2;
         const u32 D = (u32)ctx->tune.mfma_chunk;
