@@ -14,7 +14,6 @@ crossover.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,14 +33,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("k_addsub.hip", "bn_internal.h"):
-        with open(os.path.join(ROOT, "paper_2604_21566_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(per_launch_bytes_alg: float):
     """HBM bytes per launch of the scan kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
@@ -52,6 +43,7 @@ def measured_traffic(per_launch_bytes_alg: float):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
+    from paper_2604_21566_amd.rocprof_summary import kernel_source_hash
     if vals.get("kernel_src_sha") != kernel_source_hash():
         return None
     try:

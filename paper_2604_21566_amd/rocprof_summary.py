@@ -1,8 +1,33 @@
-"""Turn a rocprofv3 results database into a short per-kernel text summary (the files
-under profiles/).  Usage: python -m paper_2604_21566_amd.rocprof_summary <results.db> "<command>" > out.txt"""
+"""Short text summaries of rocprofv3 output (the files under profiles/).
+
+  python -m paper_2604_21566_amd.rocprof_summary <results.db> "<command>" > out.txt
+      per-kernel durations from a --kernel-trace --stats run
+  python -m paper_2604_21566_amd.rocprof_summary traffic <fetch.csv> <write.csv> "<fetch cmd>" "<write cmd>" > out.txt
+      HBM bytes per launch of the add/sub scan kernel on the batched workload
+      (2^20 pairs x 64 limbs) from one FETCH_SIZE and one WRITE_SIZE --pmc run of
+      `bench.py --calibrate`, each scaled by what the counter reads for the 512 MiB
+      device-to-device copies that run makes
+"""
+import csv
+import hashlib
+import os
 import re
 import sqlite3
 import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+COPY_BYTES = 512 << 20
+C2_PAIRS, C2_LIMBS = 1 << 20, 64
+
+
+def kernel_source_hash() -> str:
+    """Hash of the scan kernel's sources: a counter summary is valid only for the
+    source it was taken on."""
+    h = hashlib.sha256()
+    for f in ("k_addsub.hip", "bn_internal.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def short(name: str) -> str:
@@ -26,5 +51,57 @@ def main(db, cmd):
               f"{100*tot/total:6.2f} {vg:5d} {ag:5d} {lds:6d} {gx:9d} {wg:4d}")
 
 
+def _counter_rows(path):
+    with open(path, newline="") as fh:
+        return [(r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])) for r in csv.DictReader(fh)]
+
+
+def traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
+    F, W = _counter_rows(fetch_csv), _counter_rows(write_csv)
+    copy_kib = COPY_BYTES / 1024
+
+    def split(rows):
+        # the calibration copies are the three largest rocclr copy dispatches
+        copies = sorted((v for n, g, v in rows if "copyBuffer" in n), reverse=True)[:3]
+        scans = [v for n, g, v in rows if "k_flat_scan" in n]
+        names = sorted({re.sub(r"\(anonymous namespace\)::", "", n).split("(")[0] for n, g, v in rows
+                        if "k_flat_scan" in n})
+        return copies, scans, names
+
+    fc, fs, names = split(F)
+    wc, ws, _ = split(W)
+    if len(fc) < 3 or len(wc) < 3 or not fs or not ws:
+        raise SystemExit("counter files lack the calibration copies or the scan dispatches")
+    fcm, wcm = sum(fc) / len(fc), sum(wc) / len(wc)
+    fscale, wscale = copy_kib / fcm, copy_kib / wcm
+    fm, wm = sum(fs) / len(fs), sum(ws) / len(ws)
+    fb, wb = fm * 1024 * fscale, wm * 1024 * wscale
+    alg = C2_PAIRS * C2_LIMBS * 24 + C2_PAIRS * 8
+    print("# HBM traffic of the add/sub scan kernel on the batched workload (2^20 pairs x 64 limbs)")
+    print("# commands (run from the repository root on the GPU box):")
+    print(f"#   {fetch_cmd}")
+    print(f"#   {write_cmd}")
+    print("#   python -m paper_2604_21566_amd.rocprof_summary traffic <fetch csv> <write csv> ...")
+    print("# Counter values are KiB per dispatch.  Calibration: --calibrate runs three plain")
+    print("# device-to-device copies of 512 MiB (524288 KiB read and 524288 KiB written); the")
+    print("# counters for those copies give the scale factors below.")
+    print(f"copy_fetch_kib_measured = {fcm:.1f}")
+    print(f"copy_write_kib_measured = {wcm:.1f}")
+    print(f"fetch_scale = {fscale:.5f}")
+    print(f"write_scale = {wscale:.5f}")
+    print(f"scan_dispatches = {len(fs)} ({', '.join(names)})")
+    print(f"scan_fetch_kib_measured = {fm:.1f}  (min {min(fs):.1f}, max {max(fs):.1f})")
+    print(f"scan_write_kib_measured = {wm:.1f}  (min {min(ws):.1f}, max {max(ws):.1f})")
+    print(f"scan_fetch_bytes = {fb:.4e}")
+    print(f"scan_write_bytes = {wb:.4e}")
+    print(f"algorithmic_bytes_per_launch = {alg:.4e}  (24 B per limb + 8 B per pair)")
+    print(f"traffic_over_algorithmic = {(fb + wb) / alg:.4f}")
+    print(f"traffic_bytes_per_launch = {fb + wb:.6e}")
+    print(f"kernel_src_sha = {kernel_source_hash()}")
+
+
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2])
+    if sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:6])
+    else:
+        main(sys.argv[1], sys.argv[2])
