@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tuning", default=None, help="tuning JSON written by bn_autotune")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated secondary workloads to run alone (copy,c1,c3,c4,c5,crossover); "
+                         "prints their figures only, for profiling runs")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy 3 times (the known-size reference "
                          "for scaling HBM byte counters)")
@@ -94,6 +97,11 @@ def main():
     if args.tuning:
         bn.bn_load_tuning(ctx, args.tuning)
     D = bn.to_device
+    if args.only:
+        res = extra_workloads(ctx, bn, wl, torch, only=set(args.only.split(",")))
+        bn.bn_destroy(ctx)
+        print(json.dumps({"workloads": res}), flush=True)
+        return
 
     # ------------------------------------------------------------ headline: c2 add + sub
     n, npairs = 64, 1 << 20
@@ -152,25 +160,12 @@ def main():
     # ------------------------------------------------------------ CPU oracle baseline (same workload)
     cpu = None
     if not args.no_cpu:
-        import oracle
-        log("timing the CPU oracle on the full c2 batch (add + sub, one thread)")
-        oracle._load()
-        reps = 0
-        t0 = time.perf_counter()
-        while True:
-            oracle.add_batch(a_add, b_add, n)
-            oracle.sub_batch(a_sub, b_sub, n)
-            reps += 1
-            if time.perf_counter() - t0 > 10.0 or reps >= 20:
-                break
-        dt = (time.perf_counter() - t0) / reps
-        cpu = {"value": 2 * bytes_per_launch / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"full 2^20 x 64-limb batch, add + sub, {reps} repetitions, one thread",
-               "ms_per_step": dt * 1e3}
+        cpu = cpu_oracle_baseline(a_add, b_add, a_sub, b_sub, n, npairs, bytes_per_launch)
     del a_sub, b_sub, sa, sb
 
     if not args.quick:
         workloads.update(extra_workloads(ctx, bn, wl, torch))
+        workloads["c2_addsub"]["frac_of_measured_copy"] = achieved / workloads["hbm_copy_GBps"]
 
     bn.bn_destroy(ctx)
     out = {
@@ -196,105 +191,229 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extra_workloads(ctx, bn, wl, torch):
+def host_threads() -> int:
+    """Host cores this process may use (at most 16, the CPU share of one GPU)."""
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_oracle_baseline(a_add, b_add, a_sub, b_sub, n, npairs, bytes_per_launch):
+    """The CPU oracle on the same 2^20 x 64-limb add + sub step: pairs split into
+    contiguous chunks, one oracle call per chunk on a pool of threads (the oracle's
+    C loops run without the interpreter lock), and once more on one thread."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle._load()
+    threads = host_threads()
+    bounds = np.linspace(0, npairs, threads + 1).astype(np.int64)
+
+    def step(pool):
+        if pool is None:
+            oracle.add_batch(a_add, b_add, n)
+            oracle.sub_batch(a_sub, b_sub, n)
+            return
+        jobs = []
+        for f, x, y in ((oracle.add_batch, a_add, b_add), (oracle.sub_batch, a_sub, b_sub)):
+            for p0, p1 in zip(bounds[:-1], bounds[1:]):
+                jobs.append(pool.submit(f, x[p0 * n:p1 * n], y[p0 * n:p1 * n], n))
+        for j in jobs:
+            j.result()
+
+    def timed(pool, budget_s, max_reps):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            step(pool)
+            reps += 1
+            if time.perf_counter() - t0 > budget_s or reps >= max_reps:
+                return (time.perf_counter() - t0) / reps, reps
+
+    log(f"timing the CPU oracle on the full c2 batch (add + sub), {threads} threads and one thread")
+    with ThreadPoolExecutor(threads) as pool:
+        step(pool)
+        dt_mt, reps_mt = timed(pool, 8.0, 40)
+    dt_1, reps_1 = timed(None, 8.0, 20)
+    return {"value": 2 * bytes_per_launch / dt_mt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"full 2^20 x 64-limb batch, add + sub, {reps_mt} repetitions, pairs split over "
+                      f"{threads} threads",
+            "ms_per_step": dt_mt * 1e3,
+            "one_thread": {"value": 2 * bytes_per_launch / dt_1 / 1e9, "ms_per_step": dt_1 * 1e3,
+                           "repetitions": reps_1},
+            "host_cpu": host_cpu_model()}
+
+
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def extra_workloads(ctx, bn, wl, torch, only=None):
+    """Secondary workloads (all, or those named in `only`)."""
     D = bn.to_device
     res = {}
+    s = torch.cuda.Stream()
+
+    # ---- measured HBM reference: a plain 512 MiB device-to-device copy
+    if only is None or "copy" in only:
+        src = torch.empty(1 << 26, dtype=torch.int64, device="cuda").random_()
+        dst = torch.empty_like(src)
+        ms, _ = gpu_time(lambda: dst.copy_(src), 20, 3)
+        res["hbm_copy_GBps"] = 2.0 * src.numel() * 8 / (ms * 1e-3) / 1e9
+        del src, dst
 
     # ---- c1: 1088 pairs of 4 limbs, graph replay (latency)
-    log("c1")
-    c1 = {}
-    s = torch.cuda.Stream()
-    for op in ("add", "sub", "mul_mad", "mul_mfma"):
-        a, b = wl.c1("sub" if op == "sub" else "add")
-        ta, tb = D(a), D(b)
-        if op.startswith("mul"):
-            tr = torch.empty(1088 * 8, dtype=torch.int64, device="cuda")
-            g = bn.bn_graph_capture_batch(ctx, 2, tr, ta, tb, 4, 4, 1088, None, op[4:], s)
-        else:
-            tr = torch.empty(1088 * 4, dtype=torch.int64, device="cuda")
-            tc = torch.empty(1088, dtype=torch.int64, device="cuda")
-            g = bn.bn_graph_capture_batch(ctx, 0 if op == "add" else 1, tr, ta, tb, 4, 0, 1088, tc, 0, s)
-        with torch.cuda.stream(s):
-            ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 50, 5)
-        bn.bn_graph_destroy(g)
-        c1[op + "_us"] = ms * 1e3
-        c1[op + "_pairs_per_s"] = 1088 / (ms * 1e-3)
-    res["c1"] = c1
+    if only is None or "c1" in only:
+        log("c1")
+        c1 = {}
+        for op in ("add", "sub", "mul_mad", "mul_mfma"):
+            a, b = wl.c1("sub" if op == "sub" else "add")
+            ta, tb = D(a), D(b)
+            if op.startswith("mul"):
+                tr = torch.empty(1088 * 8, dtype=torch.int64, device="cuda")
+                g = bn.bn_graph_capture_batch(ctx, 2, tr, ta, tb, 4, 4, 1088, None, op[4:], s)
+            else:
+                tr = torch.empty(1088 * 4, dtype=torch.int64, device="cuda")
+                tc = torch.empty(1088, dtype=torch.int64, device="cuda")
+                g = bn.bn_graph_capture_batch(ctx, 0 if op == "add" else 1, tr, ta, tb, 4, 0, 1088, tc, 0, s)
+            with torch.cuda.stream(s):
+                ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 50, 5)
+            bn.bn_graph_destroy(g)
+            c1[op + "_us"] = ms * 1e3
+            c1[op + "_pairs_per_s"] = 1088 / (ms * 1e-3)
+            # the same call launched directly
+            if op.startswith("mul"):
+                fn = lambda: bn.bn_mul_n_batch(ctx, tr, ta, tb, 4, 4, 1088, op[4:])
+            else:
+                f = bn.bn_add_n_batch if op == "add" else bn.bn_sub_n_batch
+                fn = lambda: f(ctx, tr, ta, tb, 4, 1088, tc)
+            ms, _ = gpu_time(fn, 50, 5)
+            c1[op + "_direct_us"] = ms * 1e3
+        res["c1"] = c1
 
     # ---- c3: one pair of 2^26 limbs (random with runs, and the all-propagate worst case)
-    log("c3")
-    c3 = {}
-    n3 = 1 << 26
-    tr = torch.empty(n3, dtype=torch.int64, device="cuda")
-    tc = torch.empty(1, dtype=torch.int64, device="cuda")
-    for op in ("add", "sub"):
-        for worst in (False, True):
-            a, b = wl.c3(op, n=n3, worst=worst)
-            ta, tb = D(a), D(b)
-            f = bn.bn_add if op == "add" else bn.bn_sub
-            ms, _ = gpu_time(lambda: f(ctx, tr, ta, tb, tc), 10, 2)
-            c3[f"{op}{'_worst' if worst else ''}_GBps"] = 24.0 * n3 / (ms * 1e-3) / 1e9
-            del ta, tb
-    res["c3"] = c3
+    if only is None or "c3" in only:
+        log("c3")
+        c3 = {}
+        n3 = 1 << 26
+        tr = torch.empty(n3, dtype=torch.int64, device="cuda")
+        tc = torch.empty(1, dtype=torch.int64, device="cuda")
+        for op in ("add", "sub"):
+            for worst in (False, True):
+                a, b = wl.c3(op, n=n3, worst=worst)
+                ta, tb = D(a), D(b)
+                f = bn.bn_add if op == "add" else bn.bn_sub
+                ms, _ = gpu_time(lambda: f(ctx, tr, ta, tb, tc), 10, 2)
+                key = f"{op}{'_worst' if worst else ''}"
+                c3[key + "_GBps"] = 24.0 * n3 / (ms * 1e-3) / 1e9
+                # look-back distances of one more (untimed) run
+                bn.bn_lookback_stats(ctx)
+                bn.bn_set_param(ctx, "debug.flags", 2)
+                f(ctx, tr, ta, tb, tc)
+                h = bn.bn_lookback_stats(ctx)
+                bn.bn_set_param(ctx, "debug.flags", 0)
+                top = max([k for k, v in enumerate(h) if v] or [0])
+                c3[key + "_lookback_hist_log2"] = h[:top + 1]
+                del ta, tb
+        res["c3"] = c3
 
     # ---- c4: 2^16 ragged products, persistent launch captured in a graph
-    log("c4")
-    a, b, desc, rsz = wl.c4()
-    work = float((desc[:, 3].astype(np.float64) * desc[:, 4].astype(np.float64)).sum())
-    ta, tb = D(a), D(b)
-    tr = torch.empty(rsz, dtype=torch.int64, device="cuda")
-    c4 = {"limb_products": work}
-    for form in ("mad", "mfma", "auto"):
-        plan = bn.bn_plan_mul_ragged(ctx, desc, form)
-        g = bn.bn_graph_capture_mul_ragged(ctx, plan, tr, ta, tb, s)
-        with torch.cuda.stream(s):
-            ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 10, 2)
-        bn.bn_graph_destroy(g)
+    if only is None or "c4" in only:
+        log("c4")
+        a, b, desc, rsz = wl.c4()
+        work = float((desc[:, 3].astype(np.float64) * desc[:, 4].astype(np.float64)).sum())
+        ta, tb = D(a), D(b)
+        tr = torch.empty(rsz, dtype=torch.int64, device="cuda")
+        c4 = {"limb_products": work}
+        for form in ("mad", "mfma", "auto"):
+            plan = bn.bn_plan_mul_ragged(ctx, desc, form)
+            g = bn.bn_graph_capture_mul_ragged(ctx, plan, tr, ta, tb, s)
+            with torch.cuda.stream(s):
+                ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 10, 2)
+            bn.bn_graph_destroy(g)
+            bn.bn_plan_destroy(plan)
+            c4[f"{form}_ms"] = ms
+            c4[f"{form}_limb_products_per_s"] = work / (ms * 1e-3)
+            c4[f"{form}_pairs_per_s"] = len(desc) / (ms * 1e-3)
+        # the same batch launched directly (no graph)
+        plan = bn.bn_plan_mul_ragged(ctx, desc, "auto")
+        ms, _ = gpu_time(lambda: bn.bn_mul_ragged(ctx, plan, tr, ta, tb), 10, 2)
         bn.bn_plan_destroy(plan)
-        c4[f"{form}_ms"] = ms
-        c4[f"{form}_limb_products_per_s"] = work / (ms * 1e-3)
-        c4[f"{form}_pairs_per_s"] = len(desc) / (ms * 1e-3)
-    res["c4"] = c4
+        c4["auto_direct_ms"] = ms
+        # per size bucket (larger operand length in [lo, 2 lo)), each bucket its own graph
+        big = np.maximum(desc[:, 3], desc[:, 4])
+        buckets = {}
+        crossover = None
+        lo = 4
+        while lo <= 128:
+            sel = desc[(big >= lo) & (big < 2 * lo)] if lo < 128 else desc[big >= lo]
+            if len(sel):
+                w = float((sel[:, 3].astype(np.float64) * sel[:, 4].astype(np.float64)).sum())
+                row = {"pairs": int(len(sel)), "limb_products": w}
+                for form in ("mad", "mfma"):
+                    plan = bn.bn_plan_mul_ragged(ctx, sel, form)
+                    g = bn.bn_graph_capture_mul_ragged(ctx, plan, tr, ta, tb, s)
+                    with torch.cuda.stream(s):
+                        ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 10, 2)
+                    bn.bn_graph_destroy(g)
+                    bn.bn_plan_destroy(plan)
+                    row[f"{form}_us"] = ms * 1e3
+                    row[f"{form}_limb_products_per_s"] = w / (ms * 1e-3)
+                if row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"] and crossover is None:
+                    crossover = lo
+                buckets[f"{lo}-{2 * lo - 1 if lo < 128 else 128}"] = row
+            lo *= 2
+        c4["buckets_by_longer_operand_limbs"] = buckets
+        c4["mfma_faster_from_bucket"] = crossover
+        res["c4"] = c4
 
     # ---- c5: 64 products of 16384-limb operands
-    log("c5")
-    n5 = 16384
-    a, b = wl.c5()
-    ta, tb = D(a), D(b)
-    tr = torch.empty(64 * 2 * n5, dtype=torch.int64, device="cuda")
-    c5 = {"limb_products": 64.0 * n5 * n5}
-    for form in ("mad", "mfma"):
-        ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, tr, ta, tb, n5, n5, 64, form), 3, 1)
-        c5[f"{form}_ms"] = ms
-        c5[f"{form}_limb_products_per_s"] = 64.0 * n5 * n5 / (ms * 1e-3)
-        c5[f"{form}_products_per_s"] = 64 / (ms * 1e-3)
-    c5["mfma_int8_TOPS"] = 2 * 64.0 * 64.0 * n5 * n5 / (c5["mfma_ms"] * 1e-3) / 1e12
-    c5["mfma_frac_of_int8_peak"] = c5["mfma_int8_TOPS"] / INT8_PEAK_TOPS
-    c5["mfma_over_mad"] = c5["mad_ms"] / c5["mfma_ms"]
-    res["c5"] = c5
+    if only is None or "c5" in only:
+        log("c5")
+        n5 = 16384
+        a, b = wl.c5()
+        ta, tb = D(a), D(b)
+        tr = torch.empty(64 * 2 * n5, dtype=torch.int64, device="cuda")
+        c5 = {"limb_products": 64.0 * n5 * n5}
+        for form in ("mad", "mfma"):
+            ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, tr, ta, tb, n5, n5, 64, form), 3, 1)
+            c5[f"{form}_ms"] = ms
+            c5[f"{form}_limb_products_per_s"] = 64.0 * n5 * n5 / (ms * 1e-3)
+            c5[f"{form}_products_per_s"] = 64 / (ms * 1e-3)
+        c5["mfma_int8_TOPS"] = 2 * 64.0 * 64.0 * n5 * n5 / (c5["mfma_ms"] * 1e-3) / 1e12
+        c5["mfma_frac_of_int8_peak"] = c5["mfma_int8_TOPS"] / INT8_PEAK_TOPS
+        c5["mfma_over_mad"] = c5["mad_ms"] / c5["mfma_ms"]
+        res["c5"] = c5
 
     # ---- crossover sweep: square products, similar work per size
-    log("crossover sweep")
-    sweep = {}
-    crossover = None
-    n = 4
-    big = torch.empty(1 << 25, dtype=torch.int64, device="cuda").random_()
-    out = torch.empty(1 << 26, dtype=torch.int64, device="cuda")
-    while n <= 16384:
-        npairs = int(max(1, min(65535, (1 << 28) // (n * n), (1 << 25) // n)))
-        row = {}
-        for form in ("mad", "mfma"):
-            ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, out, big, big, n, n, npairs, form), 3, 1)
-            row[form + "_limb_products_per_s"] = npairs * n * n / (ms * 1e-3)
-        row["pairs"] = npairs
-        sweep[str(n)] = row
-        faster = row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"]
-        if faster and crossover is None:
-            crossover = n
-        elif not faster:
-            crossover = None
-        n *= 2
-    res["crossover"] = {"sweep": sweep, "mfma_faster_from_limbs": crossover}
+    if only is None or "crossover" in only:
+        log("crossover sweep")
+        sweep = {}
+        crossover = None
+        n = 4
+        big = torch.empty(1 << 25, dtype=torch.int64, device="cuda").random_()
+        out = torch.empty(1 << 26, dtype=torch.int64, device="cuda")
+        while n <= 16384:
+            npairs = int(max(1, min(65535, (1 << 28) // (n * n), (1 << 25) // n)))
+            row = {}
+            for form in ("mad", "mfma"):
+                ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, out, big, big, n, n, npairs, form), 3, 1)
+                row[form + "_limb_products_per_s"] = npairs * n * n / (ms * 1e-3)
+            row["pairs"] = npairs
+            sweep[str(n)] = row
+            faster = row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"]
+            if faster and crossover is None:
+                crossover = n
+            elif not faster:
+                crossover = None
+            n *= 2
+        res["crossover"] = {"sweep": sweep, "mfma_faster_from_limbs": crossover}
+
     res["lookback_self_help_latch"] = bn.bn_check(ctx)
     return res
 

@@ -83,6 +83,18 @@ size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npair
  * Returns BN_OK, or BN_EHIP if the stream reported an error. */
 bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags);
 
+/* Look-back distance histogram of the chained add/sub scans run since the last
+ * call, recorded only while "debug.flags" bit 1 is set (one atomic per tile).
+ * hist[k] (host array of nbins entries, nbins may be 0) receives the number of
+ * workgroup tiles whose carry-in was decided by a predecessor 2^k <= d < 2^(k+1)
+ * tiles back (d = 1: the nearest one had already published; reaching past the
+ * first tile of the operand counts as that tile's distance + 1).  Bins past
+ * BN_LOOKBACK_BINS read 0.  Waits for `stream`, then clears the histogram.
+ * Returns BN_EINVAL for a NULL ctx, or hist NULL with nbins > 0; BN_EHIP on a
+ * stream error. */
+#define BN_LOOKBACK_BINS 32
+bn_status bn_lookback_stats(bn_ctx *ctx, bn_stream stream, uint64_t *hist, size_t nbins);
+
 /* ------------------------------------------------------- add / subtract ---- */
 
 /* r = (a + b) mod 2^(64n); *carry_out = carry-out c_n in {0,1} (Theorem 1).
@@ -181,12 +193,13 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
  *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large
- *                                      MFMA kernel (<= 2047: 64 digit products of at most
- *                                      2^14 per step keep an int32 round sum exact)
+ *                                      MFMA kernel: even, 16..256
  *   "lookback.spin_limit"              look-back polls before a tile computes an
  *                                      unpublished predecessor's carry itself
  *   "debug.flags"                      bit 0: tile 0 never publishes its status
- *                                      (test hook for the self-computed look-back)
+ *                                      (test hook for the self-computed look-back);
+ *                                      bit 1: record look-back distances
+ *                                      (read with bn_lookback_stats)
  * Returns BN_EINVAL for an unknown key or an out-of-range value. */
 bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t value);
 bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *value);

@@ -62,6 +62,7 @@ _PROTOS = {
     "bn_reserve": (_i, [_vp, _sz]),
     "bn_workspace_size": (_sz, [_vp, _i, _sz, _sz, _sz, _i]),
     "bn_check": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "bn_lookback_stats": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64), _sz]),
     "bn_add": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_sub": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_add_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
@@ -171,6 +172,17 @@ def bn_check(ctx, stream=None) -> int:
     flags = ctypes.c_uint32(0)
     _ck(lib().bn_check(ctx, _stream(stream), ctypes.byref(flags)), "bn_check")
     return flags.value
+
+
+BN_LOOKBACK_BINS = 32
+
+
+def bn_lookback_stats(ctx, stream=None):
+    """Look-back distance histogram since the last call (recorded while debug.flags
+    bit 1 is set): entry k counts tiles decided 2^k..2^(k+1)-1 tiles back."""
+    h = (ctypes.c_uint64 * BN_LOOKBACK_BINS)()
+    _ck(lib().bn_lookback_stats(ctx, _stream(stream), h, BN_LOOKBACK_BINS), "bn_lookback_stats")
+    return [int(x) for x in h]
 
 
 def bn_set_param(ctx, key: str, value: int):

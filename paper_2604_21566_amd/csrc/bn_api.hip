@@ -136,6 +136,18 @@ size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npair
     return mul_workspace_bytes(ctx, na, nb, npairs, form);
 }
 
+bn_status bn_lookback_stats(bn_ctx *ctx, bn_stream stream, uint64_t *hist, size_t nbins) {
+    if (!ctx || (!hist && nbins)) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (hipStreamSynchronize(S(stream)) != hipSuccess) return BN_EHIP;
+    u64 h[LOOKBACK_BINS];
+    if (hipMemcpy(h, ctx->ctl->hist, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return BN_EHIP;
+    const u64 zero[LOOKBACK_BINS] = {};
+    if (hipMemcpy(ctx->ctl->hist, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return BN_EHIP;
+    for (size_t i = 0; i < nbins; ++i) hist[i] = i < (size_t)LOOKBACK_BINS ? h[i] : 0;
+    return BN_OK;
+}
+
 bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags) {
     if (!ctx) return BN_EINVAL;
     DeviceGuard g(ctx->device);
@@ -345,13 +357,13 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
         if (v < 64 || v > (1 << 20) || (v % 8)) return BN_EINVAL;
         t.mad_xchunk = (int)v;
     } else if (k == "mul.mfma_chunk") {
-        if (v < 16 || v > 2047) return BN_EINVAL;  // int32 bound: 2047 steps of 64 digit products <= 2^14
+        if (v < 16 || v > 256 || (v & 1)) return BN_EINVAL;  // even (steps run in pairs); staging registers
         t.mfma_chunk = (int)v;
     } else if (k == "lookback.spin_limit") {
         if (v < 0 || v > 0xffffffffll) return BN_EINVAL;
         t.spin_limit = (u32)v;
     } else if (k == "debug.flags") {
-        if (v < 0 || v > 1) return BN_EINVAL;
+        if (v < 0 || v > 3) return BN_EINVAL;
         t.debug_flags = (u32)v;
     } else {
         return BN_EINVAL;

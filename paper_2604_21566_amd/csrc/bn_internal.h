@@ -24,10 +24,12 @@ typedef int64_t i64;
 //           scan, so status words of earlier launches never match
 //   err   : sticky latch read and cleared by bn_check (bit 0: a look-back computed
 //           a predecessor tile's aggregate itself instead of waiting for it)
+constexpr int LOOKBACK_BINS = 32;
 struct ScanCtl {
     u64 epoch;
     u64 err;
     u64 pad[6];
+    u64 hist[LOOKBACK_BINS];  // look-back distances, recorded when debug flag bit 1 is set
 };
 
 // Tile-shape selector for the flat scan kernel.
@@ -46,9 +48,10 @@ struct Tuning {
     i64 mul_crossover_limbs = 256;     // BN_MUL_AUTO: MFMA when min(na, nb) >= this
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
-    int mfma_chunk = 256;              // Toeplitz steps staged in LDS per round (<= 2047, int32 bound)
+    int mfma_chunk = 256;              // Toeplitz steps staged in LDS per round (even, 16..256)
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
+                                       // bit 1: record look-back distances in ScanCtl::hist
 };
 
 // Workspace buffer that grows on demand (never while the stream is being captured).

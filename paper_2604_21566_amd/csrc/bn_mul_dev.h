@@ -189,6 +189,10 @@ __device__ __forceinline__ TWords toeplitz_words(const u32 *__restrict__ lds_wor
     const u32 q = off >> 2;
     return TWords{lds_words[q], lds_words[q + 1], lds_words[q + 2], lds_words[q + 3], lds_words[q + 4]};
 }
+template <class P>
+__device__ __forceinline__ TWords tw_at(P lds_words, int q) {
+    return TWords{lds_words[q], lds_words[q + 1], lds_words[q + 2], lds_words[q + 3], lds_words[q + 4]};
+}
 __device__ __forceinline__ v4i toeplitz_combine(const TWords &t, u32 s) {
     v4i f;
     f.x = (int)__builtin_amdgcn_alignbyte(t.w1, t.w0, s);

@@ -128,10 +128,11 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
 // that is not an all-propagate aggregate decides: a known carry-out ends the walk;
 // an unpublished tile is waited for up to `spin_limit` polls, after which the wave
 // computes that tile's aggregate from the operands itself and walks on.  Tiles
-// below index 0 count as "carry-out 0".
+// below index 0 count as "carry-out 0".  `dist` returns how many tiles back the
+// deciding predecessor was.
 template <bool SUB>
 __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64 *latch,
-                        const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G) {
+                        const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G, u64 &dist) {
     const int lane = threadIdx.x & 63;
     // fast probe: the nearest predecessor usually knows its carry-out already
     {
@@ -139,6 +140,7 @@ __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64
         if (lane == 0) st = ld_relaxed(status + t - 1);
         st = __shfl(st, 0);
         const u32 state = ((st >> 2) == epoch) ? (u32)(st & 3) : 0u;
+        dist = 1;
         if (state >= ST_I0) return state & 1u;
     }
     i64 base = (i64)t - 1;
@@ -155,6 +157,7 @@ __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64
         }
         const int first = __ffsll((unsigned long long)notA) - 1;
         const u32 sf = __shfl(state, first);
+        dist = (u64)((i64)t - (base - first));  // base - first >= -1: "tile -1" is a carry-out 0
         if (sf != 0) return sf & 1u;
         if (++spins <= spin_limit) {
             __builtin_amdgcn_s_sleep(1);
@@ -334,7 +337,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     if (w == 0) {
         u32 cin = 0;
         const u64 first_pos = __shfl(pos0, 0);
-        if (t > 0 && first_pos != 0) cin = lookback<SUB>(status, t, epoch, spin_limit, &ctl->err, a, b, G);
+        if (t > 0 && first_pos != 0) {
+            u64 dist;
+            cin = lookback<SUB>(status, t, epoch, spin_limit, &ctl->err, a, b, G, dist);
+            if ((dbg & 2u) && lane == 0)
+                __hip_atomic_fetch_add(ctl->hist + (63 - __clzll((long long)dist)), 1ull, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (lane == 0) {
             if (sh_pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
             u32 c = cin;

@@ -143,8 +143,9 @@ __global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, 
     __shared__ u32 sh[4];
     u64 n;
     u32 *lp;
-    const u64 *x = prep_operand(a, b, na, nb, blockIdx.y, n, lpa, lpb, lp);
-    const u64 base = (u64)blockIdx.x * PREP_SEG + 4 * (u64)threadIdx.x;
+    const u64 op_pair = blockIdx.x / nseg, sg = blockIdx.x % nseg;
+    const u64 *x = prep_operand(a, b, na, nb, op_pair, n, lpa, lpb, lp);
+    const u64 base = sg * PREP_SEG + 4 * (u64)threadIdx.x;
     u32 sum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, 
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) seg_tot[(u64)blockIdx.y * nseg + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    if (threadIdx.x == 0) seg_tot[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 __global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
@@ -161,13 +162,14 @@ __global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, co
     __shared__ u32 sh[4], shp[4];
     u64 n;
     u32 *lp;
-    const u64 *x = prep_operand(a, b, na, nb, blockIdx.y, n, lpa, lpb, lp);
-    const u64 seg0 = (u64)blockIdx.x * PREP_SEG;
-    if (seg0 >= n && !(n == 0 && blockIdx.x == 0)) return;
+    const u64 op_pair = blockIdx.x / nseg, sg = blockIdx.x % nseg;
+    const u64 *x = prep_operand(a, b, na, nb, op_pair, n, lpa, lpb, lp);
+    const u64 seg0 = sg * PREP_SEG;
+    if (seg0 >= n && !(n == 0 && sg == 0)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // digits of all earlier segments (strided over the workgroup, then reduced)
     u32 pre = 0;
-    for (u32 s2 = threadIdx.x; s2 < blockIdx.x; s2 += 256) pre += seg_tot[(u64)blockIdx.y * nseg + s2];
+    for (u64 s2 = threadIdx.x; s2 < sg; s2 += 256) pre += seg_tot[op_pair * nseg + s2];
     for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
     if (lane == 0) shp[w] = pre;
     const u64 base = seg0 + 4 * (u64)threadIdx.x;
@@ -230,7 +232,11 @@ __device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u64 nda, 
     return m + 128 * (sa + sb) - 16384 * cnt;
 }
 
+template <class T>
+using lds_cptr = const __attribute__((address_space(3))) T *;  // read-only pointer into LDS
+
 constexpr int AZ_SLOT_U64 = 10;  // one 64-digit chunk per 80-byte LDS slot: ds_read_b128 without bank conflicts
+
 
 // Large products on the MFMA form.  Output digit columns are grouped 64 at a time
 // (t = 64 W + r, r < 64), the Toeplitz step consumes 64 digits of b:
@@ -244,15 +250,31 @@ constexpr int AZ_SLOT_U64 = 10;  // one 64-digit chunk per 80-byte LDS slot: ds_
 // few workgroups to fill the device), staging D steps of b digits and the matching
 // window of a chunks (byte-reversed) in LDS per round: no atomics and no
 // workspace zeroing in the unsplit case.  Accumulation is int32.  Unsplit launches
-// have at most 2047 steps, so a column holds at most 131008 digit products: its
-// register holds the true signed sum M modulo 2^32 and M lies in
-// [-16256 cnt, 16384 cnt], narrower than 2^32, so the epilogue decodes it exactly,
-// folds the 64 columns of each W into 8 limb values and writes lo and shifted hi.
-// Split launches keep every slice at most 2047 steps (2047 * 64 * 2^14 < 2^31, exact)
-// and add the slice sums into an int64 column workspace that a fold kernel reads.
+// are used while a column holds at most 131586 digit products: its register holds
+// the true signed sum M modulo 2^32 and M lies in [-16256 cnt, 16384 cnt], narrower
+// than 2^32, so the epilogue decodes it exactly, folds the 64 columns of each W
+// into 8 limb values and writes lo and shifted hi.  Split launches keep every slice
+// at most 2046 steps when columns are longer (2046 * 64 * 2^14 < 2^31, exact) and
+// add the slice sums into an int64 column workspace that a fold kernel reads.
 // Workgroups are ordered by decreasing work.
+// Instruction order of one step of the large MFMA kernel: the LDS reads of the next
+// step go out first, then half of the MFMAs, then the VALU work (byte shifts of the
+// fragments just read, addresses) between the other half (the scheduler would
+// otherwise issue each read just before its use and wait for it).
+__device__ __forceinline__ void mfma_step_order() {
+    constexpr int MFMA = 0x008, VALU = 0x002, DSR = 0x100;
+    __builtin_amdgcn_sched_group_barrier(DSR, 9, 0);
+    __builtin_amdgcn_sched_group_barrier(MFMA, 4, 0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        __builtin_amdgcn_sched_group_barrier(VALU, 3, 0);
+        __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
+    }
+}
+
+// Two workgroups fit a CU's LDS, so two waves per SIMD: registers are not the limit.
 template <int NW, bool SPLIT>
-__global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mul_large_mfma(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
                                                         u64 nb, u64 npairs, const u32 *__restrict__ lpa,
                                                         const u32 *__restrict__ lpb, u32 D, u32 ngroups,
                                                         u32 nslices, u64 *__restrict__ LO, u64 *__restrict__ HS,
@@ -295,11 +317,21 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
     const i64 lastb = std::min<i64>(wb0 + 4 * NW, nWb) - 1;
     i64 ulo = std::max<i64>(0, W0g - nca + 1);
     i64 uhi = std::min<i64>(dmax, 32 * lastb + 31);
+    const i64 ulo_all = ulo, uhi_all = uhi;
     if (SPLIT) {
-        // this workgroup's slice of the contraction range (at most 2047 steps: exact int32)
-        const i64 sl = (dmax + (i64)nslices) / (i64)nslices;
+        // this workgroup's slice of the contraction range: an even number of steps, at
+        // most 2046 (exact int32 sums)
+        const i64 sl = (((dmax + (i64)nslices) / (i64)nslices) + 1) & ~(i64)1;
         ulo = std::max<i64>(ulo, (i64)slice * sl);
         uhi = std::min<i64>(uhi, (i64)slice * sl + sl - 1);
+    }
+    // Steps run in pairs.  A step outside every block's own range adds zero (its a
+    // chunks or b digits are zero-padded), so an odd range grows by one such step at
+    // an end where the workgroup's blocks end; a slice boundary in the middle of the
+    // blocks' ranges stays put (slices of even length then meet there).
+    if (ulo <= uhi && ((uhi - ulo) & 1) == 0) {
+        if (uhi == uhi_all) ++uhi;
+        else if (ulo == ulo_all) --ulo;
     }
 
     v16i acc[NW][2];
@@ -315,71 +347,133 @@ __global__ __launch_bounds__(256) void k_mul_large_mfma(const u64 *__restrict__ 
         const i64 cbase = W0g - d1;
         const i64 nslots = Wend - d0 - cbase + 1;
         __syncthreads();
-        for (u32 k = threadIdx.x; k < 8 * (D + 3); k += 256) {
-            const i64 m = 8 * (d0 - 1) + (i64)k;
-            bz[k] = (m >= 0 && m < (i64)nb) ? (pb[m] ^ XOR80) : 0ull;
+        // Staging, SG elements per thread at a time: unconditional loads from clamped
+        // indices first (no branch between a load and its use, so one wait per group),
+        // then out-of-range elements replaced by zero and the signed offset applied.
+        constexpr int SG = 8;
+        for (u32 k0 = threadIdx.x; k0 < 8 * (D + 3); k0 += 256 * SG) {
+            u64 v[SG];
+#pragma unroll
+            for (int j = 0; j < SG; ++j) {
+                const i64 m = 8 * (d0 - 1) + (i64)(k0 + 256 * j);
+                v[j] = pb[std::min<i64>(std::max<i64>(m, 0), (i64)nb - 1)];
+            }
+#pragma unroll
+            for (int j = 0; j < SG; ++j) {
+                const u32 k = k0 + 256 * j;
+                const i64 m = 8 * (d0 - 1) + (i64)k;
+                if (k < 8 * (D + 3)) bz[k] = (m >= 0 && m < (i64)nb) ? (v[j] ^ XOR80) : 0ull;
+            }
         }
-        for (u32 k = threadIdx.x; k < 8 * nslots; k += 256) {
-            const i64 c = cbase + (i64)(k >> 3);
-            const i64 m = 8 * c + 7 - (i64)(k & 7);
-            az[AZ_SLOT_U64 * (k >> 3) + (k & 7)] = (m >= 0 && m < (i64)na) ? __builtin_bswap64(pa[m] ^ XOR80) : 0ull;
+        for (u32 k0 = threadIdx.x; k0 < 8 * nslots; k0 += 256 * SG) {
+            u64 v[SG];
+#pragma unroll
+            for (int j = 0; j < SG; ++j) {
+                const u32 k = k0 + 256 * j;
+                const i64 m = 8 * (cbase + (i64)(k >> 3)) + 7 - (i64)(k & 7);
+                v[j] = pa[std::min<i64>(std::max<i64>(m, 0), (i64)na - 1)];
+            }
+#pragma unroll
+            for (int j = 0; j < SG; ++j) {
+                const u32 k = k0 + 256 * j;
+                const i64 m = 8 * (cbase + (i64)(k >> 3)) + 7 - (i64)(k & 7);
+                if (k < 8 * nslots)
+                    az[AZ_SLOT_U64 * (k >> 3) + (k & 7)] =
+                        (m >= 0 && m < (i64)na) ? __builtin_bswap64(v[j] ^ XOR80) : 0ull;
+            }
         }
         __syncthreads();
-        const i64 dlo = std::max(d0, wlo), dhi = std::min(d1, whi);
+        i64 dlo = std::max(d0, wlo), dhi = std::min(d1, whi);
         if (dlo <= dhi) {
-            // Software-pipelined: the LDS reads of step d+1 are issued before the MFMAs
-            // of step d.  The byte shift is the same for every fragment of a lane.
+            // an even step count: grow by a step past the wave's blocks, inside the round
+            if (((dhi - dlo) & 1) == 0) {
+                if (dhi < d1) ++dhi;
+                else if (dlo > d0) --dlo;
+            }
+            // Two steps per trip with two register sets (X, Y): while one step's MFMAs
+            // run, the LDS reads of the next step land in the other set, a whole step
+            // ahead of their use.  The byte shift is the same for every fragment of a
+            // lane.  Toeplitz fragments: step d uses T(d, 0), T(d, 32), T(d, 64) and
+            // T(d, 64) == T(d + 1, 0), so each step reads two new ones.
             const u32 sh = (x + 1) & 3u;
             const u32 lane_off = x + 1 + 16 * h;
-            u32 ob = (u32)(64 * (dlo - d0)) + lane_off;
-            v4i f0 = toeplitz_combine(toeplitz_words(bz32, ob), sh);
-            v4i f1 = toeplitz_combine(toeplitz_words(bz32, ob + 32), sh);
-            v4i f2 = toeplitz_combine(toeplitz_words(bz32, ob + 64), sh);
-            v4i A0[NW], A1[NW];
+            // Running LDS pointers: pT = fragment T(d, 0) in bz (a step moves it by 16
+            // words), pA[i] = block i's a chunk slot at step d + 2 in az (a step moves
+            // it back one slot; the trip's reads sit at non-negative offsets from it).  The reads for step d + 2
+            // in the last trip may lie one step past dhi: still inside the LDS arrays
+            // (b digits of step d1 + 1 are staged; slot -1 is the end of bz), unused.
+            lds_cptr<u32> pT = (lds_cptr<u32>)bz32 + (lane_off >> 2) + 16 * (int)(dlo - d0);
+            lds_cptr<u64> pA[NW];
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+                pA[i] = (lds_cptr<u64>)az + AZ_SLOT_U64 * (int)(32 * (wb0 + (i64)wave * NW + i) + (i64)x - cbase - dlo - 2) +
+                        2 * (int)h;
+            v4i FX1, FX2, FY1, FY2, FY2p;
+            v4i AX0[NW], AX1[NW], AY0[NW], AY1[NW];
+            // prologue: step dlo into X; its first fragment into FY2p (the role the
+            // previous Y step's last fragment plays in the loop)
+            FY2p = toeplitz_combine(tw_at(pT, 0), sh);
+            FX1 = toeplitz_combine(tw_at(pT, 8), sh);
+            FX2 = toeplitz_combine(tw_at(pT, 16), sh);
+            // (volatile: keeps the compiler from merging these reads with the loop's
+            // reads of the same registers into one read at the top of the loop)
 #pragma unroll
             for (int i = 0; i < NW; ++i) {
-                const i64 slot = 32 * (wb0 + (i64)wave * NW + i) + (i64)x - dlo - cbase;
-                const u64 *sp = az + AZ_SLOT_U64 * std::max<i64>(0, slot);
-                A0[i] = *reinterpret_cast<const v4i *>(sp + 2 * h);
-                A1[i] = *reinterpret_cast<const v4i *>(sp + 4 + 2 * h);
+                AX0[i] = *(const volatile __attribute__((address_space(3))) v4i *)(pA[i] + 2 * AZ_SLOT_U64);
+                AX1[i] = *(const volatile __attribute__((address_space(3))) v4i *)(pA[i] + 2 * AZ_SLOT_U64 + 4);
             }
-            for (i64 d = dlo; d <= dhi; ++d) {
-                // prefetch step d+1 (clamped to the last step: its loads stay in range)
-                const i64 dn = d < dhi ? d + 1 : d;
-                const u32 on = (u32)(64 * (dn - d0)) + lane_off;
-                const TWords t1 = toeplitz_words(bz32, on + 32);
-                const TWords t2 = toeplitz_words(bz32, on + 64);
-                v4i A0n[NW], A1n[NW];
+            // Every block of the wave runs every step of the wave's range: outside a
+            // block's own range its a chunks are zero-padded in LDS, so those MFMAs add
+            // zero.  No branches around MFMAs (the compiler would copy the
+            // accumulators); independent accumulators sit between the two MFMAs that
+            // update the same one.  One basic block per trip.
+            for (i64 d = dlo; d <= dhi; d += 2) {
+                // ---- step d on X; reads of step d + 1 into Y ----
+                const TWords ty1 = tw_at(pT, 24);
+                const TWords ty2 = tw_at(pT, 32);
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
-                    const i64 slot = 32 * (wb0 + (i64)wave * NW + i) + (i64)x - dn - cbase;
-                    const u64 *sp = az + AZ_SLOT_U64 * std::max<i64>(0, slot);
-                    A0n[i] = *reinterpret_cast<const v4i *>(sp + 2 * h);
-                    A1n[i] = *reinterpret_cast<const v4i *>(sp + 4 + 2 * h);
-                }
-                // Every block of the wave runs every step of the wave's range: outside a
-                // block's own range its a chunks are zero-padded in LDS, so those MFMAs
-                // add zero.  No branches around MFMAs (the compiler would copy the
-                // accumulators); independent accumulators sit between the two MFMAs that
-                // update the same one.
-#pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, A0[i], acc[i][0], 0, 0, 0);
-                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A0[i], acc[i][1], 0, 0, 0);
+                    AY0[i] = *(lds_cptr<v4i>)(pA[i] + AZ_SLOT_U64);
+                    AY1[i] = *(lds_cptr<v4i>)(pA[i] + AZ_SLOT_U64 + 4);
                 }
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
-                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, A1[i], acc[i][0], 0, 0, 0);
-                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, A1[i], acc[i][1], 0, 0, 0);
+                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY2p, AX0[i], acc[i][0], 0, 0, 0);
+                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX1, AX0[i], acc[i][1], 0, 0, 0);
                 }
-                f0 = f2;
-                f1 = toeplitz_combine(t1, sh);
-                f2 = toeplitz_combine(t2, sh);
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
-                    A0[i] = A0n[i];
-                    A1[i] = A1n[i];
+                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX1, AX1[i], acc[i][0], 0, 0, 0);
+                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX2, AX1[i], acc[i][1], 0, 0, 0);
                 }
+                FY1 = toeplitz_combine(ty1, sh);
+                FY2 = toeplitz_combine(ty2, sh);
+                mfma_step_order();
+                // ---- step d + 1 on Y; reads of step d + 2 into X ----
+                const TWords tx1 = tw_at(pT, 40);
+                const TWords tx2 = tw_at(pT, 48);
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    AX0[i] = *(lds_cptr<v4i>)(pA[i]);
+                    AX1[i] = *(lds_cptr<v4i>)(pA[i] + 4);
+                }
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX2, AY0[i], acc[i][0], 0, 0, 0);
+                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY1, AY0[i], acc[i][1], 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY1, AY1[i], acc[i][0], 0, 0, 0);
+                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY2, AY1[i], acc[i][1], 0, 0, 0);
+                }
+                FY2p = FY2;
+                FX1 = toeplitz_combine(tx1, sh);
+                FX2 = toeplitz_combine(tx2, sh);
+                pT += 32;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) pA[i] -= 2 * AZ_SLOT_U64;
+                mfma_step_order();
             }
         }
     }
@@ -511,7 +605,8 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, bool split
 }  // namespace
 
 // Contraction slices for the large MFMA kernel: enough workgroups to fill the device
-// (about four per CU), slices of at least 128 steps, and at most 2047 steps per slice.
+// (about four per CU), slices of at least 128 steps, and at most 2046 steps per slice
+// when the int32 slice sums need it.
 struct MfmaPlan {
     u64 ngroups;
     u32 nslices;
@@ -529,10 +624,11 @@ static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
     u64 S = 1;
     if (blocks < target) S = std::max<u64>(1, std::min<u64>((target + blocks - 1) / blocks, (steps + 127) / 128));
     // a slice sum is added to the workspace as a plain int32: |sum| <= 2^14 cnt must stay
-    // below 2^31, so slices longer than 2047 steps need cnt <= 131071
-    if (S > 1 && maxcnt > 131071) S = std::max<u64>(S, (steps + 2046) / 2047);
+    // below 2^31, so slices longer than 2047 steps need cnt <= 131071 (slices are
+    // rounded up to an even length: at most 2046 steps)
+    if (S > 1 && maxcnt > 131071) S = std::max<u64>(S, (steps + 2045) / 2046);
     // an unsplit launch decodes its int32 sums exactly while cnt <= 131586
-    if (S == 1 && maxcnt > 131586) S = std::max<u64>(2, (steps + 2046) / 2047);
+    if (S == 1 && maxcnt > 131586) S = std::max<u64>(2, (steps + 2045) / 2046);
     mp.nslices = (u32)S;
     return mp;
 }
@@ -572,7 +668,6 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
                                (u32)nb, npairs);
         return bn_launch_status();
     }
-    if (form == BN_MUL_MAD && npairs > 65535) return BN_ERANGE;  // grid.y of the mad product kernel
     const MfmaPlan mp = mfma_plan(ctx, na, nb, npairs);
     const bool split = form == BN_MUL_MFMA && mp.nslices > 1;
     const LargeLayout L = large_layout(na, nb, npairs, form, split);
@@ -602,22 +697,26 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         const u64 nitems = ncb * nxc;
         const u64 blocks = (nitems + 3) / 4;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
-        hipLaunchKernelGGL((k_mul_large_mad<Q>), dim3((u32)blocks, (u32)npairs), dim3(256), 0, s, a, b, na, nb, nxc,
-                           nitems, XC, colLo, colHi);
-        if ((st = bn_launch_status()) != BN_OK) return st;
+        for (u64 p0 = 0; p0 < npairs; p0 += 65535) {  // grid.y holds the pair
+            const u64 np = std::min<u64>(65535, npairs - p0);
+            hipLaunchKernelGGL((k_mul_large_mad<Q>), dim3((u32)blocks, (u32)np), dim3(256), 0, s, a + p0 * na,
+                               b + p0 * nb, na, nb, nxc, nitems, XC, colLo + p0 * 2 * P, colHi + p0 * 2 * P);
+            if ((st = bn_launch_status()) != BN_OK) return st;
+        }
         hipLaunchKernelGGL(k_fold_mad, dim3((u32)fold_blocks), dim3(256), 0, s, colLo, colHi, P, total, LO, HS);
         if ((st = bn_launch_status()) != BN_OK) return st;
     } else {
         u32 *lpa = reinterpret_cast<u32 *>(ws + L.lpa);
         u32 *lpb = reinterpret_cast<u32 *>(ws + L.lpb);
         u32 *seg = reinterpret_cast<u32 *>(ws + L.seg);
-        const u32 nseg = (u32)((std::max(na, nb) + PREP_SEG - 1) / PREP_SEG);
-        if (2 * npairs > 65535) return BN_ERANGE;
-        hipLaunchKernelGGL(k_prep_totals, dim3(nseg, (u32)(2 * npairs)), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
-                           nseg);
+        const u64 nseg = (std::max(na, nb) + PREP_SEG - 1) / PREP_SEG;
+        const u64 prep_blocks = nseg * 2 * npairs;
+        if (prep_blocks > 0x7fffffffull) return BN_ERANGE;
+        hipLaunchKernelGGL(k_prep_totals, dim3((u32)prep_blocks), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
+                           (u32)nseg);
         if ((st = bn_launch_status()) != BN_OK) return st;
-        hipLaunchKernelGGL(k_prep_scan, dim3(nseg, (u32)(2 * npairs)), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
-                           nseg);
+        hipLaunchKernelGGL(k_prep_scan, dim3((u32)prep_blocks), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
+                           (u32)nseg);
         if ((st = bn_launch_status()) != BN_OK) return st;
         constexpr int NW = 2;
         const u32 D = (u32)ctx->tune.mfma_chunk;

@@ -2,6 +2,8 @@
 
   python -m paper_2604_21566_amd.rocprof_summary <results.db> "<command>" > out.txt
       per-kernel durations from a --kernel-trace --stats run
+  python -m paper_2604_21566_amd.rocprof_summary pmc <counter_collection.csv> "<command>" > out.txt
+      per-kernel mean of every counter of a --pmc run (one row per kernel and counter)
   python -m paper_2604_21566_amd.rocprof_summary traffic <fetch.csv> <write.csv> "<fetch cmd>" "<write cmd>" > out.txt
       HBM bytes per launch of the add/sub scan kernel on the batched workload
       (2^20 pairs x 64 limbs) from one FETCH_SIZE and one WRITE_SIZE --pmc run of
@@ -56,6 +58,19 @@ def _counter_rows(path):
         return [(r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])) for r in csv.DictReader(fh)]
 
 
+def pmc(path, cmd):
+    per = {}
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            k = (short(r["Kernel_Name"]), r["Counter_Name"])
+            per.setdefault(k, []).append(float(r["Counter_Value"]))
+    print(f"# command: {cmd}")
+    print("# mean (min, max) over the kernel's dispatches of each counter, as rocprofv3 --pmc reports it")
+    print(f"{'kernel':60s} {'counter':30s} {'dispatches':>10s} {'mean':>14s} {'min':>14s} {'max':>14s}")
+    for (name, ctr), v in sorted(per.items()):
+        print(f"{name[:60]:60s} {ctr:30s} {len(v):10d} {sum(v) / len(v):14.6g} {min(v):14.6g} {max(v):14.6g}")
+
+
 def traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
     F, W = _counter_rows(fetch_csv), _counter_rows(write_csv)
     copy_kib = COPY_BYTES / 1024
@@ -103,5 +118,7 @@ def traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
 if __name__ == "__main__":
     if sys.argv[1] == "traffic":
         traffic(*sys.argv[2:6])
+    elif sys.argv[1] == "pmc":
+        pmc(sys.argv[2], sys.argv[3])
     else:
         main(sys.argv[1], sys.argv[2])

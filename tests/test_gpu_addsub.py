@@ -210,3 +210,31 @@ def test_self_help_every_tile(bnctx, op):
             _check(bnctx, op, a, b, a.size, 1)
     finally:
         bn.bn_set_param(bnctx, "lookback.spin_limit", old)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("n,npairs", [((1 << 20) + 5, 1), (100003, 7)])
+def test_lookback_histogram_counts_every_chained_tile(bnctx, op, n, npairs):
+    """With debug flag bit 1 every tile that looks back records one distance: the
+    histogram total is the number of tiles that do not start a segment."""
+    announce("look-back histogram", op, f"n={n}", f"npairs={npairs}")
+    old = bn.bn_get_param(bnctx, "debug.flags")
+    waves = bn.bn_get_param(bnctx, "addsub.chain_waves")
+    rows = bn.bn_get_param(bnctx, "addsub.chain_rows")
+    TL = waves * rows * 128
+    N = n * npairs
+    ntiles = -(-N // TL)
+    expect = sum(1 for t in range(1, ntiles) if (t * TL) % n != 0)
+    a, b = wl.c3(op, n=N, worst=True)
+    bn.bn_lookback_stats(bnctx)  # clear
+    try:
+        bn.bn_set_param(bnctx, "debug.flags", 2)
+        _check(bnctx, op, a, b, n, npairs)
+        h = bn.bn_lookback_stats(bnctx)
+    finally:
+        bn.bn_set_param(bnctx, "debug.flags", old)
+    assert sum(h) == expect, (sum(h), expect, h)
+    assert all(v == 0 for v in h[max(1, ntiles.bit_length()):]), h
+    # not recorded with the flag off
+    _check(bnctx, op, a, b, n, npairs)
+    assert sum(bn.bn_lookback_stats(bnctx)) == 0

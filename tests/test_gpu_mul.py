@@ -251,3 +251,11 @@ def test_single_large_pair(bnctx, form, na, nb):
     workgroups (MFMA) or into small slices (mad)."""
     g = np.random.default_rng(na + nb)
     _check(bnctx, _rand(g, na), _rand(g, nb), na, nb, 1, form)
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+def test_many_large_pairs(bnctx, form):
+    """More pairs than one grid dimension holds (65535) on the column-workspace path."""
+    na, nb, npairs = 150, 131, 70000
+    g = np.random.default_rng(7)
+    _check(bnctx, _rand(g, na * npairs), _rand(g, nb * npairs), na, nb, npairs, form)
