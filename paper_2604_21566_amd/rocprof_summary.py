@@ -23,13 +23,10 @@ C2_PAIRS, C2_LIMBS = 1 << 20, 64
 
 
 def kernel_source_hash() -> str:
-    """Hash of the scan kernel's sources: a counter summary is valid only for the
+    """Hash of the scan kernel's source file: a counter summary is valid only for the
     source it was taken on."""
-    h = hashlib.sha256()
-    for f in ("k_addsub.hip", "bn_internal.h"):
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    with open(os.path.join(CSRC, "k_addsub.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def short(name: str) -> str:
