@@ -364,13 +364,22 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
                     bn.bn_plan_destroy(plan)
                     row[f"{form}_us"] = ms * 1e3
                     row[f"{form}_limb_products_per_s"] = w / (ms * 1e-3)
-                if row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"] and crossover is None:
-                    crossover = lo
+                # the smallest bucket from which MFMA is faster in every larger bucket
+                if row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"]:
+                    crossover = lo if crossover is None else crossover
+                else:
+                    crossover = None
                 buckets[f"{lo}-{2 * lo - 1 if lo < 128 else 128}"] = row
             lo *= 2
         c4["buckets_by_longer_operand_limbs"] = buckets
         c4["mfma_faster_from_bucket"] = crossover
         res["c4"] = c4
+
+    # ---- measured ceilings of the two multiplication forms' inner operations
+    mac_rate, mfma_rate = bn.bn_probe_rates(ctx)
+    res["measured_rates"] = {"mac96_per_s": mac_rate, "mfma_i8_ops_per_s": mfma_rate,
+                             "mad_form_limb_products_per_s_ceiling": mac_rate / 4,
+                             "mfma_form_limb_products_per_s_ceiling": mfma_rate / 128}
 
     # ---- c5: 64 products of 16384-limb operands
     if only is None or "c5" in only:
@@ -387,6 +396,8 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
             c5[f"{form}_products_per_s"] = 64 / (ms * 1e-3)
         c5["mfma_int8_TOPS"] = 2 * 64.0 * 64.0 * n5 * n5 / (c5["mfma_ms"] * 1e-3) / 1e12
         c5["mfma_frac_of_int8_peak"] = c5["mfma_int8_TOPS"] / INT8_PEAK_TOPS
+        c5["mfma_frac_of_measured_int8"] = c5["mfma_int8_TOPS"] * 1e12 / mfma_rate
+        c5["mad_frac_of_measured_mac96"] = c5["mad_limb_products_per_s"] * 4 / mac_rate
         c5["mfma_over_mad"] = c5["mad_ms"] / c5["mfma_ms"]
         res["c5"] = c5
 

@@ -210,6 +210,16 @@ const char *bn_param_names(void);
  * out_json != NULL, write them as a JSON object.  Synchronous; takes seconds. */
 bn_status bn_autotune(bn_ctx *ctx, const char *out_json);
 
+/* Measured device rates for the two multiplication forms' inner operations, the
+ * ceilings their rooflines are stated against: *mac96_per_s = 32x32-bit multiply-
+ * accumulates into a 96-bit sum per second (v_mad_u64_u32 + v_addc_co_u32, the
+ * plain form's column step, Alg. 2 phase 2 on 32-bit digits) and
+ * *mfma_i8_ops_per_s = int8 MFMA operations per second (2 per multiply-add,
+ * v_mfma_i32_32x32x32_i8 with independent accumulators), each over every CU of the
+ * context's device.  Synchronises the device; allocates and frees a small buffer.
+ * Returns BN_EINVAL for NULL arguments, BN_ENOMEM, or BN_EHIP. */
+bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mfma_i8_ops_per_s);
+
 /* Load parameters written by bn_autotune (flat JSON object of "key": integer). */
 bn_status bn_load_tuning(bn_ctx *ctx, const char *json_path);
 

@@ -63,6 +63,7 @@ _PROTOS = {
     "bn_workspace_size": (_sz, [_vp, _i, _sz, _sz, _sz, _i]),
     "bn_check": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),
     "bn_lookback_stats": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64), _sz]),
+    "bn_probe_rates": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "bn_add": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_sub": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_add_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
@@ -183,6 +184,13 @@ def bn_lookback_stats(ctx, stream=None):
     h = (ctypes.c_uint64 * BN_LOOKBACK_BINS)()
     _ck(lib().bn_lookback_stats(ctx, _stream(stream), h, BN_LOOKBACK_BINS), "bn_lookback_stats")
     return [int(x) for x in h]
+
+
+def bn_probe_rates(ctx):
+    """Measured (mac96 per s, int8 MFMA ops per s) of the context's device."""
+    m, f = ctypes.c_double(0), ctypes.c_double(0)
+    _ck(lib().bn_probe_rates(ctx, ctypes.byref(m), ctypes.byref(f)), "bn_probe_rates")
+    return m.value, f.value
 
 
 def bn_set_param(ctx, key: str, value: int):

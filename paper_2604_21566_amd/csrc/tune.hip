@@ -7,8 +7,46 @@
 #include <vector>
 
 #include "bn_internal.h"
+#include "bn_mul_dev.h"
 
 namespace {
+
+// Rate probes.  k_rate_mac96: eight independent chains per lane of the plain form's
+// instruction pair (v_mad_u64_u32 + v_addc_co_u32, one 32x32 -> 96-bit accumulate).
+__global__ __launch_bounds__(256) void k_rate_mac96(u64 *out, u32 x, u32 y, int iters) {
+    u64 lo[8];
+    u32 hi[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        lo[k] = threadIdx.x + k;
+        hi[k] = 0;
+    }
+    for (int i = 0; i < iters; ++i)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mac96(lo[k], hi[k], x, y + k);
+    u64 sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sum += lo[k] + hi[k];
+    out[blockIdx.x * (u64)blockDim.x + threadIdx.x] = sum;
+}
+
+// k_rate_mfma: four independent accumulators per wave of v_mfma_i32_32x32x32_i8.
+__global__ __launch_bounds__(256) void k_rate_mfma(int *out, int iters) {
+    const int l = (int)threadIdx.x;
+    const v4i p{l, l + 1, l + 2, l + 3}, q{l ^ 5, l ^ 7, l ^ 9, l ^ 11};
+    v16i acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = v16i{0};
+    for (int i = 0; i < iters; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(p, q, acc[k], 0, 0, 0);
+    u32 sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sum += (u32)acc[k][e];
+    out[blockIdx.x * (u64)blockDim.x + threadIdx.x] = (int)sum;
+}
 
 __global__ void k_fill_random(u64 *p, u64 n, u64 seed) {
     for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) {
@@ -53,6 +91,36 @@ float time_ms(F &&f, int reps = 5) {
 }
 
 }  // namespace
+
+extern "C" bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mfma_i8_ops_per_s) {
+    if (!ctx || !mac96_per_s || !mfma_i8_ops_per_s) return BN_EINVAL;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(ctx->device) != hipSuccess) return BN_EHIP;
+    const u64 cus = (u64)std::max(1, ctx->num_cu);
+    const u64 bm = cus * 16, bf = cus * 8;  // resident waves: 16 and 8 per CU
+    const int im = 4096, iff = 1024;
+    void *out = nullptr;
+    if (hipMalloc(&out, bm * 256 * sizeof(u64)) != hipSuccess) {
+        (void)hipSetDevice(prev);
+        return BN_ENOMEM;
+    }
+    const float tm = time_ms([&] {
+        hipLaunchKernelGGL(k_rate_mac96, dim3((u32)bm), dim3(256), 0, nullptr, (u64 *)out, 3u, 5u, im);
+    });
+    const float tf = time_ms([&] {
+        hipLaunchKernelGGL(k_rate_mfma, dim3((u32)bf), dim3(256), 0, nullptr, (int *)out, iff);
+    });
+    const bool ok = hipGetLastError() == hipSuccess;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(out);
+    (void)hipSetDevice(prev);
+    if (!ok || tm <= 0 || tf <= 0) return BN_EHIP;
+    *mac96_per_s = (double)bm * 256 * im * 8 / (tm * 1e-3);
+    // per wave and iteration: 4 MFMAs of 32 x 32 x 32 multiply-adds, 2 ops each
+    *mfma_i8_ops_per_s = (double)bf * 4 * iff * 4 * 32768.0 * 2 / (tf * 1e-3);
+    return BN_OK;
+}
 
 extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
     if (!ctx) return BN_EINVAL;

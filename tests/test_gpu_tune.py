@@ -57,3 +57,11 @@ def test_autotune_roundtrip(tmp_path):
         assert (bn.to_host(t3) == r3).all()
     finally:
         bn.bn_destroy(ctx)
+
+
+def test_probe_rates_are_plausible(bnctx):
+    """The measured ceilings sit between a tenth of and just above the published
+    figures (VALU: 256 CUs x 64 lanes x 2.4 GHz per full-rate op; int8 MFMA 5.0 POPS)."""
+    mac, mfma = bn.bn_probe_rates(bnctx)
+    assert 1e12 < mac < 4.0e13, mac
+    assert 5e14 < mfma < 5.5e15, mfma
