@@ -401,7 +401,7 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         c5["mfma_over_mad"] = c5["mad_ms"] / c5["mfma_ms"]
         res["c5"] = c5
 
-    # ---- crossover sweep: square products, similar work per size
+    # ---- crossover sweep: square products
     if only is None or "crossover" in only:
         log("crossover sweep")
         sweep = {}
@@ -410,7 +410,9 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         big = torch.empty(1 << 25, dtype=torch.int64, device="cuda").random_()
         out = torch.empty(1 << 26, dtype=torch.int64, device="cuda")
         while n <= 16384:
-            npairs = int(max(1, min(65535, (1 << 28) // (n * n), (1 << 25) // n)))
+            # about 2^32 limb products per size (fewer where the 2^25-limb operand
+            # buffer runs out), so that every size fills the device
+            npairs = int(max(1, min((1 << 32) // (n * n), (1 << 25) // n)))
             row = {}
             for form in ("mad", "mfma"):
                 ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, out, big, big, n, n, npairs, form), 3, 1)

@@ -1,7 +1,8 @@
 // k_mul.hip -- multiplication kernels and the uniform-batch dispatcher.
 //
-// Small products (na + nb <= 256 limbs): one wave per pair does everything --
-// column products, fold, and the in-wave carry pass -- with no workspace.
+// Small products (na + nb <= 256 limbs, and up to 1024 limbs in the mad form): one
+// wave per pair does everything -- column products, fold, and the in-wave carry
+// pass -- with no workspace.
 // Large products: a product kernel accumulates column sums into a workspace with
 // atomics (work items = output-column block x slice of the contraction range, so
 // every item has about the same work), a fold kernel turns column sums into
@@ -14,6 +15,7 @@
 namespace {
 
 constexpr u64 XOR80 = 0x8080808080808080ull;
+constexpr u64 SMALL_MAD_MAX_P = 1024;  // one-wave mad products: up to 16 limbs of output per lane
 
 // -------------------------------------------------------------- small kernels ----
 
@@ -119,13 +121,14 @@ __global__ void k_fold_mad(const u64 *__restrict__ colLo, const u64 *__restrict_
 
 // ---------------------------------------------------------- large: MFMA form ----
 // Per-limb digit-sum prefix tables lp[k] = sum of the digits of limbs [0, k) of every
-// operand of the batch (for the unsigned-sum corrections of the fold).  Two small
-// kernels over segments of PREP_SEG limbs: segment totals, then each segment adds
-// the totals before it and scans its own limbs in the workgroup.
+// operand of the batch (for the unsigned-sum corrections of the fold), 64-bit so that
+// any operand length is exact.  Two small kernels over segments of PREP_SEG limbs:
+// segment totals, then each segment adds the totals before it and scans its own
+// limbs in the workgroup.
 constexpr u32 PREP_SEG = 1024;  // limbs per segment: 256 threads x 4 limbs
 
 __device__ __forceinline__ const u64 *prep_operand(const u64 *a, const u64 *b, u64 na, u64 nb, u64 op_pair, u64 &n,
-                                                   u32 *lpa, u32 *lpb, u32 *&lp) {
+                                                   u64 *lpa, u64 *lpb, u64 *&lp) {
     const u64 pair = op_pair >> 1;
     if (op_pair & 1) {
         n = nb;
@@ -138,15 +141,15 @@ __device__ __forceinline__ const u64 *prep_operand(const u64 *a, const u64 *b, u
 }
 
 __global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                     u64 nb, u32 *__restrict__ lpa, u32 *__restrict__ lpb,
+                                                     u64 nb, u64 *__restrict__ lpa, u64 *__restrict__ lpb,
                                                      u32 *__restrict__ seg_tot, u32 nseg) {
     __shared__ u32 sh[4];
     u64 n;
-    u32 *lp;
+    u64 *lp;
     const u64 op_pair = blockIdx.x / nseg, sg = blockIdx.x % nseg;
     const u64 *x = prep_operand(a, b, na, nb, op_pair, n, lpa, lpb, lp);
     const u64 base = sg * PREP_SEG + 4 * (u64)threadIdx.x;
-    u32 sum = 0;
+    u32 sum = 0;  // at most 1024 limbs x 2040
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         if (base + k < n) sum += bytesum64(x[base + k]);
@@ -157,18 +160,18 @@ __global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, 
 }
 
 __global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                   u64 nb, u32 *__restrict__ lpa, u32 *__restrict__ lpb,
+                                                   u64 nb, u64 *__restrict__ lpa, u64 *__restrict__ lpb,
                                                    const u32 *__restrict__ seg_tot, u32 nseg) {
-    __shared__ u32 sh[4], shp[4];
+    __shared__ u64 sh[4], shp[4];
     u64 n;
-    u32 *lp;
+    u64 *lp;
     const u64 op_pair = blockIdx.x / nseg, sg = blockIdx.x % nseg;
     const u64 *x = prep_operand(a, b, na, nb, op_pair, n, lpa, lpb, lp);
     const u64 seg0 = sg * PREP_SEG;
     if (seg0 >= n && !(n == 0 && sg == 0)) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // digits of all earlier segments (strided over the workgroup, then reduced)
-    u32 pre = 0;
+    u64 pre = 0;
     for (u64 s2 = threadIdx.x; s2 < sg; s2 += 256) pre += seg_tot[op_pair * nseg + s2];
     for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
     if (lane == 0) shp[w] = pre;
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, co
     }
     if (lane == 63) sh[w] = inc;
     __syncthreads();
-    u32 run = shp[0] + shp[1] + shp[2] + shp[3] + inc - sum;
+    u64 run = shp[0] + shp[1] + shp[2] + shp[3] + inc - sum;
     for (int i = 0; i < w; ++i) run += sh[i];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -211,24 +214,49 @@ __device__ __forceinline__ u32 middle_out(u32 k, u32 n) {
     return (k & 1) ? m + (k + 1) / 2 : m - k / 2;
 }
 
-// Exact unsigned column sum from the MFMA sum `raw` of signed digits.  When the
-// accumulation was plain int32 (wide == false) the register holds the true sum M
-// modulo 2^32; M lies in [-16256 cnt, 16384 cnt], an interval narrower than 2^32
-// for cnt <= 131586, so M is recovered exactly.
-__device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u64 nda, u64 ndb, const u64 *__restrict__ a,
-                                            const u32 *__restrict__ lpa, const u64 *__restrict__ b,
-                                            const u32 *__restrict__ lpb) {
-    const u64 ilo = t + 1 > ndb ? t + 1 - ndb : 0;
-    const u64 ihi = t < nda - 1 ? t : nda - 1;
-    if (ilo > ihi) return 0;
-    const i64 cnt = (i64)(ihi - ilo + 1);
+// Exact unsigned column sums from the MFMA sums of signed digits, eight columns at a
+// time: the columns t = 8 j + u (u < 8) of limb j.  With nda, ndb the digit counts,
+// ilo = max(0, t + 1 - ndb) and ihi = min(t, nda - 1), the digits meeting in column t
+// are a[ilo..ihi] and b[t-ihi..t-ilo], cnt = ihi - ilo + 1 of each (0 past the
+// product), and
+//     C = M + 128 (S_a + S_b) - 16384 cnt,
+//     S_a = PA(min(t + 1, nda)) - PA(max(0, t + 1 - ndb)),
+//     S_b = PB(min(t + 1, ndb)) - PB(max(0, t + 1 - nda)),
+// with PA, PB the digit prefix sums.  Every argument is t + 1 + (0, -ndb, 0, -nda),
+// i.e. 8 q + u + 1 for q = j, j - nb, j, j - na: one prefix-table entry and one limb
+// per term give all eight columns, PX(8 q + u + 1) = lp[q] + (digits 0..u of limb q),
+// with limbs outside the operand read as zero and lp clamped to [0, n] (which is
+// exactly the clamping of the arguments above).
+struct ColTerm {
+    u64 pre;   // lp[q] (clamped)
+    u64 limb;  // limb q (0 outside the operand)
+};
+__device__ __forceinline__ ColTerm col_term(const u64 *__restrict__ x, const u64 *__restrict__ lp, u64 n, i64 q) {
+    ColTerm c;
+    c.pre = lp[q < 0 ? 0 : (q > (i64)n ? (i64)n : q)];
+    c.limb = (q >= 0 && q < (i64)n) ? x[q] : 0ull;
+    return c;
+}
+// digits 0..u of a limb
+__device__ __forceinline__ u64 low_digits(u64 limb, u32 u) {
+    return bytesum64(u >= 7 ? limb : (limb & ((1ull << (8 * (u + 1))) - 1)));
+}
+// Column sum of column t = 8 j + u from its raw MFMA sum.  When the accumulation was
+// plain int32 (wide == false) the register holds the true sum M modulo 2^32; M lies in
+// [-16256 cnt, 16384 cnt], an interval narrower than 2^32 for cnt <= 131586, so M is
+// recovered exactly.
+__device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u32 u, u64 nda, u64 ndb, const ColTerm &A1,
+                                            const ColTerm &A2, const ColTerm &B1, const ColTerm &B2) {
+    const i64 ilo = t + 1 > ndb ? (i64)(t + 1 - ndb) : 0;
+    const i64 ihi = t < nda - 1 ? (i64)t : (i64)nda - 1;
+    const i64 cnt = ihi >= ilo ? ihi - ilo + 1 : 0;
     i64 m = raw;
     if (!wide) {
         m = (i64)(int)(u32)raw;
         if (m < -16256 * cnt) m += (i64)1 << 32;
     }
-    const i64 sa = digit_prefix(a, lpa, ihi + 1) - digit_prefix(a, lpa, ilo);
-    const i64 sb = digit_prefix(b, lpb, t - ilo + 1) - digit_prefix(b, lpb, t - ihi);
+    const i64 sa = (i64)((A1.pre + low_digits(A1.limb, u)) - (A2.pre + low_digits(A2.limb, u)));
+    const i64 sb = (i64)((B1.pre + low_digits(B1.limb, u)) - (B2.pre + low_digits(B2.limb, u)));
     return m + 128 * (sa + sb) - 16384 * cnt;
 }
 
@@ -275,10 +303,10 @@ __device__ __forceinline__ void mfma_step_order() {
 // Two workgroups fit a CU's LDS, so two waves per SIMD: registers are not the limit.
 template <int NW, bool SPLIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mul_large_mfma(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                        u64 nb, u64 npairs, const u32 *__restrict__ lpa,
-                                                        const u32 *__restrict__ lpb, u32 D, u32 ngroups,
+                                                        u64 nb, u64 npairs, const u64 *__restrict__ lpa,
+                                                        const u64 *__restrict__ lpb, u32 D, u32 ngroups,
                                                         u32 nslices, u64 *__restrict__ LO, u64 *__restrict__ HS,
-                                                        u64 *__restrict__ col) {
+                                                        int *__restrict__ part) {
     extern __shared__ u64 lds[];
     u64 *bz = lds;                     // 8 (D + 3) words of signed b digits
     u64 *az = lds + 8 * ((u64)D + 3);  // (128 NW + D) chunk slots of reversed signed a digits
@@ -479,9 +507,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 
     if (SPLIT) {
-        // partial column sums of this slice -> int64 column workspace (folded later)
-        if (ulo > uhi) return;
-        u64 *pc = col + pair * 8 * (u64)P;
+        // this slice's column sums (exact int32) -> its own partial array, every column
+        // of the workgroup's blocks written (zeros for an empty slice); a fold kernel
+        // adds the slices
+        int *pc = part + ((u64)slice * npairs + pair) * 8 * (u64)P;
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
             const i64 wb = wb0 + (i64)wave * NW + i;
@@ -491,15 +520,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
                 for (int gg = 0; gg < 16; ++gg) {
                     const u64 t = 64 * ((u64)(32 * wb) + x) + 32 * mi + acc_row(gg, lane);
-                    const int v = acc[i][mi][gg];
-                    if (v != 0 && t < 8 * (u64)P)
-                        __hip_atomic_fetch_add(pc + t, (u64)(i64)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (t < 8 * (u64)P) pc[t] = acc[i][mi][gg];
                 }
         }
         return;
     }
     // ---- epilogue: exact column sums -> limb values -> lo / shifted hi ----
-    const u32 *la = lpa + pair * (na + 1), *lb = lpb + pair * (nb + 1);
+    // Lane (x, h) holds, for each of its blocks, columns t = 64 W + 32 mi + 8 m + 4 h + ii
+    // (W = 32 wb + x): limb jl = 4 mi + m of W's eight, digits u = 4 h + ii.
+    const u64 *la = lpa + pair * (na + 1), *lb = lpb + pair * (nb + 1);
     const u64 nda = 8 * na, ndb = 8 * nb;
     u64 *lo_out = LO + pair * (u64)P, *hs_out = HS + pair * (u64)P;
 #pragma unroll
@@ -512,13 +541,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int mi = 0; mi < 2; ++mi) {
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
+                const i64 j = (i64)(8 * W) + 4 * mi + m;
+                const ColTerm A1 = col_term(pa, la, na, j), A2 = col_term(pa, la, na, j - (i64)nb);
+                const ColTerm B1 = col_term(pb, lb, nb, j), B2 = col_term(pb, lb, nb, j - (i64)na);
                 u128 v = 0;
 #pragma unroll
                 for (int ii = 0; ii < 4; ++ii) {
-                    const int gg = 4 * m + ii;
-                    const u64 t = 64 * W + 32 * mi + 8 * m + 4 * h + ii;
-                    const i64 cf = column_exact((i64)acc[i][mi][gg], false, t, nda, ndb, pa, la, pb, lb);
-                    v += (u128)(u64)cf << (8 * (4 * h + ii));
+                    const u32 u = 4 * h + ii;
+                    const u64 t = 8 * (u64)j + u;
+                    const i64 cf = column_exact((i64)acc[i][mi][4 * m + ii], false, t, u, nda, ndb, A1, A2, B1, B2);
+                    v += (u128)(u64)cf << (8 * u);
                 }
                 plo[mi][m] = (u64)v;
                 phi[mi][m] = (u64)(v >> 64);
@@ -543,21 +575,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
-// Column sums from the split MFMA kernel -> exact unsigned sums -> limb lo / shifted hi.
-__global__ void k_fold_mfma_cols(const u64 *__restrict__ col, const u64 *__restrict__ a, const u64 *__restrict__ b,
-                                 const u32 *__restrict__ lpa, const u32 *__restrict__ lpb, u64 na, u64 nb, u64 total,
-                                 u64 *__restrict__ LO, u64 *__restrict__ HS) {
-    const u64 P = na + nb;
+// Slice sums from the split MFMA kernel -> exact unsigned column sums -> limb lo /
+// shifted hi.
+__global__ void k_fold_mfma_cols(const int *__restrict__ part, u32 nslices, const u64 *__restrict__ a,
+                                 const u64 *__restrict__ b, const u64 *__restrict__ lpa, const u64 *__restrict__ lpb,
+                                 u64 na, u64 nb, u64 npairs, u64 *__restrict__ LO, u64 *__restrict__ HS) {
+    const u64 P = na + nb, total = P * npairs, sstride = npairs * 8 * P;
     for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
         const u64 p = idx / P, j = idx - p * P;
         const u64 *pa = a + p * na, *pb = b + p * nb;
-        const u32 *la = lpa + p * (na + 1), *lb = lpb + p * (nb + 1);
-        const u64 *pc = col + p * 8 * P;
+        const u64 *la = lpa + p * (na + 1), *lb = lpb + p * (nb + 1);
+        const int *pc = part + p * 8 * P + 8 * j;
+        const ColTerm A1 = col_term(pa, la, na, (i64)j), A2 = col_term(pa, la, na, (i64)j - (i64)nb);
+        const ColTerm B1 = col_term(pb, lb, nb, (i64)j), B2 = col_term(pb, lb, nb, (i64)j - (i64)na);
+        i64 m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (u32 sl = 0; sl < nslices; ++sl)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) m[u] += pc[sl * sstride + u];
         u128 V = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const u64 t = 8 * j + u;
-            const i64 cf = column_exact((i64)pc[t], true, t, 8 * na, 8 * nb, pa, la, pb, lb);
+        for (u32 u = 0; u < 8; ++u) {
+            const i64 cf = column_exact(m[u], true, 8 * j + u, u, 8 * na, 8 * nb, A1, A2, B1, B2);
             V += (u128)(u64)cf << (8 * u);
         }
         LO[idx] = (u64)V;
@@ -568,12 +606,13 @@ __global__ void k_fold_mfma_cols(const u64 *__restrict__ col, const u64 *__restr
 
 // ---------------------------------------------------------------- workspace ----
 struct LargeLayout {
-    size_t colLo, colHi, col64, lpa, lpb, seg, LO, HS, total;
+    size_t colLo, colHi, part, lpa, lpb, seg, LO, HS, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, bool split) {
+static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, u32 nslices) {
+    const bool split = nslices > 1;
     LargeLayout L{};
     const u64 P = na + nb;
     size_t off = 0;
@@ -584,13 +623,13 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, bool split
         off = align256(off + npairs * 2 * P * 8);
     } else {
         if (split) {
-            L.col64 = off;
-            off = align256(off + npairs * 8 * P * 8);
+            L.part = off;
+            off = align256(off + (size_t)nslices * npairs * 8 * P * 4);
         }
         L.lpa = off;
-        off = align256(off + npairs * (na + 1) * 4);
+        off = align256(off + npairs * (na + 1) * 8);
         L.lpb = off;
-        off = align256(off + npairs * (nb + 1) * 4);
+        off = align256(off + npairs * (nb + 1) * 8);
         L.seg = off;
         off = align256(off + npairs * 2 * ((std::max(na, nb) + PREP_SEG - 1) / PREP_SEG + 1) * 4);
     }
@@ -641,8 +680,8 @@ int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
 size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form) {
     if (na == 0 || nb == 0 || npairs == 0) return 0;
     form = mul_pick_form(ctx, na, nb, form);
-    if (na + nb <= 256) return 0;
-    return large_layout(na, nb, npairs, form, form == BN_MUL_MFMA && mfma_plan(ctx, na, nb, npairs).nslices > 1).total;
+    if (na + nb <= 256 || (form == BN_MUL_MAD && na + nb <= SMALL_MAD_MAX_P)) return 0;
+    return large_layout(na, nb, npairs, form, form == BN_MUL_MFMA ? mfma_plan(ctx, na, nb, npairs).nslices : 1u).total;
 }
 
 bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 na, u64 nb, u64 npairs, int form,
@@ -651,7 +690,7 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
     const u64 P = na + nb;
     if (na == 0 || nb == 0) return launch_fill_u64(r, P * npairs, 0, s);
     form = mul_pick_form(ctx, na, nb, form);
-    if (P <= 256) {
+    if (P <= 256 || (form == BN_MUL_MAD && P <= SMALL_MAD_MAX_P)) {
         const u64 blocks = (npairs + 3) / 4;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
         if (form == BN_MUL_MFMA)
@@ -663,14 +702,20 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         else if (P <= 128)
             hipLaunchKernelGGL((k_mul_small<BN_MUL_MAD, 2>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
                                (u32)nb, npairs);
-        else
+        else if (P <= 256)
             hipLaunchKernelGGL((k_mul_small<BN_MUL_MAD, 4>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
+                               (u32)nb, npairs);
+        else if (P <= 512)
+            hipLaunchKernelGGL((k_mul_small<BN_MUL_MAD, 8>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
+                               (u32)nb, npairs);
+        else
+            hipLaunchKernelGGL((k_mul_small<BN_MUL_MAD, 16>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
                                (u32)nb, npairs);
         return bn_launch_status();
     }
     const MfmaPlan mp = mfma_plan(ctx, na, nb, npairs);
     const bool split = form == BN_MUL_MFMA && mp.nslices > 1;
-    const LargeLayout L = large_layout(na, nb, npairs, form, split);
+    const LargeLayout L = large_layout(na, nb, npairs, form, split ? mp.nslices : 1u);
     bn_status st = bn_ensure(ctx, ctx->work, L.total, s);
     if (st != BN_OK) return st;
     char *ws = static_cast<char *>(ctx->work.ptr);
@@ -706,8 +751,8 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         hipLaunchKernelGGL(k_fold_mad, dim3((u32)fold_blocks), dim3(256), 0, s, colLo, colHi, P, total, LO, HS);
         if ((st = bn_launch_status()) != BN_OK) return st;
     } else {
-        u32 *lpa = reinterpret_cast<u32 *>(ws + L.lpa);
-        u32 *lpb = reinterpret_cast<u32 *>(ws + L.lpb);
+        u64 *lpa = reinterpret_cast<u64 *>(ws + L.lpa);
+        u64 *lpb = reinterpret_cast<u64 *>(ws + L.lpb);
         u32 *seg = reinterpret_cast<u32 *>(ws + L.seg);
         const u64 nseg = (std::max(na, nb) + PREP_SEG - 1) / PREP_SEG;
         const u64 prep_blocks = nseg * 2 * npairs;
@@ -724,13 +769,12 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         if (blocks > 0x7fffffffull) return BN_ERANGE;
         const size_t lds = (size_t)64 * (D + 3) + (size_t)80 * (128 * NW + D);
         if (split) {
-            u64 *col = reinterpret_cast<u64 *>(ws + L.col64);
-            if ((st = launch_fill_u64(col, npairs * 8 * P, 0, s)) != BN_OK) return st;
+            int *part = reinterpret_cast<int *>(ws + L.part);
             hipLaunchKernelGGL((k_mul_large_mfma<NW, true>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb, npairs,
-                               lpa, lpb, D, (u32)mp.ngroups, mp.nslices, LO, HS, col);
+                               lpa, lpb, D, (u32)mp.ngroups, mp.nslices, LO, HS, part);
             if ((st = bn_launch_status()) != BN_OK) return st;
-            hipLaunchKernelGGL(k_fold_mfma_cols, dim3((u32)fold_blocks), dim3(256), 0, s, col, a, b, lpa, lpb, na, nb,
-                               total, LO, HS);
+            hipLaunchKernelGGL(k_fold_mfma_cols, dim3((u32)fold_blocks), dim3(256), 0, s, part, mp.nslices, a, b, lpa,
+                               lpb, na, nb, npairs, LO, HS);
         } else {
             hipLaunchKernelGGL((k_mul_large_mfma<NW, false>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb,
                                npairs, lpa, lpb, D, (u32)mp.ngroups, 1u, LO, HS, nullptr);

@@ -54,8 +54,9 @@ def test_small_pathological(bnctx, form, n):
     _check(bnctx, pa.reshape(-1), pb.reshape(-1), n, n, pa.shape[0], form)
 
 
-LARGE = [(129, 128), (300, 1), (1, 300), (257, 3), (3, 257), (500, 500), (1000, 999), (1024, 1024),
-         (4099, 1031), (1031, 4099), (4096, 4096)]
+LARGE = [(129, 128), (300, 1), (1, 300), (257, 3), (3, 257), (256, 256), (200, 312), (500, 500), (511, 513),
+         (1000, 24), (7, 1017), (512, 512), (513, 512), (1000, 999), (1024, 1024), (4099, 1031), (1031, 4099),
+         (4096, 4096)]
 
 
 @pytest.mark.parametrize("form", ["mad", "mfma"])
@@ -67,7 +68,7 @@ def test_large_random(bnctx, form, na, nb):
 
 
 @pytest.mark.parametrize("form", ["mad", "mfma"])
-@pytest.mark.parametrize("n", [300, 2048])
+@pytest.mark.parametrize("n", [300, 480, 2048])
 def test_large_pathological(bnctx, form, n):
     pa, pb = wl.pathological(n, 1, seed=n)
     _check(bnctx, pa.reshape(-1), pb.reshape(-1), n, n, pa.shape[0], form)
