@@ -202,31 +202,56 @@ __device__ __forceinline__ v4i toeplitz_combine(const TWords &t, u32 s) {
     return f;
 }
 
+// Exact unsigned column sums from the MFMA sums of signed digits, eight columns at a
+// time: the columns t = 8 j + u (u < 8) of limb j.  With nda, ndb the digit counts,
+// ilo = max(0, t + 1 - ndb) and ihi = min(t, nda - 1), the digits meeting in column t
+// are a[ilo..ihi] and b[t-ihi..t-ilo], cnt = ihi - ilo + 1 of each (0 past the
+// product), and
+//     C = M + 128 (S_a + S_b) - 16384 cnt,
+//     S_a = PA(min(t + 1, nda)) - PA(max(0, t + 1 - ndb)),
+//     S_b = PB(min(t + 1, ndb)) - PB(max(0, t + 1 - nda)),
+// with PA, PB the digit prefix sums.  Every argument is t + 1 + (0, -ndb, 0, -nda),
+// i.e. 8 q + u + 1 for q = j, j - nb, j, j - na: one prefix-table entry and one limb
+// per term give all eight columns, PX(8 q + u + 1) = lp[q] + (digits 0..u of limb q),
+// with limbs outside the operand read as zero and lp clamped to [0, n] (which is
+// exactly the clamping of the arguments above).
+struct ColTerm {
+    u64 pre;   // lp[q] (clamped)
+    u64 limb;  // limb q (0 outside the operand)
+};
+template <class LP>
+__device__ __forceinline__ ColTerm col_term(const u64 *__restrict__ x, const LP *lp, u64 n, i64 q) {
+    ColTerm c;
+    c.pre = (u64)lp[q < 0 ? 0 : (q > (i64)n ? (i64)n : q)];
+    c.limb = (q >= 0 && q < (i64)n) ? x[q] : 0ull;
+    return c;
+}
+// digits 0..u of a limb
+__device__ __forceinline__ u64 low_digits(u64 limb, u32 u) {
+    return bytesum64(u >= 7 ? limb : (limb & ((1ull << (8 * (u + 1))) - 1)));
+}
+// Column sum of column t = 8 j + u from its raw MFMA sum.  When the accumulation was
+// plain int32 (wide == false) the register holds the true sum M modulo 2^32; M lies in
+// [-16256 cnt, 16384 cnt], an interval narrower than 2^32 for cnt <= 131586, so M is
+// recovered exactly.
+__device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u32 u, u64 nda, u64 ndb, const ColTerm &A1,
+                                            const ColTerm &A2, const ColTerm &B1, const ColTerm &B2) {
+    const i64 ilo = t + 1 > ndb ? (i64)(t + 1 - ndb) : 0;
+    const i64 ihi = t < nda - 1 ? (i64)t : (i64)nda - 1;
+    const i64 cnt = ihi >= ilo ? ihi - ilo + 1 : 0;
+    i64 m = raw;
+    if (!wide) {
+        m = (i64)(int)(u32)raw;
+        if (m < -16256 * cnt) m += (i64)1 << 32;
+    }
+    const i64 sa = (i64)((A1.pre + low_digits(A1.limb, u)) - (A2.pre + low_digits(A2.limb, u)));
+    const i64 sb = (i64)((B1.pre + low_digits(B1.limb, u)) - (B2.pre + low_digits(B2.limb, u)));
+    return m + 128 * (sa + sb) - 16384 * cnt;
+}
+
 // Accumulator element (reg g of lane l) -> (row rr, column x) of the 32x32 tile.
 __device__ __forceinline__ u32 acc_row(int g, int lane) { return (u32)((g & 3) + 4 * (lane >> 5) + 8 * (g >> 2)); }
 
-// Sum of the unsigned digits x in [0, X) of an operand, from a per-limb prefix table
-// lp[k] = sum of the digits of limbs < k.
-__device__ __forceinline__ i64 digit_prefix(const u64 *__restrict__ limbs, const u32 *__restrict__ lp, u64 x) {
-    const u64 k = x >> 3;
-    const u32 rem = (u32)(x & 7);
-    i64 s = lp[k];
-    if (rem) s += bytesum64(limbs[k] & ((1ull << (8 * rem)) - 1));
-    return s;
-}
-
-// Exact unsigned column sum from the signed-digit MFMA sum m of column t.
-__device__ __forceinline__ i64 column_fix(i64 m, u64 t, u64 nda, u64 ndb, const u64 *__restrict__ a,
-                                          const u32 *__restrict__ lpa, const u64 *__restrict__ b,
-                                          const u32 *__restrict__ lpb) {
-    const u64 ilo = t + 1 > ndb ? t + 1 - ndb : 0;
-    const u64 ihi = t < nda - 1 ? t : nda - 1;
-    if (ilo > ihi) return 0;
-    const i64 sa = digit_prefix(a, lpa, ihi + 1) - digit_prefix(a, lpa, ilo);
-    const i64 sb = digit_prefix(b, lpb, t - ilo + 1) - digit_prefix(b, lpb, t - ihi);
-    const i64 cnt = (i64)(ihi - ilo + 1);
-    return m + 128 * (sa + sb) - 16384 * cnt;
-}
 
 // ------------------------------------------------- small products, MFMA form ----
 constexpr u64 BN_XOR80 = 0x8080808080808080ull;
@@ -319,14 +344,19 @@ __device__ __noinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 
     for (int blk = 0; blk < 2; ++blk) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
+            const i64 j = 4 * (32 * blk + (i64)x) + m;
             u128 v = 0;
+            if (j < (i64)P) {
+                const ColTerm A1 = col_term(a, lpa, na, j), A2 = col_term(a, lpa, na, j - (i64)nb);
+                const ColTerm B1 = col_term(b, lpb, nb, j), B2 = col_term(b, lpb, nb, j - (i64)na);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int g = 4 * m + i;
-                const int raw = blk ? acc1[g] : acc0[g];
-                const u64 t = 32ull * (32 * blk + x) + 8 * m + 4 * h + i;
-                const i64 cf = (t < 8ull * P) ? column_fix(raw, t, nda, ndb, a, lpa, b, lpb) : 0;
-                v += (u128)(u64)cf << (8 * (4 * h + i));
+                for (int i = 0; i < 4; ++i) {
+                    const int g = 4 * m + i;
+                    const u32 u = 4 * h + i;
+                    const int raw = blk ? acc1[g] : acc0[g];  // exact: at most 1024 products
+                    const i64 cf = column_exact(raw, true, 8 * (u64)j + u, u, nda, ndb, A1, A2, B1, B2);
+                    v += (u128)(u64)cf << (8 * u);
+                }
             }
             plo[blk][m] = (u64)v;
             phi[blk][m] = (u64)(v >> 64);

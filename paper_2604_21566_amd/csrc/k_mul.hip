@@ -214,52 +214,6 @@ __device__ __forceinline__ u32 middle_out(u32 k, u32 n) {
     return (k & 1) ? m + (k + 1) / 2 : m - k / 2;
 }
 
-// Exact unsigned column sums from the MFMA sums of signed digits, eight columns at a
-// time: the columns t = 8 j + u (u < 8) of limb j.  With nda, ndb the digit counts,
-// ilo = max(0, t + 1 - ndb) and ihi = min(t, nda - 1), the digits meeting in column t
-// are a[ilo..ihi] and b[t-ihi..t-ilo], cnt = ihi - ilo + 1 of each (0 past the
-// product), and
-//     C = M + 128 (S_a + S_b) - 16384 cnt,
-//     S_a = PA(min(t + 1, nda)) - PA(max(0, t + 1 - ndb)),
-//     S_b = PB(min(t + 1, ndb)) - PB(max(0, t + 1 - nda)),
-// with PA, PB the digit prefix sums.  Every argument is t + 1 + (0, -ndb, 0, -nda),
-// i.e. 8 q + u + 1 for q = j, j - nb, j, j - na: one prefix-table entry and one limb
-// per term give all eight columns, PX(8 q + u + 1) = lp[q] + (digits 0..u of limb q),
-// with limbs outside the operand read as zero and lp clamped to [0, n] (which is
-// exactly the clamping of the arguments above).
-struct ColTerm {
-    u64 pre;   // lp[q] (clamped)
-    u64 limb;  // limb q (0 outside the operand)
-};
-__device__ __forceinline__ ColTerm col_term(const u64 *__restrict__ x, const u64 *__restrict__ lp, u64 n, i64 q) {
-    ColTerm c;
-    c.pre = lp[q < 0 ? 0 : (q > (i64)n ? (i64)n : q)];
-    c.limb = (q >= 0 && q < (i64)n) ? x[q] : 0ull;
-    return c;
-}
-// digits 0..u of a limb
-__device__ __forceinline__ u64 low_digits(u64 limb, u32 u) {
-    return bytesum64(u >= 7 ? limb : (limb & ((1ull << (8 * (u + 1))) - 1)));
-}
-// Column sum of column t = 8 j + u from its raw MFMA sum.  When the accumulation was
-// plain int32 (wide == false) the register holds the true sum M modulo 2^32; M lies in
-// [-16256 cnt, 16384 cnt], an interval narrower than 2^32 for cnt <= 131586, so M is
-// recovered exactly.
-__device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u32 u, u64 nda, u64 ndb, const ColTerm &A1,
-                                            const ColTerm &A2, const ColTerm &B1, const ColTerm &B2) {
-    const i64 ilo = t + 1 > ndb ? (i64)(t + 1 - ndb) : 0;
-    const i64 ihi = t < nda - 1 ? (i64)t : (i64)nda - 1;
-    const i64 cnt = ihi >= ilo ? ihi - ilo + 1 : 0;
-    i64 m = raw;
-    if (!wide) {
-        m = (i64)(int)(u32)raw;
-        if (m < -16256 * cnt) m += (i64)1 << 32;
-    }
-    const i64 sa = (i64)((A1.pre + low_digits(A1.limb, u)) - (A2.pre + low_digits(A2.limb, u)));
-    const i64 sb = (i64)((B1.pre + low_digits(B1.limb, u)) - (B2.pre + low_digits(B2.limb, u)));
-    return m + 128 * (sa + sb) - 16384 * cnt;
-}
-
 template <class T>
 using lds_cptr = const __attribute__((address_space(3))) T *;  // read-only pointer into LDS
 

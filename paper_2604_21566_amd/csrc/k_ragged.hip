@@ -188,7 +188,7 @@ bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a
         if (st != BN_OK) return st;
     }
     if (nmfma) {
-        hipLaunchKernelGGL(k_mul_ragged_mfma, dim3(persistent_blocks(ctx, nmfma, 2)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_mul_ragged_mfma, dim3(persistent_blocks(ctx, nmfma, 4)), dim3(256), 0, s,
                            pl->d_items + nmad, nmfma, r, a, b);
         bn_status st = bn_launch_status();
         if (st != BN_OK) return st;
