@@ -399,6 +399,17 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         c5["mfma_frac_of_measured_int8"] = c5["mfma_int8_TOPS"] * 1e12 / mfma_rate
         c5["mad_frac_of_measured_mac96"] = c5["mad_limb_products_per_s"] * 4 / mac_rate
         c5["mfma_over_mad"] = c5["mad_ms"] / c5["mfma_ms"]
+        # Karatsuba levels above the MFMA schoolbook kernel (same products; the rate is
+        # stated in schoolbook limb products per second for comparison)
+        kar = {}
+        for levels in (1, 2, 3):
+            ms, _ = gpu_time(lambda: bn.bn_mul_karatsuba_n_batch(ctx, tr, ta, tb, n5, 64, levels, "mfma"), 3, 1)
+            kar[f"levels{levels}_ms"] = ms
+            kar[f"levels{levels}_limb_products_per_s"] = 64.0 * n5 * n5 / (ms * 1e-3)
+        best = min((1, 2, 3), key=lambda l: kar[f"levels{l}_ms"])
+        kar["best_levels"] = best
+        kar["best_over_schoolbook_mfma"] = c5["mfma_ms"] / kar[f"levels{best}_ms"]
+        c5["karatsuba_mfma"] = kar
         res["c5"] = c5
 
     # ---- crossover sweep: square products

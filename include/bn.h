@@ -134,6 +134,22 @@ bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const u
 bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na,
                          size_t nb, size_t npairs, int form, bn_stream stream);
 
+/* Uniform batch of square products through `levels` Karatsuba levels above the
+ * schoolbook kernels of `form` (the recursion the paper's libraries put above the
+ * base case, App. A, Algorithm 4): with k = m/2, A = A_H X^k + A_L, B likewise,
+ * P1 = A_H B_H, P0 = A_L B_L, P2 = sign(A_H-A_L) sign(B_H-B_L) |A_H-A_L| |B_H-B_L|,
+ * A B = P1 X^(2k) + (P1 + P0 - P2) X^k + P0.  Each level turns N products of m limbs
+ * into 3N of m/2 limbs; the bottom level is one bn_mul_n_batch-style launch, the
+ * splits and combines are batched add/sub passes.  Pair p: a + p*n, b + p*n, product
+ * at r + 2*p*n (exactly 2n limbs).  levels = 0 is bn_mul_n_batch; n must be a
+ * multiple of 2^levels and levels <= BN_KARATSUBA_MAX_LEVELS (else BN_EINVAL).  r must
+ * not overlap a or b (BN_EALIAS).  The context keeps a workspace of about
+ * 100 n npairs (3/2)^levels bytes across calls (grown with a device synchronisation;
+ * BN_ECAPTURE while a stream capture is active and it would have to grow). */
+#define BN_KARATSUBA_MAX_LEVELS 8
+bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                                   size_t npairs, int levels, int form, bn_stream stream);
+
 /* ------------------------------------------------- ragged batches + plans ---- */
 
 /* One pair of a ragged batch: offsets in limbs into pooled device arrays. */

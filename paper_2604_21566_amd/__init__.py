@@ -70,6 +70,7 @@ _PROTOS = {
     "bn_sub_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
     "bn_mul": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _i, _vp]),
     "bn_mul_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _sz, _i, _vp]),
+    "bn_mul_karatsuba_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _i, _i, _vp]),
     "bn_plan_mul_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, _i, ctypes.POINTER(_vp)]),
     "bn_plan_add_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, ctypes.POINTER(_vp)]),
     "bn_plan_destroy": (_i, [_vp]),
@@ -250,6 +251,11 @@ def bn_mul(ctx, r, a, b, form=BN_MUL_AUTO, stream=None):
 def bn_mul_n_batch(ctx, r, a, b, na: int, nb: int, npairs: int, form=BN_MUL_AUTO, stream=None):
     _ck(lib().bn_mul_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), na, nb, npairs, _form(form),
                              _stream(stream)), "bn_mul_n_batch")
+
+
+def bn_mul_karatsuba_n_batch(ctx, r, a, b, n: int, npairs: int, levels: int, form=BN_MUL_AUTO, stream=None):
+    _ck(lib().bn_mul_karatsuba_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, int(levels),
+                                       _form(form), _stream(stream)), "bn_mul_karatsuba_n_batch")
 
 
 # ------------------------------------------------------------------ ragged ----

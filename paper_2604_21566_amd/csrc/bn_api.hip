@@ -119,6 +119,7 @@ bn_status bn_destroy(bn_ctx *ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->status.ptr) (void)hipFree(ctx->status.ptr);
     if (ctx->work.ptr) (void)hipFree(ctx->work.ptr);
+    if (ctx->kwork.ptr) (void)hipFree(ctx->kwork.ptr);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
     delete ctx;
     return BN_OK;
@@ -228,6 +229,16 @@ bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
     if (st != BN_OK) return st;
     DeviceGuard g(ctx->device);
     return launch_mul_batch(ctx, r, a, b, na, nb, npairs, form, S(stream));
+}
+
+bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                                   size_t npairs, int levels, int form, bn_stream stream) {
+    bn_status st = mul_args(ctx, r, a, b, n, n, npairs, form);
+    if (st != BN_OK) return st;
+    if (levels < 0 || levels > BN_KARATSUBA_MAX_LEVELS) return BN_EINVAL;
+    if (n && (n % ((size_t)1 << levels))) return BN_EINVAL;
+    DeviceGuard g(ctx->device);
+    return launch_mul_karatsuba(ctx, r, a, b, n, npairs, levels, form, S(stream));
 }
 
 // ------------------------------------------------------------------ ragged ----

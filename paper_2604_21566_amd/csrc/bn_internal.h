@@ -66,6 +66,8 @@ struct bn_ctx {
     ScanCtl *ctl = nullptr;     // device control block
     DevBuf status;              // look-back status words
     DevBuf work;                // mul column accumulators / folded limbs
+    DevBuf kwork;               // Karatsuba operand, product and combine arrays
+    u64 host_epoch = 1ull << 61;  // epochs of chained scans launched outside a capture
     Tuning tune;
 };
 
@@ -110,6 +112,11 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
                            int form, hipStream_t s);
 size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form);
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form);
+
+// ---- Karatsuba levels (k_karatsuba.hip) ----
+bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, int levels,
+                               int form, hipStream_t s);
+size_t karatsuba_workspace_bytes(u64 n, u64 npairs, int levels);
 
 // ---- ragged (k_ragged.hip) ----
 bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int form, bn_plan **plan);

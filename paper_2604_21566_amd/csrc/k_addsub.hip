@@ -90,6 +90,7 @@ struct ScanGeom {
     u64 n;         // segment (pair) length
     int nshift;    // log2(n) if n is a power of two, else -1
     u64 TL;        // limbs per tile
+    u64 epoch;     // chained launches: this launch's epoch, or 0 to read it from the control block
 };
 
 // (generate, propagate) aggregate of tile u computed from the operands by one
@@ -189,10 +190,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     // Tile t is workgroup t.  chain == 0: every tile starts a segment (the tile
     // length is a multiple of the segment length), so no tile needs its
     // predecessor's carry and the look-back machinery is skipped.  chain == 1:
-    // tiles publish status words tagged with the launch epoch (a plain load: the
-    // epoch only changes between launches) and look back.
+    // tiles publish status words tagged with the launch epoch and look back.  The
+    // epoch comes with the launch, or (launches recorded into a graph, which replay
+    // the same arguments) from the control block, which a one-thread kernel after
+    // the launch moves on (a plain load: it only changes between launches).
     const u64 t = blockIdx.x;
-    const u64 epoch = chain ? ctl->epoch : 0;
+    const u64 epoch = chain ? (G.epoch ? G.epoch : ctl->epoch) : 0;
     constexpr u64 TL = (u64)WAVES * ROWS * 128;
     const u64 N = G.N, n = G.n;
     const u64 idx0 = t * TL + (u64)w * ROWS * 128 + 2 * (u64)lane;
@@ -499,12 +502,18 @@ bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
         f = sub ? k_flat_scan<true, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false>
                 : k_flat_scan<false, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false>;
     if (!f) return BN_EINVAL;
-    ScanGeom G{N, n, -1, TL};
+    // Chained launches outside a stream capture take a fresh epoch from the host
+    // counter (its range, from 2^61 up, is disjoint from the control block's, which
+    // counts from 1); captured ones read the control block and bump it after.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (chain && hipStreamIsCapturing(s, &cs) != hipSuccess) return BN_EHIP;
+    const bool captured = cs != hipStreamCaptureStatusNone;
+    ScanGeom G{N, n, -1, TL, (chain && !captured) ? ++ctx->host_epoch : 0};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
                        ctx->ctl, (u64 *)ctx->status.ptr, ctx->tune.spin_limit, ctx->tune.debug_flags);
     bn_status st = bn_launch_status();
-    if (st != BN_OK || !chain) return st;
+    if (st != BN_OK || !captured) return st;
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, ctx->ctl);
     return bn_launch_status();
 }

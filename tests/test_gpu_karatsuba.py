@@ -1,0 +1,107 @@
+"""Karatsuba levels above the schoolbook kernels: bit-exact against the CPU oracle's
+schoolbook product (the product is unique, so the recursion must reproduce it)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_21566_amd as bn
+from _bigint import to_int
+from conftest import announce
+from paper_2604_21566_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+D = bn.to_device
+H = bn.to_host
+MAX = 2 ** 64 - 1
+
+
+def _kmul(ctx, a, b, n, npairs, levels, form):
+    announce("karatsuba", form, f"n={n}", f"npairs={npairs}", f"levels={levels}")
+    tr = torch.full((2 * n * npairs,), -1, dtype=torch.int64, device="cuda")
+    bn.bn_mul_karatsuba_n_batch(ctx, tr, D(a), D(b), n, npairs, levels, form)
+    torch.cuda.synchronize()
+    return H(tr)
+
+
+def _check(ctx, a, b, n, npairs, levels, form):
+    r = _kmul(ctx, a, b, n, npairs, levels, form)
+    rr = oracle.mul_batch(a, b, n, n, npairs)
+    bad = np.nonzero(r != rr)[0]
+    assert bad.size == 0, f"{form} n={n} levels={levels}: {bad.size} bad limbs, first at {bad[0]}"
+
+
+SHAPES = [(2, 3, 1), (8, 5, 1), (8, 3, 3), (64, 7, 2), (96, 4, 5), (256, 4, 1), (1024, 3, 2), (2048, 2, 3),
+          (4096, 2, 1), (640, 9, 4)]
+
+
+@pytest.mark.parametrize("form", ["auto", "mad", "mfma"])
+@pytest.mark.parametrize("n,npairs,levels", SHAPES)
+def test_random(bnctx, form, n, npairs, levels):
+    g = np.random.default_rng(n * 31 + levels)
+    a = g.integers(0, MAX, n * npairs, dtype=np.uint64, endpoint=True)
+    b = g.integers(0, MAX, n * npairs, dtype=np.uint64, endpoint=True)
+    _check(bnctx, a, b, n, npairs, levels, form)
+
+
+def _halves(lo, hi):
+    return np.concatenate([lo, hi])
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_signs_and_carries(bnctx, form, levels):
+    """Every sign pattern of the differences (A_H >, =, < A_L and the same for B),
+    all-ones operands (the largest carries in the combine), zeros, and the
+    pathological patterns."""
+    n = 64
+    g = np.random.default_rng(levels)
+    ones = np.full(n // 2, MAX, np.uint64)
+    zero = np.zeros(n // 2, np.uint64)
+    rnd = lambda: g.integers(0, MAX, n // 2, dtype=np.uint64, endpoint=True)
+    x = rnd()
+    y = x.copy()
+    y[-1] ^= np.uint64(1)  # differs in the top limb only
+    halves = [_halves(x, x), _halves(x, y), _halves(y, x), _halves(ones, ones), _halves(zero, ones),
+              _halves(ones, zero), _halves(zero, zero), _halves(rnd(), rnd())]
+    A = np.concatenate([h for h in halves for _ in halves])
+    B = np.concatenate([h for _ in halves for h in halves])
+    npairs = len(halves) ** 2
+    _check(bnctx, A, B, n, npairs, levels, form)
+    pa, pb = wl.pathological(n, 1, seed=levels)
+    _check(bnctx, pa.reshape(-1), pb.reshape(-1), n, pa.shape[0], levels, form)
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_c5_full(bnctx, levels):
+    """64 pairs x 16384 limbs (incl. all-ones x all-ones and zero x zero): sampled pairs
+    against the oracle, every pair by residues."""
+    n, npairs = 16384, 64
+    a, b = wl.c5()
+    r = _kmul(bnctx, a, b, n, npairs, levels, "mfma")
+    for p in (0, 1, 2, 63):
+        rr = oracle.mul(a[p * n:(p + 1) * n], b[p * n:(p + 1) * n])
+        assert (r[p * 2 * n:(p + 1) * 2 * n] == rr).all(), f"pair {p}"
+    for p in range(npairs):
+        A = to_int(a[p * n:(p + 1) * n])
+        B = to_int(b[p * n:(p + 1) * n])
+        R = to_int(r[p * 2 * n:(p + 1) * 2 * n])
+        for q in (65537, 998244353, (1 << 61) - 1):
+            assert (A % q) * (B % q) % q == R % q, f"pair {p} mod {q}"
+
+
+def test_errors(bnctx):
+    ta = torch.zeros(96, dtype=torch.int64, device="cuda")
+    tr = torch.zeros(192, dtype=torch.int64, device="cuda")
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 1, 6)  # 96 is not a multiple of 64
+    assert e.value.status == bn.BN_EINVAL
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 1, 9)  # more levels than allowed
+    assert e.value.status == bn.BN_EINVAL
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_mul_karatsuba_n_batch(bnctx, tr, tr[:96], ta, 96, 1, 1)  # r overlaps a
+    assert e.value.status == bn.BN_EALIAS
+    # empty batch and n = 0 are no-ops
+    bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 0, 2)
+    bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 0, 3, 2)
