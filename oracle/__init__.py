@@ -56,6 +56,9 @@ def _load():
     for f in (lib.bnref_add_n_batch, lib.bnref_sub_n_batch):
         f.restype = None
         f.argtypes = [_u64p, _u64p, _u64p, _sz, _sz, _u64p]
+    for f in (lib.bnref_add_nc_batch, lib.bnref_sub_nc_batch):
+        f.restype = None
+        f.argtypes = [_u64p, _u64p, _u64p, _sz, _sz, _u64p, _u64p]
     lib.bnref_mul_n_batch.restype = None
     lib.bnref_mul_n_batch.argtypes = [_u64p, _u64p, _u64p, _sz, _sz, _sz]
     lib.bnref_mul_ragged.restype = None
@@ -125,6 +128,34 @@ def sub_batch(a: np.ndarray, b: np.ndarray, n: int):
     r = np.empty_like(a)
     c = np.empty(npairs, dtype=np.uint64)
     _load().bnref_sub_n_batch(_p(r), _p(a), _p(b), n, npairs, _p(c))
+    return r, c
+
+
+def add_nc_batch(a: np.ndarray, b: np.ndarray, n: int, cin: np.ndarray):
+    """Uniform batch with a carry into limb 0 of pair p (cin[p] in {0, 1})."""
+    a, b, cin = _c(a), _c(b), _c(cin)
+    if a.size != b.size or (n and a.size % n):
+        raise ValueError("bad batch shape")
+    npairs = a.size // n if n else 0
+    if cin.size != npairs:
+        raise ValueError("one carry-in per pair")
+    r = np.empty_like(a)
+    c = np.empty(npairs, dtype=np.uint64)
+    _load().bnref_add_nc_batch(_p(r), _p(a), _p(b), n, npairs, _p(cin), _p(c))
+    return r, c
+
+
+def sub_nc_batch(a: np.ndarray, b: np.ndarray, n: int, bin_: np.ndarray):
+    """Uniform batch with a borrow into limb 0 of pair p (bin_[p] in {0, 1})."""
+    a, b, bin_ = _c(a), _c(b), _c(bin_)
+    if a.size != b.size or (n and a.size % n):
+        raise ValueError("bad batch shape")
+    npairs = a.size // n if n else 0
+    if bin_.size != npairs:
+        raise ValueError("one borrow-in per pair")
+    r = np.empty_like(a)
+    c = np.empty(npairs, dtype=np.uint64)
+    _load().bnref_sub_nc_batch(_p(r), _p(a), _p(b), n, npairs, _p(bin_), _p(c))
     return r, c
 
 

@@ -102,6 +102,52 @@ void bnref_sub_n_batch(uint64_t *r, const uint64_t *a, const uint64_t *b,
     }
 }
 
+/*
+ * With a carry (borrow) into limb 0: the W-limb addition step of Alg. 1 takes a
+ * carry-in c_in (Sec. 3.1); the recurrences above with c_0 = cin (resp. br_0 = bin)
+ * instead of 0.  cin, bin in {0, 1}.
+ */
+uint64_t bnref_add_nc(uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, uint64_t cin)
+{
+    uint64_t c = cin;
+    for (size_t i = 0; i < n; ++i) {
+        u128 t = (u128)a[i] + (u128)b[i] + (u128)c;
+        r[i] = (uint64_t)t;
+        c = (uint64_t)(t >> 64);
+    }
+    return c;
+}
+
+uint64_t bnref_sub_nc(uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, uint64_t bin)
+{
+    uint64_t br = bin;
+    for (size_t i = 0; i < n; ++i) {
+        u128 need = (u128)b[i] + (u128)br;
+        u128 t = (u128)a[i] - need;
+        r[i] = (uint64_t)t;
+        br = ((u128)a[i] < need) ? 1u : 0u;
+    }
+    return br;
+}
+
+void bnref_add_nc_batch(uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                        const uint64_t *cin, uint64_t *carry)
+{
+    for (size_t p = 0; p < npairs; ++p) {
+        uint64_t c = bnref_add_nc(r + p * n, a + p * n, b + p * n, n, cin[p] & 1u);
+        if (carry) carry[p] = c;
+    }
+}
+
+void bnref_sub_nc_batch(uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                        const uint64_t *bin, uint64_t *borrow)
+{
+    for (size_t p = 0; p < npairs; ++p) {
+        uint64_t c = bnref_sub_nc(r + p * n, a + p * n, b + p * n, n, bin[p] & 1u);
+        if (borrow) borrow[p] = c;
+    }
+}
+
 /* pair p: a at p*na, b at p*nb, product at p*(na+nb) */
 void bnref_mul_n_batch(uint64_t *r, const uint64_t *a, const uint64_t *b,
                        size_t na, size_t nb, size_t npairs)

@@ -62,6 +62,27 @@ def test_add_sub_random_vs_int(oracle_mod, n):
         assert to_int(r) == (A - B) % mod and c == int(A < B)
 
 
+@pytest.mark.parametrize("n", [1, 2, 5, 33])
+def test_carry_in_variants_vs_int(oracle_mod, n):
+    """Carry (borrow) into limb 0: r = a + b + c, c_out = floor(.../X^n); r = a - b - c
+    with a borrow out when it is negative.  Includes the all-ones / zero operands
+    where the carry-in alone crosses every limb."""
+    g = np.random.default_rng(77 + n)
+    mod = 1 << (64 * n)
+    ones, zero = np.full(n, MASK64, np.uint64), np.zeros(n, np.uint64)
+    cases = [(_rand(g, n), _rand(g, n)) for _ in range(5)] + [(ones, zero), (zero, zero), (zero, ones),
+                                                                (ones, ones)]
+    a = np.concatenate([x for x, _ in cases] * 2)
+    b = np.concatenate([y for _, y in cases] * 2)
+    cin = np.array([0] * len(cases) + [1] * len(cases), np.uint64)
+    r, c = oracle_mod.add_nc_batch(a, b, n, cin)
+    r2, c2 = oracle_mod.sub_nc_batch(a, b, n, cin)
+    for p in range(2 * len(cases)):
+        A, B, C = to_int(a[p * n:(p + 1) * n]), to_int(b[p * n:(p + 1) * n]), int(cin[p])
+        assert to_int(r[p * n:(p + 1) * n]) == (A + B + C) % mod and int(c[p]) == (A + B + C) // mod
+        assert to_int(r2[p * n:(p + 1) * n]) == (A - B - C) % mod and int(c2[p]) == int(A - B - C < 0)
+
+
 @pytest.mark.parametrize("na,nb", [(0, 3), (3, 0), (1, 1), (1, 7), (7, 1), (4, 4), (5, 5), (13, 29),
                                    (64, 64), (100, 37), (128, 128), (257, 129)])
 def test_mul_random_vs_int(oracle_mod, na, nb):
