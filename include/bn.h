@@ -117,6 +117,34 @@ bn_status bn_add_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
 bn_status bn_sub_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b,
                          size_t n, size_t npairs, uint64_t *borrow_out, bn_stream stream);
 
+/* With a carry (borrow) into limb 0 of every pair: the c_in of Algorithm 1's W-limb
+ * step (Sec. 3.1), which chains additions of more limbs than one call holds.
+ * r_p = (a_p + b_p + cin_p) mod 2^(64n), carry_out[p] = the carry out; sub:
+ * r_p = (a_p - b_p - bin_p) mod 2^(64n), borrow_out[p] = [a_p < b_p + bin_p].
+ * carry_in (device, npairs uint64, bit 0 used) must be given (BN_EINVAL if NULL with
+ * npairs > 0) and must not overlap carry_out or r (BN_EALIAS); r may equal a or b
+ * exactly.  n = 0 copies carry_in to carry_out. */
+bn_status bn_add_nc_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                            const uint64_t *carry_in, uint64_t *carry_out, bn_stream stream);
+bn_status bn_sub_nc_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                            const uint64_t *borrow_in, uint64_t *borrow_out, bn_stream stream);
+
+/* Unequal lengths (na >= nb, else BN_EINVAL): r[0, na) = a + b with b zero-extended
+ * (the shorter operand padded with zero limbs, as in the proof of Theorem 2), carry
+ * out in *carry_out; sub: r = (a - b) mod 2^(64 na) and the borrow.  The low nb limbs
+ * are one scan, the carry then runs through a's top na - nb limbs (a second scan with
+ * b = 0 and the carry as carry-in).  r may equal a exactly (or b when na == nb). */
+bn_status bn_add_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
+                         uint64_t *carry_out, bn_stream stream);
+bn_status bn_sub_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
+                         uint64_t *borrow_out, bn_stream stream);
+
+/* r_p = |a_p - b_p| and sign[p] = [a_p < b_p] (device, may be NULL): the signed
+ * difference the Karatsuba step needs (App. A, Algorithm 4).  b - a goes to the
+ * context's workspace, then a - b to r, then a select; r may equal a or b exactly. */
+bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                             size_t npairs, uint64_t *sign, bn_stream stream);
+
 /* ------------------------------------------------------------ multiply ---- */
 
 #define BN_MUL_AUTO 0 /* pick per size from the tuning table (mad below the crossover) */

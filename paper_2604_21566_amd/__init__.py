@@ -68,6 +68,11 @@ _PROTOS = {
     "bn_sub": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_add_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
     "bn_sub_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
+    "bn_add_nc_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp, _vp]),
+    "bn_sub_nc_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp, _vp]),
+    "bn_add_unequal": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _vp, _vp]),
+    "bn_sub_unequal": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _vp, _vp]),
+    "bn_sub_abs_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
     "bn_mul": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _i, _vp]),
     "bn_mul_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _sz, _i, _vp]),
     "bn_mul_karatsuba_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _i, _i, _vp]),
@@ -251,6 +256,32 @@ def bn_mul(ctx, r, a, b, form=BN_MUL_AUTO, stream=None):
 def bn_mul_n_batch(ctx, r, a, b, na: int, nb: int, npairs: int, form=BN_MUL_AUTO, stream=None):
     _ck(lib().bn_mul_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), na, nb, npairs, _form(form),
                              _stream(stream)), "bn_mul_n_batch")
+
+
+def bn_add_nc_n_batch(ctx, r, a, b, n: int, npairs: int, carry_in, carry_out=None, stream=None):
+    _ck(lib().bn_add_nc_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(carry_in, "carry_in"),
+                                _ptr(carry_out, "carry_out"), _stream(stream)), "bn_add_nc_n_batch")
+
+
+def bn_sub_nc_n_batch(ctx, r, a, b, n: int, npairs: int, borrow_in, borrow_out=None, stream=None):
+    _ck(lib().bn_sub_nc_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs,
+                                _ptr(borrow_in, "borrow_in"), _ptr(borrow_out, "borrow_out"), _stream(stream)),
+        "bn_sub_nc_n_batch")
+
+
+def bn_add_unequal(ctx, r, a, na: int, b, nb: int, carry_out=None, stream=None):
+    _ck(lib().bn_add_unequal(ctx, _ptr(r, "r"), _ptr(a, "a"), na, _ptr(b, "b"), nb, _ptr(carry_out, "carry_out"),
+                             _stream(stream)), "bn_add_unequal")
+
+
+def bn_sub_unequal(ctx, r, a, na: int, b, nb: int, borrow_out=None, stream=None):
+    _ck(lib().bn_sub_unequal(ctx, _ptr(r, "r"), _ptr(a, "a"), na, _ptr(b, "b"), nb, _ptr(borrow_out, "borrow_out"),
+                             _stream(stream)), "bn_sub_unequal")
+
+
+def bn_sub_abs_n_batch(ctx, r, a, b, n: int, npairs: int, sign=None, stream=None):
+    _ck(lib().bn_sub_abs_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(sign, "sign"),
+                                 _stream(stream)), "bn_sub_abs_n_batch")
 
 
 def bn_mul_karatsuba_n_batch(ctx, r, a, b, n: int, npairs: int, levels: int, form=BN_MUL_AUTO, stream=None):

@@ -179,6 +179,31 @@ static bn_status addsub(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, c
     return launch_flat_scan(ctx, sub, r, a, b, n, npairs, carry, S(stream));
 }
 
+static bn_status addsub_nc(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                           size_t npairs, const uint64_t *cin, uint64_t *carry, bn_stream stream) {
+    if (!ctx) return BN_EINVAL;
+    if (!cin && npairs) return BN_EINVAL;
+    if (cin && ((uintptr_t)cin & 7u)) return BN_EINVAL;
+    size_t N;
+    if (mul_overflow(n, npairs, &N) || N > BN_MAX_LIMBS) return BN_ERANGE;
+    bn_status st;
+    if ((st = check_ptr(r, N)) || (st = check_ptr(a, N)) || (st = check_ptr(b, N))) return st;
+    if (carry && ((uintptr_t)carry & 7u)) return BN_EINVAL;
+    const size_t bytes = N * 8;
+    if ((r != a && overlaps(r, bytes, a, bytes)) || (r != b && overlaps(r, bytes, b, bytes))) return BN_EALIAS;
+    if (carry && (overlaps(carry, npairs * 8, r, bytes) || overlaps(carry, npairs * 8, a, bytes) ||
+                  overlaps(carry, npairs * 8, b, bytes) || overlaps(carry, npairs * 8, cin, npairs * 8)))
+        return BN_EALIAS;  // (a segment's carry-in and carry-out may be read and written by different workgroups)
+    if (cin && overlaps(cin, npairs * 8, r, bytes)) return BN_EALIAS;
+    DeviceGuard g(ctx->device);
+    if (N == 0) {  // no limbs: the carry passes through
+        if (!carry || npairs == 0) return BN_OK;
+        return hipMemcpyAsync(carry, cin, npairs * 8, hipMemcpyDeviceToDevice, S(stream)) == hipSuccess ? BN_OK
+                                                                                                : BN_EHIP;
+    }
+    return launch_addsub_nc(ctx, sub, r, a, b, n, npairs, cin, carry, S(stream));
+}
+
 bn_status bn_add(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, uint64_t *carry_out,
                  bn_stream stream) {
     return addsub(ctx, false, r, a, b, n, 1, carry_out, stream);
@@ -197,6 +222,61 @@ bn_status bn_add_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
 bn_status bn_sub_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
                          uint64_t *borrow_out, bn_stream stream) {
     return addsub(ctx, true, r, a, b, n, npairs, borrow_out, stream);
+}
+
+bn_status bn_add_nc_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                            const uint64_t *carry_in, uint64_t *carry_out, bn_stream stream) {
+    return addsub_nc(ctx, false, r, a, b, n, npairs, carry_in, carry_out, stream);
+}
+
+bn_status bn_sub_nc_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
+                            const uint64_t *borrow_in, uint64_t *borrow_out, bn_stream stream) {
+    return addsub_nc(ctx, true, r, a, b, n, npairs, borrow_in, borrow_out, stream);
+}
+
+static bn_status addsub_unequal(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
+                                size_t nb, uint64_t *carry, bn_stream stream) {
+    if (!ctx) return BN_EINVAL;
+    if (na < nb) return BN_EINVAL;
+    if (na > BN_MAX_LIMBS) return BN_ERANGE;
+    bn_status st;
+    if ((st = check_ptr(r, na)) || (st = check_ptr(a, na)) || (st = check_ptr(b, nb))) return st;
+    if (carry && ((uintptr_t)carry & 7u)) return BN_EINVAL;
+    // r may be a exactly, or b exactly when the lengths are equal
+    if ((r != a && overlaps(r, na * 8, a, na * 8)) || (!(r == b && na == nb) && overlaps(r, na * 8, b, nb * 8)))
+        return BN_EALIAS;
+    if (carry && (overlaps(carry, 8, r, na * 8) || overlaps(carry, 8, a, na * 8) || overlaps(carry, 8, b, nb * 8)))
+        return BN_EALIAS;
+    DeviceGuard g(ctx->device);
+    if (na == 0) return carry ? launch_fill_u64(carry, 1, 0, S(stream)) : BN_OK;
+    return launch_addsub_unequal(ctx, sub, r, a, na, b, nb, carry, S(stream));
+}
+
+bn_status bn_add_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
+                         uint64_t *carry_out, bn_stream stream) {
+    return addsub_unequal(ctx, false, r, a, na, b, nb, carry_out, stream);
+}
+
+bn_status bn_sub_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
+                         uint64_t *borrow_out, bn_stream stream) {
+    return addsub_unequal(ctx, true, r, a, na, b, nb, borrow_out, stream);
+}
+
+bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                             size_t npairs, uint64_t *sign, bn_stream stream) {
+    if (!ctx) return BN_EINVAL;
+    size_t N;
+    if (mul_overflow(n, npairs, &N) || N > BN_MAX_LIMBS) return BN_ERANGE;
+    bn_status st;
+    if ((st = check_ptr(r, N)) || (st = check_ptr(a, N)) || (st = check_ptr(b, N))) return st;
+    if (sign && ((uintptr_t)sign & 7u)) return BN_EINVAL;
+    const size_t bytes = N * 8;
+    if ((r != a && overlaps(r, bytes, a, bytes)) || (r != b && overlaps(r, bytes, b, bytes))) return BN_EALIAS;
+    if (sign && (overlaps(sign, npairs * 8, r, bytes) || overlaps(sign, npairs * 8, a, bytes) ||
+                 overlaps(sign, npairs * 8, b, bytes)))
+        return BN_EALIAS;
+    DeviceGuard g(ctx->device);
+    return launch_sub_abs(ctx, r, a, b, n, npairs, sign, S(stream));
 }
 
 // ---------------------------------------------------------------- multiply ----

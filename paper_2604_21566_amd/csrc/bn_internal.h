@@ -104,8 +104,20 @@ bn_status bn_launch_status();
 // Flat segmented add/sub over N = n * npairs limbs; a segment (pair) starts every n limbs.
 bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                            u64 *carry, hipStream_t s);
+// The same with a per-segment carry-in (cin, device, bit 0; NULL for none) and/or b
+// taken as zero (bzero; b unused): r = a +- b +- cin.
+bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
+                               const u64 *cin, bool bzero, u64 *carry, hipStream_t s);
 size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N);
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s);
+
+// ---- add/sub extras (k_addsub_ext.hip) ----
+bn_status launch_addsub_nc(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
+                           const u64 *cin, u64 *carry, hipStream_t s);
+bn_status launch_addsub_unequal(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,
+                                u64 *carry, hipStream_t s);
+bn_status launch_sub_abs(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *sign,
+                         hipStream_t s);
 
 // ---- mul (k_mul_*.hip) ----
 bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 na, u64 nb, u64 npairs,

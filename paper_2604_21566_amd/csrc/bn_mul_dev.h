@@ -92,6 +92,7 @@ __device__ __forceinline__ void wave_normalise_store(const u64 (&lo)[L], const u
 template <int L>
 __device__ void mul_item_mad(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
                              u64 *__restrict__ r) {
+    static_assert(L > 0 && (L & (L - 1)) == 0 && L <= 16, "2 L steps per group must divide the 64 of a load");
     // the step loop runs over the digits of a: make a the shorter operand (a*b = b*a)
     if (na > nb) {
         const u64 *t = a;

@@ -91,12 +91,24 @@ struct ScanGeom {
     int nshift;    // log2(n) if n is a power of two, else -1
     u64 TL;        // limbs per tile
     u64 epoch;     // chained launches: this launch's epoch, or 0 to read it from the control block
+    const u64 *cin;  // EXT_CIN: per-segment carry (borrow) into the segment's first limb (bit 0)
+    u64 nseg;        // segments (pairs)
 };
+
+// Kernel variants beyond the plain a +- b: a per-segment carry-in, and b = 0 (the
+// carry-in alone propagates through a).
+constexpr int EXT_CIN = 1, EXT_BZERO = 2;
+
+template <int EXT>
+__device__ __forceinline__ bool seg_cin(const ScanGeom &G, u64 q) {
+    if constexpr ((EXT & EXT_CIN) != 0) return q < G.nseg && (G.cin[q] & 1ull) != 0;
+    return false;
+}
 
 // (generate, propagate) aggregate of tile u computed from the operands by one
 // wave, 128 limbs per step.  Used when the tile has not published its status yet
 // (self-help), so the waiting tile never depends on another workgroup making progress.
-template <bool SUB>
+template <bool SUB, int EXT>
 __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G,
                                          u64 u, u32 &g_out, u32 &p_out) {
     const int lane = threadIdx.x & 63;
@@ -109,8 +121,12 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
         divmod_u64(i0, G.n, G.nshift, q, pos);
         bool g0 = false, p0 = false, g1 = false, p1 = false;
         u64 s;
-        if (i0 < hi) limb_gp<SUB>(a[i0], b[i0], s, g0, p0);
-        if (i0 + 1 < hi) limb_gp<SUB>(a[i0 + 1], b[i0 + 1], s, g1, p1);
+        const bool bz = (EXT & EXT_BZERO) != 0;
+        if (i0 < hi) limb_gp<SUB>(a[i0], bz ? 0ull : b[i0], s, g0, p0);
+        if (i0 + 1 < hi) limb_gp<SUB>(a[i0 + 1], bz ? 0ull : b[i0 + 1], s, g1, p1);
+        // a segment's first limb takes the segment's carry-in, not its neighbour's carry
+        g0 = g0 || (pos == 0 && p0 && seg_cin<EXT>(G, q));
+        g1 = g1 || (pos + 1 == G.n && i0 + 1 < hi && p1 && seg_cin<EXT>(G, q + 1));
         p0 = p0 && pos != 0;
         p1 = p1 && pos + 1 != G.n;
         const u64 Gm = __ballot(g1 || (p1 && g0));
@@ -131,7 +147,7 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
 // computes that tile's aggregate from the operands itself and walks on.  Tiles
 // below index 0 count as "carry-out 0".  `dist` returns how many tiles back the
 // deciding predecessor was.
-template <bool SUB>
+template <bool SUB, int EXT>
 __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64 *latch,
                         const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G, u64 &dist) {
     const int lane = threadIdx.x & 63;
@@ -168,7 +184,7 @@ __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64
         // into t is the carry out of tile u
         const u64 u = (u64)(base - first);
         u32 gu, pu;
-        tile_aggregate_from_data<SUB>(a, b, G, u, gu, pu);
+        tile_aggregate_from_data<SUB, EXT>(a, b, G, u, gu, pu);
         if (lane == 0) __hip_atomic_fetch_or(latch, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!pu) return gu;
         base = (i64)u - 1;
@@ -176,7 +192,7 @@ __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64
     }
 }
 
-template <bool SUB, int WAVES, int ROWS, bool VEC, bool CHAIN>
+template <bool SUB, int WAVES, int ROWS, bool VEC, bool CHAIN, int EXT = 0>
 __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, const u64 *__restrict__ a,
                                                           const u64 *__restrict__ b, ScanGeom G, u64 step_mod,
                                                           u64 step_div, u64 *__restrict__ carry,
@@ -207,24 +223,29 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     // stores keep them from displacing other lines in the caches (measured +10%).
     const bool full = VEC && (t + 1) * TL <= N;
     u64 x0[ROWS], x1[ROWS], y0[ROWS], y1[ROWS];
+    constexpr bool BZ = (EXT & EXT_BZERO) != 0;
     if (full) {
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const u64v2 va = __builtin_nontemporal_load(reinterpret_cast<const u64v2 *>(a + idx0 + (u64)j * 128));
-            const u64v2 vb = __builtin_nontemporal_load(reinterpret_cast<const u64v2 *>(b + idx0 + (u64)j * 128));
             x0[j] = va.x;
             x1[j] = va.y;
-            y0[j] = vb.x;
-            y1[j] = vb.y;
+            if (BZ) {
+                y0[j] = y1[j] = 0;
+            } else {
+                const u64v2 vb = __builtin_nontemporal_load(reinterpret_cast<const u64v2 *>(b + idx0 + (u64)j * 128));
+                y0[j] = vb.x;
+                y1[j] = vb.y;
+            }
         }
     } else {
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const u64 idx = idx0 + (u64)j * 128;
             x0[j] = idx < N ? a[idx] : 0;
-            y0[j] = idx < N ? b[idx] : 0;
+            y0[j] = (!BZ && idx < N) ? b[idx] : 0;
             x1[j] = idx + 1 < N ? a[idx + 1] : 0;
-            y1[j] = idx + 1 < N ? b[idx + 1] : 0;
+            y1[j] = (!BZ && idx + 1 < N) ? b[idx + 1] : 0;
         }
     }
 
@@ -236,7 +257,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     u32 fl[ROWS];  // bit0 g0, bit1 p0, bit2 g1, bit3 p1 (raw flags of the lane's two limbs)
     u32 wg = 0, wp = 1;
     {
-        u64 pos = pos0;
+        u64 pos = pos0, q = q0;
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const u64 idx = idx0 + (u64)j * 128;
@@ -256,7 +277,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
             const bool st1 = (pos + 1 == n);
             const bool pp0 = p0 && !st0;  // a segment start does not pass a carry in
             const bool pp1 = p1 && !st1;
-            const bool Gl = g1 || (pp1 && g0);
+            // ... it takes the segment's own carry-in instead (EXT_CIN)
+            const bool ge0 = g0 || (st0 && p0 && seg_cin<EXT>(G, q));
+            const bool ge1 = g1 || (st1 && p1 && seg_cin<EXT>(G, q + 1));
+            const bool Gl = ge1 || (pp1 && ge0);
             const bool Pl = pp0 && pp1;
             Gm[j] = __ballot(Gl);
             Pm[j] = __ballot(Pl);
@@ -265,7 +289,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
             wg = (u32)co;
             wp &= (Pm[j] == ~0ull) ? 1u : 0u;
             pos += step_mod;
-            if (pos >= n) pos -= n;
+            q += step_div;
+            if (pos >= n) {
+                pos -= n;
+                q += 1;
+            }
         }
     }
     if (lane == 0) {
@@ -309,9 +337,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
             const bool st0 = (pos == 0);
             const bool st1 = (pos + 1 == n);
             const bool en1 = (n == 1) || (pos + 2 == n);
-            const bool ci0 = cb && !st0;
+            const bool ci0 = st0 ? seg_cin<EXT>(G, q) : cb;
             const bool co0 = g0 || (p0 && ci0);
-            const bool ci1 = co0 && !st1;
+            const bool ci1 = st1 ? seg_cin<EXT>(G, q + 1) : co0;
             const bool co1 = g1 || (p1 && ci1);
             const u64 r0 = SUB ? x0[j] - (u64)ci0 : x0[j] + (u64)ci0;
             const u64 r1 = SUB ? x1[j] - (u64)ci1 : x1[j] + (u64)ci1;
@@ -342,7 +370,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
         const u64 first_pos = __shfl(pos0, 0);
         if (t > 0 && first_pos != 0) {
             u64 dist;
-            cin = lookback<SUB>(status, t, epoch, spin_limit, &ctl->err, a, b, G, dist);
+            cin = lookback<SUB, EXT>(status, t, epoch, spin_limit, &ctl->err, a, b, G, dist);
             if ((dbg & 2u) && lane == 0)
                 __hip_atomic_fetch_add(ctl->hist + (63 - __clzll((long long)dist)), 1ull, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -378,9 +406,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
                 const bool st0 = (pos == 0);
                 const bool st1 = (pos + 1 == n);
                 const bool en1 = (n == 1) || (pos + 2 == n);
-                const bool ci0a = ((Ca >> lane) & 1ull) && !st0, ci0t = ((Ct >> lane) & 1ull) && !st0;
+                const bool cs0 = seg_cin<EXT>(G, q), cs1 = st1 && seg_cin<EXT>(G, q + 1);
+                const bool ci0a = st0 ? cs0 : ((Ca >> lane) & 1ull), ci0t = st0 ? cs0 : ((Ct >> lane) & 1ull);
                 const bool co0a = g0 || (p0 && ci0a), co0t = g0 || (p0 && ci0t);
-                const bool ci1a = co0a && !st1, ci1t = co0t && !st1;
+                const bool ci1a = st1 ? cs1 : co0a, ci1t = st1 ? cs1 : co0t;
                 const bool co1a = g1 || (p1 && ci1a), co1t = g1 || (p1 && ci1t);
                 if (ci0a != ci0t && idx < N) r[idx] = SUB ? x0[j] - (u64)ci0t : x0[j] + (u64)ci0t;
                 if (ci1a != ci1t && idx + 1 < N) r[idx + 1] = SUB ? x1[j] - (u64)ci1t : x1[j] + (u64)ci1t;
@@ -476,14 +505,30 @@ bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s) {
     return bn_launch_status();
 }
 
-bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *carry,
-                           hipStream_t s) {
+// The extended variants (carry-in, b = 0) come in fixed shapes: 1 x 1 independent
+// tiles, 4 x 8 (4 x 4 unaligned) chained tiles.
+template <bool SUB, int EXT>
+static scan_fn pick_ext(bool vec, bool chain) {
+    if (vec) return chain ? k_flat_scan<SUB, 4, 8, true, true, EXT> : k_flat_scan<SUB, 1, 1, true, false, EXT>;
+    return chain ? k_flat_scan<SUB, UNALIGNED_CHAIN_WAVES, UNALIGNED_CHAIN_ROWS, false, true, EXT>
+                 : k_flat_scan<SUB, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false, EXT>;
+}
+
+bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
+                               const u64 *cin, bool bzero, u64 *carry, hipStream_t s) {
     const u64 N = n * npairs;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
-    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)b) & 15u) == 0;
+    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bzero ? nullptr : b)) & 15u) == 0;
+    const int ext = (cin ? EXT_CIN : 0) | (bzero ? EXT_BZERO : 0);
     int waves, rows;
     bool chain;
-    flat_scan_shape(ctx, n, vec, waves, rows, chain);
+    if (ext == 0) {
+        flat_scan_shape(ctx, n, vec, waves, rows, chain);
+    } else {
+        chain = (128 % n) != 0;
+        waves = chain ? (vec ? 4 : UNALIGNED_CHAIN_WAVES) : 1;
+        rows = chain ? (vec ? 8 : UNALIGNED_CHAIN_ROWS) : 1;
+    }
     const u64 TL = (u64)waves * rows * 128;
     const u64 ntiles = (N + TL - 1) / TL;
     if (chain) {
@@ -492,7 +537,13 @@ bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
     }
     if (ntiles > 0x7fffffffull) return BN_ERANGE;
     scan_fn f = nullptr;
-    if (vec)
+    if (ext == EXT_CIN)
+        f = sub ? pick_ext<true, EXT_CIN>(vec, chain) : pick_ext<false, EXT_CIN>(vec, chain);
+    else if (ext == (EXT_CIN | EXT_BZERO))
+        f = sub ? pick_ext<true, EXT_CIN | EXT_BZERO>(vec, chain) : pick_ext<false, EXT_CIN | EXT_BZERO>(vec, chain);
+    else if (ext != 0)
+        return BN_EINVAL;
+    else if (vec)
         f = sub ? (chain ? pick<true, true>(waves, rows) : pick<true, false>(waves, rows))
                 : (chain ? pick<false, true>(waves, rows) : pick<false, false>(waves, rows));
     else if (chain)
@@ -508,12 +559,17 @@ bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (chain && hipStreamIsCapturing(s, &cs) != hipSuccess) return BN_EHIP;
     const bool captured = cs != hipStreamCaptureStatusNone;
-    ScanGeom G{N, n, -1, TL, (chain && !captured) ? ++ctx->host_epoch : 0};
+    ScanGeom G{N, n, -1, TL, (chain && !captured) ? ++ctx->host_epoch : 0, cin, npairs};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
                        ctx->ctl, (u64 *)ctx->status.ptr, ctx->tune.spin_limit, ctx->tune.debug_flags);
     bn_status st = bn_launch_status();
-    if (st != BN_OK || !captured) return st;
+    if (st != BN_OK || !chain || !captured) return st;
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, ctx->ctl);
     return bn_launch_status();
+}
+
+bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *carry,
+                           hipStream_t s) {
+    return launch_flat_scan_ext(ctx, sub, r, a, b, n, npairs, nullptr, false, carry, s);
 }

@@ -21,8 +21,12 @@ __global__ __launch_bounds__(256) void k_mul_ragged_mad(const RItem *__restrict_
                                                         u64 *__restrict__ r, const u64 *__restrict__ a,
                                                         const u64 *__restrict__ b) {
     const u32 W = gridDim.x * 4;
-    for (u32 it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += W) {
-        const RItem m = items[it];
+    u32 it = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (it >= nitems) return;
+    RItem next = items[it];
+    for (; it < nitems; it += W) {
+        const RItem m = next;
+        if (it + W < nitems) next = items[it + W];  // the next descriptor loads during this product
         const u64 *pa = a + m.a_off;
         const u64 *pb = b + m.b_off;
         u64 *pr = r + m.r_off;
@@ -42,8 +46,12 @@ __global__ __launch_bounds__(256) void k_mul_ragged_mfma(const RItem *__restrict
     __shared__ u64 lds[4 * RAGGED_LDS_U64];
     const int w = threadIdx.x >> 6;
     const u32 W = gridDim.x * 4;
-    for (u32 it = blockIdx.x * 4 + w; it < nitems; it += W) {
-        const RItem m = items[it];
+    u32 it = blockIdx.x * 4 + w;
+    if (it >= nitems) return;
+    RItem next = items[it];
+    for (; it < nitems; it += W) {
+        const RItem m = next;
+        if (it + W < nitems) next = items[it + W];
         mul_item_mfma_small(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
         wave_sync();
     }
