@@ -166,6 +166,7 @@ def main():
     if not args.quick:
         workloads.update(extra_workloads(ctx, bn, wl, torch))
         workloads["c2_addsub"]["frac_of_measured_copy"] = achieved / workloads["hbm_copy_GBps"]
+        workloads["c2_addsub"]["frac_of_nt_copy"] = achieved / workloads["measured_rates"]["nt_copy_GBps"]
 
     bn.bn_destroy(ctx)
     out = {
@@ -376,8 +377,9 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         res["c4"] = c4
 
     # ---- measured ceilings of the two multiplication forms' inner operations
-    mac_rate, mfma_rate = bn.bn_probe_rates(ctx)
+    mac_rate, mfma_rate, copy_rate = bn.bn_probe_rates(ctx)
     res["measured_rates"] = {"mac96_per_s": mac_rate, "mfma_i8_ops_per_s": mfma_rate,
+                             "nt_copy_GBps": copy_rate / 1e9,
                              "mad_form_limb_products_per_s_ceiling": mac_rate / 4,
                              "mfma_form_limb_products_per_s_ceiling": mfma_rate / 128}
 

@@ -153,8 +153,13 @@ bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const 
 
 /* r[0 .. na+nb) = a * b (Theorem 2), exactly na+nb limbs, leading zeros kept.
  * Column products (all independent), then one deferred carry-normalise pass
- * (Algorithm 2, phases 1-5).  r must not overlap a or b (BN_EALIAS).
- * na = 0 or nb = 0 gives r = 0 (na+nb limbs). */
+ * (Algorithm 2, phases 1-5).  na = 0 or nb = 0 gives r = 0 (na+nb limbs).
+ * In place: r may overlap a or b, in whole or in part (e.g. r == a with room for
+ * na+nb limbs).  The product then goes to a staging buffer the context owns (na+nb
+ * limbs per pair, kept across calls and grown like the workspace: with a device
+ * synchronisation, BN_ECAPTURE while a capture is active and it would have to grow)
+ * and one device-to-device copy on `stream` moves it into r after every read of a
+ * and b. */
 bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
                  int form, bn_stream stream);
 
@@ -170,8 +175,8 @@ bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
  * into 3N of m/2 limbs; the bottom level is one bn_mul_n_batch-style launch, the
  * splits and combines are batched add/sub passes.  Pair p: a + p*n, b + p*n, product
  * at r + 2*p*n (exactly 2n limbs).  levels = 0 is bn_mul_n_batch; n must be a
- * multiple of 2^levels and levels <= BN_KARATSUBA_MAX_LEVELS (else BN_EINVAL).  r must
- * not overlap a or b (BN_EALIAS).  The context keeps a workspace of about
+ * multiple of 2^levels and levels <= BN_KARATSUBA_MAX_LEVELS (else BN_EINVAL).  r may
+ * overlap a or b (in place, as for bn_mul).  The context keeps a workspace of about
  * 100 n npairs (3/2)^levels bytes across calls (grown with a device synchronisation;
  * BN_ECAPTURE while a stream capture is active and it would have to grow). */
 #define BN_KARATSUBA_MAX_LEVELS 8
@@ -254,15 +259,17 @@ const char *bn_param_names(void);
  * out_json != NULL, write them as a JSON object.  Synchronous; takes seconds. */
 bn_status bn_autotune(bn_ctx *ctx, const char *out_json);
 
-/* Measured device rates for the two multiplication forms' inner operations, the
- * ceilings their rooflines are stated against: *mac96_per_s = 32x32-bit multiply-
- * accumulates into a 96-bit sum per second (v_mad_u64_u32 + v_addc_co_u32, the
- * plain form's column step, Alg. 2 phase 2 on 32-bit digits) and
- * *mfma_i8_ops_per_s = int8 MFMA operations per second (2 per multiply-add,
- * v_mfma_i32_32x32x32_i8 with independent accumulators), each over every CU of the
- * context's device.  Synchronises the device; allocates and frees a small buffer.
- * Returns BN_EINVAL for NULL arguments, BN_ENOMEM, or BN_EHIP. */
-bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mfma_i8_ops_per_s);
+/* Measured device rates, the ceilings the rooflines are also stated against:
+ * *mac96_per_s = 32x32-bit multiply-accumulates into a 96-bit sum per second
+ * (v_mad_u64_u32 + v_addc_co_u32, the plain form's column step, Alg. 2 phase 2 on
+ * 32-bit digits); *mfma_i8_ops_per_s = int8 MFMA operations per second (2 per
+ * multiply-add, v_mfma_i32_32x32x32_i8 with independent accumulators); and
+ * *copy_bytes_per_s = bytes read plus written per second by a 512 MiB device copy
+ * with 16-byte non-temporal loads and stores per lane (how the add/sub scan moves
+ * its operands), the fastest of 2, 4 or 8 loads in flight per lane.  Each runs over every CU of the context's device.  Synchronises the
+ * device; allocates and frees about 1 GiB.  Returns BN_EINVAL for NULL arguments,
+ * BN_ENOMEM, or BN_EHIP. */
+bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mfma_i8_ops_per_s, double *copy_bytes_per_s);
 
 /* Load parameters written by bn_autotune (flat JSON object of "key": integer). */
 bn_status bn_load_tuning(bn_ctx *ctx, const char *json_path);

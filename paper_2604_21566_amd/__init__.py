@@ -63,7 +63,8 @@ _PROTOS = {
     "bn_workspace_size": (_sz, [_vp, _i, _sz, _sz, _sz, _i]),
     "bn_check": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),
     "bn_lookback_stats": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64), _sz]),
-    "bn_probe_rates": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "bn_probe_rates": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double)]),
     "bn_add": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_sub": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_add_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
@@ -193,10 +194,11 @@ def bn_lookback_stats(ctx, stream=None):
 
 
 def bn_probe_rates(ctx):
-    """Measured (mac96 per s, int8 MFMA ops per s) of the context's device."""
-    m, f = ctypes.c_double(0), ctypes.c_double(0)
-    _ck(lib().bn_probe_rates(ctx, ctypes.byref(m), ctypes.byref(f)), "bn_probe_rates")
-    return m.value, f.value
+    """Measured (mac96 per s, int8 MFMA ops per s, streaming copy bytes per s) of the
+    context's device."""
+    m, f, c = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _ck(lib().bn_probe_rates(ctx, ctypes.byref(m), ctypes.byref(f), ctypes.byref(c)), "bn_probe_rates")
+    return m.value, f.value, c.value
 
 
 def bn_set_param(ctx, key: str, value: int):

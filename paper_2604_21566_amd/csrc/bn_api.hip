@@ -120,6 +120,7 @@ bn_status bn_destroy(bn_ctx *ctx) {
     if (ctx->status.ptr) (void)hipFree(ctx->status.ptr);
     if (ctx->work.ptr) (void)hipFree(ctx->work.ptr);
     if (ctx->kwork.ptr) (void)hipFree(ctx->kwork.ptr);
+    if (ctx->mstage.ptr) (void)hipFree(ctx->mstage.ptr);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
     delete ctx;
     return BN_OK;
@@ -291,8 +292,25 @@ static bn_status mul_args(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uin
         return BN_ERANGE;
     bn_status st;
     if ((st = check_ptr(r, R)) || (st = check_ptr(a, A)) || (st = check_ptr(b, B))) return st;
-    if (overlaps(r, R * 8, a, A * 8) || overlaps(r, R * 8, b, B * 8)) return BN_EALIAS;
     return BN_OK;
+}
+
+// A product whose output overlaps an operand is written to the context's staging
+// buffer and copied into r after the last kernel that reads a or b.
+static bool mul_in_place(const uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na, size_t nb,
+                         size_t npairs) {
+    return overlaps(r, (na + nb) * npairs * 8, a, na * npairs * 8) || overlaps(r, (na + nb) * npairs * 8, b, nb * npairs * 8);
+}
+
+static bn_status mul_staged(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na, size_t nb,
+                            size_t npairs, hipStream_t s, const std::function<bn_status(u64 *)> &run) {
+    if (!mul_in_place(r, a, b, na, nb, npairs)) return run(r);
+    const size_t bytes = (na + nb) * npairs * 8;
+    bn_status st = bn_ensure(ctx, ctx->mstage, bytes, s);
+    if (st != BN_OK) return st;
+    u64 *stage = static_cast<u64 *>(ctx->mstage.ptr);
+    if ((st = run(stage)) != BN_OK) return st;
+    return hipMemcpyAsync(r, stage, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess ? BN_OK : BN_EHIP;
 }
 
 bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb, int form,
@@ -300,7 +318,8 @@ bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const u
     bn_status st = mul_args(ctx, r, a, b, na, nb, 1, form);
     if (st != BN_OK) return st;
     DeviceGuard g(ctx->device);
-    return launch_mul_batch(ctx, r, a, b, na, nb, 1, form, S(stream));
+    return mul_staged(ctx, r, a, b, na, nb, 1, S(stream),
+                      [&](u64 *out) { return launch_mul_batch(ctx, out, a, b, na, nb, 1, form, S(stream)); });
 }
 
 bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na, size_t nb,
@@ -308,7 +327,8 @@ bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
     bn_status st = mul_args(ctx, r, a, b, na, nb, npairs, form);
     if (st != BN_OK) return st;
     DeviceGuard g(ctx->device);
-    return launch_mul_batch(ctx, r, a, b, na, nb, npairs, form, S(stream));
+    return mul_staged(ctx, r, a, b, na, nb, npairs, S(stream),
+                      [&](u64 *out) { return launch_mul_batch(ctx, out, a, b, na, nb, npairs, form, S(stream)); });
 }
 
 bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
@@ -318,7 +338,9 @@ bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, 
     if (levels < 0 || levels > BN_KARATSUBA_MAX_LEVELS) return BN_EINVAL;
     if (n && (n % ((size_t)1 << levels))) return BN_EINVAL;
     DeviceGuard g(ctx->device);
-    return launch_mul_karatsuba(ctx, r, a, b, n, npairs, levels, form, S(stream));
+    return mul_staged(ctx, r, a, b, n, n, npairs, S(stream), [&](u64 *out) {
+        return launch_mul_karatsuba(ctx, out, a, b, n, npairs, levels, form, S(stream));
+    });
 }
 
 // ------------------------------------------------------------------ ragged ----
@@ -390,6 +412,9 @@ bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_
     if (op == 2) {
         if ((st = mul_args(ctx, r, a, b, na, nb, npairs, form)) != BN_OK) return st;
         if ((st = bn_ensure(ctx, ctx->work, mul_workspace_bytes(ctx, na, nb, npairs, form), nullptr)) != BN_OK)
+            return st;
+        if (mul_in_place(r, a, b, na, nb, npairs) &&
+            (st = bn_ensure(ctx, ctx->mstage, (na + nb) * npairs * 8, nullptr)) != BN_OK)
             return st;
         if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)(na + nb), (u64)(na + nb) * npairs), nullptr)) !=
             BN_OK)

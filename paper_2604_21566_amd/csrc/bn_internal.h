@@ -26,9 +26,11 @@ typedef int64_t i64;
 //           a predecessor tile's aggregate itself instead of waiting for it)
 constexpr int LOOKBACK_BINS = 32;
 struct ScanCtl {
-    u64 epoch;
-    u64 err;
-    u64 pad[6];
+    u64 epoch;                // look-back epoch of launches recorded into graphs
+    u64 err;                  // latched device events (bit 0: a look-back computed a predecessor itself)
+    u64 carry_tmp;            // carry between the two passes of an unequal-length add/sub
+    u64 zero;                 // always 0 (a carry-in of zero)
+    u64 pad[4];
     u64 hist[LOOKBACK_BINS];  // look-back distances, recorded when debug flag bit 1 is set
 };
 
@@ -67,6 +69,7 @@ struct bn_ctx {
     DevBuf status;              // look-back status words
     DevBuf work;                // mul column accumulators / folded limbs
     DevBuf kwork;               // Karatsuba operand, product and combine arrays
+    DevBuf mstage;              // products computed in place: staged here, then copied
     u64 host_epoch = 1ull << 61;  // epochs of chained scans launched outside a capture
     Tuning tune;
 };

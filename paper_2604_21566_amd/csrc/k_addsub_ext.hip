@@ -26,8 +26,8 @@ bn_status launch_addsub_nc(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
 // as a plain pair, then the carry (borrow) through a's remaining limbs.
 bn_status launch_addsub_unequal(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,
                                 u64 *carry, hipStream_t s) {
-    u64 *tmp = &ctx->ctl->pad[0];   // the carry between the two passes (device)
-    const u64 *zero = &ctx->ctl->pad[1];  // stays 0
+    u64 *tmp = &ctx->ctl->carry_tmp;
+    const u64 *zero = &ctx->ctl->zero;
     bn_status st;
     if (na == nb) return launch_flat_scan(ctx, sub, r, a, b, na, 1, carry, s);
     if (nb > 0 && (st = launch_flat_scan(ctx, sub, r, a, b, nb, 1, tmp, s)) != BN_OK) return st;

@@ -101,10 +101,18 @@ __global__ __launch_bounds__(256) void k_add_ragged(const RItem *__restrict__ it
     }
 }
 
-// Persistent grid: as many 4-wave workgroups as stay resident (occupancy in waves
-// per SIMD, 4 SIMDs per CU), but no more than the items need.
-u32 persistent_blocks(const bn_ctx *ctx, u32 nitems, int waves_per_simd) {
-    const u32 want = (u32)std::max(1, ctx->num_cu) * (u32)waves_per_simd;
+// Persistent grid: exactly as many 4-wave workgroups as stay resident at once (the
+// runtime's occupancy for the kernel: registers and LDS decide it), but no more than
+// the items need.  A grid larger than the resident set would run its last
+// workgroups after the first ones finish, doubling the time of a balanced batch.
+template <auto KERNEL>
+u32 persistent_blocks(const bn_ctx *ctx, u32 nitems) {
+    static const int per_cu = [] {  // one query per kernel (every device here is gfx950)
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, KERNEL, 256, 0) != hipSuccess || v < 1) v = 1;
+        return v;
+    }();
+    const u32 want = (u32)std::max(1, ctx->num_cu) * (u32)per_cu;
     const u32 need = (nitems + 3) / 4;
     return std::max<u32>(1, std::min(want, need));
 }
@@ -190,13 +198,13 @@ bn_status plan_add_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, bn_p
 bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, hipStream_t s) {
     const u32 nmad = pl->nsmall_mad, nmfma = pl->nsmall - pl->nsmall_mad;
     if (nmad) {
-        hipLaunchKernelGGL(k_mul_ragged_mad, dim3(persistent_blocks(ctx, nmad, 8)), dim3(256), 0, s, pl->d_items, nmad,
+        hipLaunchKernelGGL(k_mul_ragged_mad, dim3(persistent_blocks<k_mul_ragged_mad>(ctx, nmad)), dim3(256), 0, s, pl->d_items, nmad,
                            r, a, b);
         bn_status st = bn_launch_status();
         if (st != BN_OK) return st;
     }
     if (nmfma) {
-        hipLaunchKernelGGL(k_mul_ragged_mfma, dim3(persistent_blocks(ctx, nmfma, 4)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_mul_ragged_mfma, dim3(persistent_blocks<k_mul_ragged_mfma>(ctx, nmfma)), dim3(256), 0, s,
                            pl->d_items + nmad, nmfma, r, a, b);
         bn_status st = bn_launch_status();
         if (st != BN_OK) return st;
@@ -211,7 +219,7 @@ bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a
 bn_status launch_add_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, u64 *carry,
                             hipStream_t s) {
     if (!pl->nsmall) return BN_OK;
-    hipLaunchKernelGGL(k_add_ragged<false>, dim3(persistent_blocks(ctx, pl->nsmall, 8)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_add_ragged<false>, dim3(persistent_blocks<k_add_ragged<false>>(ctx, pl->nsmall)), dim3(256), 0, s,
                        pl->d_items, pl->nsmall, r, a, b, carry);
     return bn_launch_status();
 }

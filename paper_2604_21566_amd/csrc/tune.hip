@@ -90,10 +90,26 @@ float time_ms(F &&f, int reps = 5) {
     return v[v.size() / 2];
 }
 
+// k_rate_copy: the streaming reference for the add/sub roofline -- 16 bytes per lane,
+// non-temporal loads and stores, as the scan kernel moves its operands.  A workgroup
+// copies one tile of 256 U vectors: U coalesced loads in flight per lane, then the
+// stores.  The grid covers the array exactly (n a multiple of 256 U).
+typedef u64 u64v2t __attribute__((ext_vector_type(2)));
+template <int U>
+__global__ __launch_bounds__(256) void k_rate_copy(u64v2t *__restrict__ dst, const u64v2t *__restrict__ src) {
+    const u64 base = (u64)blockIdx.x * 256 * U + threadIdx.x;
+    u64v2t v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = __builtin_nontemporal_load(src + base + 256 * j);
+#pragma unroll
+    for (int j = 0; j < U; ++j) __builtin_nontemporal_store(v[j], dst + base + 256 * j);
+}
+
 }  // namespace
 
-extern "C" bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mfma_i8_ops_per_s) {
-    if (!ctx || !mac96_per_s || !mfma_i8_ops_per_s) return BN_EINVAL;
+extern "C" bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mfma_i8_ops_per_s,
+                                    double *copy_bytes_per_s) {
+    if (!ctx || !mac96_per_s || !mfma_i8_ops_per_s || !copy_bytes_per_s) return BN_EINVAL;
     int prev = 0;
     (void)hipGetDevice(&prev);
     if (hipSetDevice(ctx->device) != hipSuccess) return BN_EHIP;
@@ -111,14 +127,37 @@ extern "C" bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mf
     const float tf = time_ms([&] {
         hipLaunchKernelGGL(k_rate_mfma, dim3((u32)bf), dim3(256), 0, nullptr, (int *)out, iff);
     });
-    const bool ok = hipGetLastError() == hipSuccess;
+    bool ok = hipGetLastError() == hipSuccess;
     (void)hipDeviceSynchronize();
     (void)hipFree(out);
+    // streaming copy of 512 MiB
+    const u64 nv = (512ull << 20) / 16;
+    void *src = nullptr, *dst = nullptr;
+    float tc = 0;
+    if (hipMalloc(&src, nv * 16) != hipSuccess || hipMalloc(&dst, nv * 16) != hipSuccess) {
+        if (src) (void)hipFree(src);
+        (void)hipSetDevice(prev);
+        return BN_ENOMEM;
+    }
+    (void)hipMemset(src, 0x5a, nv * 16);
+    // the fastest of three tile depths
+    auto run_copy = [&](auto kernel, u64 per_block) {
+        return time_ms([&] {
+            hipLaunchKernelGGL(kernel, dim3((u32)(nv / per_block)), dim3(256), 0, nullptr, (u64v2t *)dst,
+                               (const u64v2t *)src);
+        });
+    };
+    tc = std::min({run_copy(k_rate_copy<2>, 512), run_copy(k_rate_copy<4>, 1024), run_copy(k_rate_copy<8>, 2048)});
+    ok = ok && hipGetLastError() == hipSuccess;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(src);
+    (void)hipFree(dst);
     (void)hipSetDevice(prev);
-    if (!ok || tm <= 0 || tf <= 0) return BN_EHIP;
+    if (!ok || tm <= 0 || tf <= 0 || tc <= 0) return BN_EHIP;
     *mac96_per_s = (double)bm * 256 * im * 8 / (tm * 1e-3);
     // per wave and iteration: 4 MFMAs of 32 x 32 x 32 multiply-adds, 2 ops each
     *mfma_i8_ops_per_s = (double)bf * 4 * iff * 4 * 32768.0 * 2 / (tf * 1e-3);
+    *copy_bytes_per_s = 2.0 * nv * 16 / (tc * 1e-3);  // bytes read + bytes written
     return BN_OK;
 }
 

@@ -54,7 +54,7 @@ def test_null_context_is_rejected_without_touching_a_device(bn):
     assert L.bn_mul(None, None, None, 0, None, 0, 0, None) == bn.BN_EINVAL
     assert L.bn_set_param(None, b"mul.crossover_limbs", 5) == bn.BN_EINVAL
     assert L.bn_lookback_stats(None, None, None, 0) == bn.BN_EINVAL
-    assert L.bn_probe_rates(None, None, None) == bn.BN_EINVAL
+    assert L.bn_probe_rates(None, None, None, None) == bn.BN_EINVAL
     assert L.bn_create(None, 0) == bn.BN_EINVAL
     assert L.bn_plan_destroy(None) == bn.BN_OK
     assert L.bn_graph_destroy(None) == bn.BN_OK

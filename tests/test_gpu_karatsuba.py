@@ -99,9 +99,6 @@ def test_errors(bnctx):
     with pytest.raises(bn.BnError) as e:
         bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 1, 9)  # more levels than allowed
     assert e.value.status == bn.BN_EINVAL
-    with pytest.raises(bn.BnError) as e:
-        bn.bn_mul_karatsuba_n_batch(bnctx, tr, tr[:96], ta, 96, 1, 1)  # r overlaps a
-    assert e.value.status == bn.BN_EALIAS
     # empty batch and n = 0 are no-ops
     bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 0, 2)
     bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 0, 3, 2)

@@ -221,9 +221,6 @@ def test_mul_errors(bnctx):
     announce("mul argument errors")
     t = torch.zeros(64, dtype=torch.int64, device="cuda")
     with pytest.raises(bn.BnError) as e:
-        bn.bn_mul(bnctx, t[0:8], t[4:8], t[8:12])     # r overlaps a
-    assert e.value.status == bn.BN_EALIAS
-    with pytest.raises(bn.BnError) as e:
         bn.bn_mul(bnctx, t[16:24], t[0:4], t[8:12], form=7)
     assert e.value.status == bn.BN_EINVAL
     z = torch.empty(0, dtype=torch.int64, device="cuda")

@@ -62,6 +62,7 @@ def test_autotune_roundtrip(tmp_path):
 def test_probe_rates_are_plausible(bnctx):
     """The measured ceilings sit between a tenth of and just above the published
     figures (VALU: 256 CUs x 64 lanes x 2.4 GHz per full-rate op; int8 MFMA 5.0 POPS)."""
-    mac, mfma = bn.bn_probe_rates(bnctx)
+    mac, mfma, copy = bn.bn_probe_rates(bnctx)
     assert 1e12 < mac < 4.0e13, mac
     assert 5e14 < mfma < 5.5e15, mfma
+    assert 1e12 < copy < 8.0e12, copy  # HBM3E: 8 TB/s published
