@@ -161,6 +161,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_oracle_baseline(a_add, b_add, a_sub, b_sub, n, npairs, bytes_per_launch)
+        workloads["cpu_dot_c2"] = cpu_dot_baseline(a_add, b_add, a_sub, b_sub, n, npairs, bytes_per_launch)
     del a_sub, b_sub, sa, sb
 
     if not args.quick:
@@ -242,6 +243,66 @@ def cpu_oracle_baseline(a_add, b_add, a_sub, b_sub, n, npairs, bytes_per_launch)
             "one_thread": {"value": 2 * bytes_per_launch / dt_1 / 1e9, "ms_per_step": dt_1 * 1e3,
                            "repetitions": reps_1},
             "host_cpu": host_cpu_model()}
+
+
+def cpu_dot_baseline(a_add, b_add, a_sub, b_sub, n, npairs, bytes_per_launch):
+    """The paper's own CPU method (DoT add/sub with AVX-512 or AVX2, and the scalar
+    carry chain) on the same full 2^20 x 64-limb add + sub step, host arrays: context
+    for the GPU rate, not the oracle."""
+    from paper_2604_21566_amd import host as H
+    threads = host_threads()
+    r = np.empty_like(a_add)
+    c = np.empty(npairs, np.uint64)
+
+    def rate(isa, nthreads, budget_s=2.0, max_reps=20):
+        def step():
+            H.bnh_add_n_batch(r, a_add, b_add, n, npairs, c, isa, nthreads)
+            H.bnh_sub_n_batch(r, a_sub, b_sub, n, npairs, c, isa, nthreads)
+        step()
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            step()
+            reps += 1
+            if time.perf_counter() - t0 > budget_s or reps >= max_reps:
+                dt = (time.perf_counter() - t0) / reps
+                return {"GBps": 2 * bytes_per_launch / dt / 1e9, "ms_per_step": dt * 1e3, "repetitions": reps}
+
+    best = H.bnh_isa_best()
+    log(f"timing host DoT ({H.ISA_NAMES[best]}) on the full c2 batch, {threads} threads and one thread per ISA")
+    out = {"isa": H.ISA_NAMES[best], "threads": threads, "host_cpu": host_cpu_model(),
+           "all_threads": rate(best, threads)}
+    for isa in range(best + 1):
+        out[f"one_thread_{H.ISA_NAMES[isa]}"] = rate(isa, 1)
+    # cache-resident operands (16384 limbs = 384 KiB per call over r, a, b; one thread):
+    # the arithmetic itself, where the paper's SIMD-versus-scalar comparison lives.  The
+    # pointers are converted once and the cost of an empty call is subtracted.
+    import ctypes
+    g = np.random.default_rng(1)
+    L = H.lib()
+    cached = {}
+    for m in (8, 64, 1024):
+        np_ = 16384 // m
+        x = g.integers(0, 2 ** 64 - 1, m * np_, dtype=np.uint64, endpoint=True)
+        y = g.integers(0, 2 ** 64 - 1, m * np_, dtype=np.uint64, endpoint=True)
+        z = np.empty_like(x)
+        cc = np.empty(np_, np.uint64)
+        px, py, pz, pc = (v.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) for v in (x, y, z, cc))
+
+        def per_call(isa, pairs, reps=400):
+            L.bnh_add_n_batch(pz, px, py, m, pairs, pc, isa, 1)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                L.bnh_add_n_batch(pz, px, py, m, pairs, pc, isa, 1)
+            return (time.perf_counter() - t0) / reps
+
+        row = {}
+        for isa in range(best + 1):
+            dt = min(per_call(isa, np_) for _ in range(3)) - min(per_call(isa, 0) for _ in range(3))
+            row[f"{H.ISA_NAMES[isa]}_ns_per_limb"] = dt / (m * np_) * 1e9
+        row["simd_speedup_over_scalar"] = row["scalar_ns_per_limb"] / row[f"{H.ISA_NAMES[best]}_ns_per_limb"]
+        cached[f"{m}_limbs"] = row
+    out["cache_resident_add_one_thread"] = cached
+    return out
 
 
 def host_cpu_model() -> str:

@@ -1,4 +1,4 @@
-"""Build libbn.so (gfx950) in-tree with hipcc.
+"""Build libbn.so (gfx950) in-tree with hipcc, and libbn_host.so (host CPU) with gcc.
 
 Each HIP translation unit is compiled to an object under ``_build/`` in
 parallel, then linked into ``paper_2604_21566_amd/libbn.so``.  Always rebuilds.
@@ -18,7 +18,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbn.so")
 SOURCES = ["bn_api.hip", "k_addsub.hip", "k_addsub_ext.hip", "k_mul.hip", "k_karatsuba.hip", "k_ragged.hip", "tune.hip"]
 
+HOST_LIB = os.path.join(HERE, "libbn_host.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CC = os.environ.get("CC", "gcc")
 CFLAGS = [
     "--offload-arch=gfx950",
     "-O3",
@@ -46,7 +48,24 @@ def _compile(src: str) -> str:
     return obj
 
 
+def build_host(verbose: bool = True) -> str:
+    """libbn_host.so: DoT add/sub on the host CPU (gcc; ISA chosen at run time)."""
+    tmp = HOST_LIB + ".tmp"
+    cmd = [CC, "-O3", "-fPIC", "-shared", "-pthread", "-std=c11", "-Wall", "-Wextra", "-I", INCLUDE,
+           os.path.join(HERE, "host", "dot_host.c"), "-o", tmp]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"gcc failed for dot_host.c:\n{p.stdout}\n{p.stderr}")
+    if p.stderr.strip():
+        sys.stderr.write(p.stderr)
+    os.replace(tmp, HOST_LIB)
+    if verbose:
+        print(f"built {HOST_LIB}")
+    return HOST_LIB
+
+
 def build(verbose: bool = True) -> str:
+    build_host(verbose)
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -40,6 +40,19 @@ def test_library_exports_every_declared_symbol(bn):
     assert sorted(bn.EXPORTED) == _declared()
 
 
+def test_host_library_exports_every_declared_symbol():
+    """libbn_host.so (DoT on the host CPU) against include/bn_host.h."""
+    from paper_2604_21566_amd import host
+    if not os.path.exists(host.LIB_PATH):
+        from paper_2604_21566_amd import build as b
+        b.build_host(verbose=False)
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "bn_host.h")).read(), flags=re.S)
+    declared = sorted(set(re.findall(r"\b(bnh_[a-z0-9_]+)\s*\(", src)))
+    L = host.lib()
+    assert declared and not [n for n in declared if not hasattr(L, n)]
+    assert host.EXPORTED == declared
+
+
 def test_strerror_and_version(bn):
     assert bn.bn_strerror(bn.BN_OK) == "ok"
     assert "overlap" in bn.bn_strerror(bn.BN_EALIAS)
