@@ -289,7 +289,7 @@ constexpr int SMALL_MFMA_LDS_U64 = 272 + 256 + 128 + 128;  // bz, aR, lpa (256 u
 
 // One product of P = na + nb <= 256 limbs on the MFMA form, one wave.
 // lds: SMALL_MFMA_LDS_U64 words private to the wave.
-__device__ __noinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
+__device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
                                     u64 *__restrict__ r, u64 *lds) {
     // the Toeplitz steps run over the digits of b: make b the shorter operand
     if (nb > na) {
@@ -300,7 +300,11 @@ __device__ __noinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 
         na = nb;
         nb = tn;
     }
-    const int lane = threadIdx.x & 63;
+    // the lane index through an opaque move: keeps a caller's item loop from hoisting
+    // the many lane-dependent values of the epilogue out of the loop (which would hold
+    // them in registers across items and cut the occupancy)
+    int lane;
+    asm volatile("v_and_b32 %0, 63, %1" : "=v"(lane) : "v"((int)threadIdx.x));
     const u32 x = lane & 31, h = lane >> 5;
     const u32 nda = 8 * na, ndb = 8 * nb, P = na + nb;
     const u32 nca = (na + 3) / 4;  // 32-digit chunks of a

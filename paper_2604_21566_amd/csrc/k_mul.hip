@@ -24,7 +24,7 @@ template <int FORM, int L>
 __global__ __launch_bounds__(256) void k_mul_small(u64 *__restrict__ r, const u64 *__restrict__ a,
                                                    const u64 *__restrict__ b, u32 na, u32 nb, u64 npairs) {
     __shared__ u64 lds[FORM == BN_MUL_MFMA ? 4 * SMALL_MFMA_LDS_U64 : 1];
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const u64 p = (u64)blockIdx.x * 4 + w;
     if (p >= npairs) return;
     const u64 *pa = a + p * na;

@@ -21,7 +21,8 @@ __global__ __launch_bounds__(256) void k_mul_ragged_mad(const RItem *__restrict_
                                                         u64 *__restrict__ r, const u64 *__restrict__ a,
                                                         const u64 *__restrict__ b) {
     const u32 W = gridDim.x * 4;
-    u32 it = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // wave-uniform item index: descriptors, sizes and loop bounds stay scalar
+    u32 it = blockIdx.x * 4 + (u32)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (it >= nitems) return;
     RItem next = items[it];
     for (; it < nitems; it += W) {
@@ -44,14 +45,10 @@ __global__ __launch_bounds__(256) void k_mul_ragged_mfma(const RItem *__restrict
                                                          u64 *__restrict__ r, const u64 *__restrict__ a,
                                                          const u64 *__restrict__ b) {
     __shared__ u64 lds[4 * RAGGED_LDS_U64];
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const u32 W = gridDim.x * 4;
-    u32 it = blockIdx.x * 4 + w;
-    if (it >= nitems) return;
-    RItem next = items[it];
-    for (; it < nitems; it += W) {
-        const RItem m = next;
-        if (it + W < nitems) next = items[it + W];
+    for (u32 it = blockIdx.x * 4 + w; it < nitems; it += W) {
+        const RItem m = items[it];
         mul_item_mfma_small(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
         wave_sync();
     }
@@ -66,7 +63,7 @@ __global__ __launch_bounds__(256) void k_add_ragged(const RItem *__restrict__ it
                                                     const u64 *__restrict__ b, u64 *__restrict__ carry) {
     const int lane = threadIdx.x & 63;
     const u32 W = gridDim.x * 4;
-    for (u32 it = blockIdx.x * 4 + (threadIdx.x >> 6); it < nitems; it += W) {
+    for (u32 it = blockIdx.x * 4 + (u32)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6); it < nitems; it += W) {
         const RItem m = items[it];
         const u64 n = m.na;
         const u64 *pa = a + m.a_off, *pb = b + m.b_off;
