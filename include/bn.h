@@ -243,6 +243,9 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
  *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large
  *                                      MFMA kernel: even, 16..256
+ *   "mul.mfma_rows"                    Toeplitz rows per column block of the large MFMA
+ *                                      kernel, in groups of 64: 1 or 2 (default 2: the same
+ *                                      LDS reads feed twice the MFMAs)
  *   "lookback.spin_limit"              look-back polls before a tile computes an
  *                                      unpublished predecessor's carry itself
  *   "debug.flags"                      bit 0: tile 0 never publishes its status

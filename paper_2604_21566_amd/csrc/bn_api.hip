@@ -446,7 +446,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 // ------------------------------------------------------------------ params ----
 static const char *kParamNames =
     "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,"
-    "mul.crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,lookback.spin_limit,debug.flags";
+    "mul.crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,lookback.spin_limit,debug.flags";
 
 const char *bn_param_names(void) { return kParamNames; }
 
@@ -475,6 +475,9 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
     } else if (k == "mul.mfma_chunk") {
         if (v < 16 || v > 256 || (v & 1)) return BN_EINVAL;  // even (steps run in pairs); staging registers
         t.mfma_chunk = (int)v;
+    } else if (k == "mul.mfma_rows") {
+        if (v != 1 && v != 2) return BN_EINVAL;
+        t.mfma_rows = (int)v;
     } else if (k == "lookback.spin_limit") {
         if (v < 0 || v > 0xffffffffll) return BN_EINVAL;
         t.spin_limit = (u32)v;
@@ -498,6 +501,7 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "mul.crossover_limbs") *v = t.mul_crossover_limbs;
     else if (k == "mul.mad_xchunk") *v = t.mad_xchunk;
     else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;
+    else if (k == "mul.mfma_rows") *v = t.mfma_rows;
     else if (k == "lookback.spin_limit") *v = t.spin_limit;
     else if (k == "debug.flags") *v = t.debug_flags;
     else return BN_EINVAL;

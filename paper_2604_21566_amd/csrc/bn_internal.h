@@ -51,6 +51,7 @@ struct Tuning {
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
     int mfma_chunk = 256;              // Toeplitz steps staged in LDS per round (even, 16..256)
+    int mfma_rows = 2;                 // Toeplitz row groups of 64 per column block (1 or 2)
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
                                        // bit 1: record look-back distances in ScanCtl::hist

@@ -220,50 +220,70 @@ using lds_cptr = const __attribute__((address_space(3))) T *;  // read-only poin
 constexpr int AZ_SLOT_U64 = 10;  // one 64-digit chunk per 80-byte LDS slot: ds_read_b128 without bank conflicts
 
 
-// Large products on the MFMA form.  Output digit columns are grouped 64 at a time
-// (t = 64 W + r, r < 64), the Toeplitz step consumes 64 digits of b:
-//     C[64 W + r] = sum_d sum_k T_d[r][k] A_d[k][W],
-//     T_d[r][k] = b'[64 (d-1) + r + 1 + k],   A_d[k][W] = a'[64 (W-d) + 63 - k].
-// A W-block (32 W = 256 output limbs, 64 rows = two 32-row M-blocks) takes four
-// 32x32x32 MFMAs per step; the three distinct Toeplitz fragments (rows + K-slice
-// offsets 0, 32, 64) are shared by the wave's NW blocks and the third becomes the
-// first of the next step.  A workgroup (4 waves, 4 NW blocks) covers the whole
+// Large products on the MFMA form.  Output digit columns are grouped 64 R at a time
+// (t = 64 R W + r, r < 64 R; R = 1 or 2), the Toeplitz step consumes 64 digits of b:
+//     C[64 R W + r] = sum_d sum_k T_d[r][k] A_d[k][W],
+//     T_d[r][k] = b'[64 (d-1) + r + 1 + k],   A_d[k][W] = a'[64 (R W - d) + 63 - k].
+// A W-block (32 W = 256 R output limbs, 64 R rows = 2 R 32-row M-blocks) takes 4 R
+// 32x32x32 MFMAs per step.  The 2 R + 1 distinct Toeplitz fragments of a step (rows +
+// K-slice offsets 0, 32, ..., 64 R) are shared by the wave's NW blocks, and all but
+// two of them are the next step's first ones: every step reads two new Toeplitz
+// fragments and two a fragments per block, whatever R, so R = 2 feeds twice the
+// MFMAs from the same LDS reads.  A workgroup (4 waves, 4 NW blocks) covers the whole
 // contraction range of its blocks (or, SPLIT, one slice of it when there are too
 // few workgroups to fill the device), staging D steps of b digits and the matching
 // window of a chunks (byte-reversed) in LDS per round: no atomics and no
 // workspace zeroing in the unsplit case.  Accumulation is int32.  Unsplit launches
 // are used while a column holds at most 131586 digit products: its register holds
 // the true signed sum M modulo 2^32 and M lies in [-16256 cnt, 16384 cnt], narrower
-// than 2^32, so the epilogue decodes it exactly, folds the 64 columns of each W
-// into 8 limb values and writes lo and shifted hi.  Split launches keep every slice
+// than 2^32, so the epilogue decodes it exactly, folds the 64 R columns of each W
+// into 8 R limb values and writes lo and shifted hi.  Split launches keep every slice
 // at most 2046 steps when columns are longer (2046 * 64 * 2^14 < 2^31, exact) and
-// add the slice sums into an int64 column workspace that a fold kernel reads.
+// write the slice sums to per-slice int32 arrays that a fold kernel adds.
 // Workgroups are ordered by decreasing work.
 // Instruction order of one step of the large MFMA kernel: the LDS reads of the next
 // step go out first, then half of the MFMAs, then the VALU work (byte shifts of the
 // fragments just read, addresses) between the other half (the scheduler would
 // otherwise issue each read just before its use and wait for it).
+template <int NW, int R>
 __device__ __forceinline__ void mfma_step_order() {
     constexpr int MFMA = 0x008, VALU = 0x002, DSR = 0x100;
-    __builtin_amdgcn_sched_group_barrier(DSR, 9, 0);
-    __builtin_amdgcn_sched_group_barrier(MFMA, 4, 0);
+    constexpr int N = 4 * R * NW;  // MFMAs per step
+    __builtin_amdgcn_sched_group_barrier(DSR, 5 + 2 * NW, 0);
+    __builtin_amdgcn_sched_group_barrier(MFMA, N / 2, 0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        __builtin_amdgcn_sched_group_barrier(VALU, 3, 0);
+    for (int k = 0; k < N / 2; ++k) {
+        __builtin_amdgcn_sched_group_barrier(VALU, N >= 8 ? 3 : 6, 0);
         __builtin_amdgcn_sched_group_barrier(MFMA, 1, 0);
     }
 }
 
+// One step: acc[i][m] += T(32 m) A0[i] + T(32 m + 32) A1[i] for the 2 R M-blocks m,
+// with F[q] = T(32 q), q = 0 .. 2 R.  The first MFMA of every accumulator goes out
+// before the second one of any, so that independent MFMAs separate each pair.
+template <int NW, int R>
+__device__ __forceinline__ void mfma_step(v16i (&acc)[NW][2 * R], const v4i (&F)[2 * R + 1], const v4i (&A0)[NW],
+                                          const v4i (&A1)[NW]) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+#pragma unroll
+        for (int m = 0; m < 2 * R; ++m) acc[i][m] = __builtin_amdgcn_mfma_i32_32x32x32_i8(F[m], A0[i], acc[i][m], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+#pragma unroll
+        for (int m = 0; m < 2 * R; ++m)
+            acc[i][m] = __builtin_amdgcn_mfma_i32_32x32x32_i8(F[m + 1], A1[i], acc[i][m], 0, 0, 0);
+}
+
 // Two workgroups fit a CU's LDS, so two waves per SIMD: registers are not the limit.
-template <int NW, bool SPLIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mul_large_mfma(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                        u64 nb, u64 npairs, const u64 *__restrict__ lpa,
-                                                        const u64 *__restrict__ lpb, u32 D, u32 ngroups,
-                                                        u32 nslices, u64 *__restrict__ LO, u64 *__restrict__ HS,
-                                                        int *__restrict__ part) {
+template <int NW, int R, bool SPLIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mul_large_mfma(
+    const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na, u64 nb, u64 npairs, const u64 *__restrict__ lpa,
+    const u64 *__restrict__ lpb, u32 D, u32 ngroups, u32 nslices, u64 *__restrict__ LO, u64 *__restrict__ HS,
+    int *__restrict__ part) {
     extern __shared__ u64 lds[];
-    u64 *bz = lds;                     // 8 (D + 3) words of signed b digits
-    u64 *az = lds + 8 * ((u64)D + 3);  // (128 NW + D) chunk slots of reversed signed a digits
+    u64 *bz = lds;                         // 8 (D + 2 + R) words of signed b digits
+    u64 *az = lds + 8 * ((u64)D + 2 + R);  // (128 NW R + D) chunk slots of reversed signed a digits
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: scalar branches below
     const u32 x = lane & 31, h = lane >> 5;
@@ -274,38 +294,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const u32 g = middle_out((u32)(bq / npairs), ngroups);
     const i64 P = (i64)(na + nb);
     const i64 nca = (i64)((na + 7) / 8);
-    const i64 dmax = (8 * (i64)nb + 62) / 64;
-    const i64 nWb = (P + 255) / 256;
+    // steps d in [dmin, dmax] reach b digits: rows r < 64 R of step d read digits from
+    // 64 (d - 1) + 1 up to 64 d + 64 R - 1
+    const i64 dmin = 1 - R, dmax = (8 * (i64)nb + 62) / 64;
+    const i64 nWb = (P + 256 * R - 1) / (256 * R);
     const i64 wb0 = (i64)g * 4 * NW;
     const i64 W0g = 32 * wb0, Wend = W0g + 128 * NW - 1;
     const u64 *pa = a + pair * na, *pb = b + pair * nb;
 
-    i64 blo[NW], bhi[NW];
+    // a chunk c = R W - d meets column group W at step d
     i64 wlo = INT64_MAX, whi = INT64_MIN;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
         const i64 wb = wb0 + (i64)wave * NW + i;
-        blo[i] = 1;
-        bhi[i] = 0;
         if (wb < nWb) {
-            blo[i] = std::max<i64>(0, 32 * wb - nca + 1);
-            bhi[i] = std::min<i64>(dmax, 32 * wb + 31);
-        }
-        if (blo[i] <= bhi[i]) {
-            wlo = std::min(wlo, blo[i]);
-            whi = std::max(whi, bhi[i]);
+            const i64 blo = std::max<i64>(dmin, R * 32 * wb - nca + 1);
+            const i64 bhi = std::min<i64>(dmax, R * (32 * wb + 31));
+            if (blo <= bhi) {
+                wlo = std::min(wlo, blo);
+                whi = std::max(whi, bhi);
+            }
         }
     }
     const i64 lastb = std::min<i64>(wb0 + 4 * NW, nWb) - 1;
-    i64 ulo = std::max<i64>(0, W0g - nca + 1);
-    i64 uhi = std::min<i64>(dmax, 32 * lastb + 31);
+    i64 ulo = std::max<i64>(dmin, R * W0g - nca + 1);
+    i64 uhi = std::min<i64>(dmax, R * (32 * lastb + 31));
     const i64 ulo_all = ulo, uhi_all = uhi;
     if (SPLIT) {
         // this workgroup's slice of the contraction range: an even number of steps, at
         // most 2046 (exact int32 sums)
-        const i64 sl = (((dmax + (i64)nslices) / (i64)nslices) + 1) & ~(i64)1;
-        ulo = std::max<i64>(ulo, (i64)slice * sl);
-        uhi = std::min<i64>(uhi, (i64)slice * sl + sl - 1);
+        const i64 sl = (((dmax - dmin + (i64)nslices) / (i64)nslices) + 1) & ~(i64)1;
+        ulo = std::max<i64>(ulo, dmin + (i64)slice * sl);
+        uhi = std::min<i64>(uhi, dmin + (i64)slice * sl + sl - 1);
     }
     // Steps run in pairs.  A step outside every block's own range adds zero (its a
     // chunks or b digits are zero-padded), so an odd range grows by one such step at
@@ -316,24 +336,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         else if (ulo == ulo_all) --ulo;
     }
 
-    v16i acc[NW][2];
+    v16i acc[NW][2 * R];
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        acc[i][0] = v16i{0};
-        acc[i][1] = v16i{0};
-    }
+    for (int i = 0; i < NW; ++i)
+#pragma unroll
+        for (int m = 0; m < 2 * R; ++m) acc[i][m] = v16i{0};
     const u32 *bz32 = reinterpret_cast<const u32 *>(bz);
+    const u32 nbz = 8 * (D + 2 + R);
 
     for (i64 d0 = ulo; d0 <= uhi; d0 += D) {
         const i64 d1 = std::min<i64>(d0 + D - 1, uhi);
-        const i64 cbase = W0g - d1;
-        const i64 nslots = Wend - d0 - cbase + 1;
+        const i64 cbase = R * W0g - d1;
+        const i64 nslots = R * Wend - d0 - cbase + 1;
         __syncthreads();
         // Staging, SG elements per thread at a time: unconditional loads from clamped
         // indices first (no branch between a load and its use, so one wait per group),
         // then out-of-range elements replaced by zero and the signed offset applied.
         constexpr int SG = 8;
-        for (u32 k0 = threadIdx.x; k0 < 8 * (D + 3); k0 += 256 * SG) {
+        for (u32 k0 = threadIdx.x; k0 < nbz; k0 += 256 * SG) {
             u64 v[SG];
 #pragma unroll
             for (int j = 0; j < SG; ++j) {
@@ -344,7 +364,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int j = 0; j < SG; ++j) {
                 const u32 k = k0 + 256 * j;
                 const i64 m = 8 * (d0 - 1) + (i64)k;
-                if (k < 8 * (D + 3)) bz[k] = (m >= 0 && m < (i64)nb) ? (v[j] ^ XOR80) : 0ull;
+                if (k < nbz) bz[k] = (m >= 0 && m < (i64)nb) ? (v[j] ^ XOR80) : 0ull;
             }
         }
         for (u32 k0 = threadIdx.x; k0 < 8 * nslots; k0 += 256 * SG) {
@@ -375,30 +395,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             // Two steps per trip with two register sets (X, Y): while one step's MFMAs
             // run, the LDS reads of the next step land in the other set, a whole step
             // ahead of their use.  The byte shift is the same for every fragment of a
-            // lane.  Toeplitz fragments: step d uses T(d, 0), T(d, 32), T(d, 64) and
-            // T(d, 64) == T(d + 1, 0), so each step reads two new ones.
+            // lane.  Fragment T(d, 32 q) is 8 q words after T(d, 0), and T(d + 1, 32 q)
+            // = T(d, 32 q + 64): step d + 1 needs two new fragments, T(d, 64 R + 32) and
+            // T(d, 64 R + 64).
             const u32 sh = (x + 1) & 3u;
             const u32 lane_off = x + 1 + 16 * h;
             // Running LDS pointers: pT = fragment T(d, 0) in bz (a step moves it by 16
             // words), pA[i] = block i's a chunk slot at step d + 2 in az (a step moves
-            // it back one slot; the trip's reads sit at non-negative offsets from it).  The reads for step d + 2
-            // in the last trip may lie one step past dhi: still inside the LDS arrays
-            // (b digits of step d1 + 1 are staged; slot -1 is the end of bz), unused.
+            // it back one slot; the trip's reads sit at non-negative offsets from it).
+            // The reads for step d + 2 in the last trip may lie one step past dhi: still
+            // inside the staged arrays (b digits up to step d1 + 1 + R are staged; slot
+            // -1 is the end of bz), unused.
             lds_cptr<u32> pT = (lds_cptr<u32>)bz32 + (lane_off >> 2) + 16 * (int)(dlo - d0);
             lds_cptr<u64> pA[NW];
 #pragma unroll
             for (int i = 0; i < NW; ++i)
-                pA[i] = (lds_cptr<u64>)az + AZ_SLOT_U64 * (int)(32 * (wb0 + (i64)wave * NW + i) + (i64)x - cbase - dlo - 2) +
-                        2 * (int)h;
-            v4i FX1, FX2, FY1, FY2, FY2p;
+                pA[i] = (lds_cptr<u64>)az +
+                        AZ_SLOT_U64 * (int)(R * (32 * (wb0 + (i64)wave * NW + i) + (i64)x) - cbase - dlo - 2) + 2 * (int)h;
+            v4i F[2 * R + 1], G[2 * R + 1];
             v4i AX0[NW], AX1[NW], AY0[NW], AY1[NW];
-            // prologue: step dlo into X; its first fragment into FY2p (the role the
-            // previous Y step's last fragment plays in the loop)
-            FY2p = toeplitz_combine(tw_at(pT, 0), sh);
-            FX1 = toeplitz_combine(tw_at(pT, 8), sh);
-            FX2 = toeplitz_combine(tw_at(pT, 16), sh);
+            // prologue: step dlo's fragments into F, its a fragments into AX
             // (volatile: keeps the compiler from merging these reads with the loop's
             // reads of the same registers into one read at the top of the loop)
+#pragma unroll
+            for (int q = 0; q <= 2 * R; ++q) F[q] = toeplitz_combine(tw_at(pT, 8 * q), sh);
 #pragma unroll
             for (int i = 0; i < NW; ++i) {
                 AX0[i] = *(const volatile __attribute__((address_space(3))) v4i *)(pA[i] + 2 * AZ_SLOT_U64);
@@ -407,55 +427,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             // Every block of the wave runs every step of the wave's range: outside a
             // block's own range its a chunks are zero-padded in LDS, so those MFMAs add
             // zero.  No branches around MFMAs (the compiler would copy the
-            // accumulators); independent accumulators sit between the two MFMAs that
-            // update the same one.  One basic block per trip.
+            // accumulators).  One basic block per trip.
             for (i64 d = dlo; d <= dhi; d += 2) {
                 // ---- step d on X; reads of step d + 1 into Y ----
-                const TWords ty1 = tw_at(pT, 24);
-                const TWords ty2 = tw_at(pT, 32);
+                const TWords ty1 = tw_at(pT, 16 * R + 8);
+                const TWords ty2 = tw_at(pT, 16 * R + 16);
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
                     AY0[i] = *(lds_cptr<v4i>)(pA[i] + AZ_SLOT_U64);
                     AY1[i] = *(lds_cptr<v4i>)(pA[i] + AZ_SLOT_U64 + 4);
                 }
+                mfma_step<NW, R>(acc, F, AX0, AX1);
 #pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY2p, AX0[i], acc[i][0], 0, 0, 0);
-                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX1, AX0[i], acc[i][1], 0, 0, 0);
-                }
-#pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX1, AX1[i], acc[i][0], 0, 0, 0);
-                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX2, AX1[i], acc[i][1], 0, 0, 0);
-                }
-                FY1 = toeplitz_combine(ty1, sh);
-                FY2 = toeplitz_combine(ty2, sh);
-                mfma_step_order();
+                for (int q = 0; q + 2 <= 2 * R; ++q) G[q] = F[q + 2];
+                G[2 * R - 1] = toeplitz_combine(ty1, sh);
+                G[2 * R] = toeplitz_combine(ty2, sh);
+                mfma_step_order<NW, R>();
                 // ---- step d + 1 on Y; reads of step d + 2 into X ----
-                const TWords tx1 = tw_at(pT, 40);
-                const TWords tx2 = tw_at(pT, 48);
+                const TWords tx1 = tw_at(pT, 16 * R + 24);
+                const TWords tx2 = tw_at(pT, 16 * R + 32);
 #pragma unroll
                 for (int i = 0; i < NW; ++i) {
                     AX0[i] = *(lds_cptr<v4i>)(pA[i]);
                     AX1[i] = *(lds_cptr<v4i>)(pA[i] + 4);
                 }
+                mfma_step<NW, R>(acc, G, AY0, AY1);
 #pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FX2, AY0[i], acc[i][0], 0, 0, 0);
-                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY1, AY0[i], acc[i][1], 0, 0, 0);
-                }
-#pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    acc[i][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY1, AY1[i], acc[i][0], 0, 0, 0);
-                    acc[i][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(FY2, AY1[i], acc[i][1], 0, 0, 0);
-                }
-                FY2p = FY2;
-                FX1 = toeplitz_combine(tx1, sh);
-                FX2 = toeplitz_combine(tx2, sh);
+                for (int q = 0; q + 2 <= 2 * R; ++q) F[q] = G[q + 2];
+                F[2 * R - 1] = toeplitz_combine(tx1, sh);
+                F[2 * R] = toeplitz_combine(tx2, sh);
                 pT += 32;
 #pragma unroll
                 for (int i = 0; i < NW; ++i) pA[i] -= 2 * AZ_SLOT_U64;
-                mfma_step_order();
+                mfma_step_order<NW, R>();
             }
         }
     }
@@ -470,18 +474,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const i64 wb = wb0 + (i64)wave * NW + i;
             if (wb >= nWb) continue;
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
+            for (int mi = 0; mi < 2 * R; ++mi)
 #pragma unroll
                 for (int gg = 0; gg < 16; ++gg) {
-                    const u64 t = 64 * ((u64)(32 * wb) + x) + 32 * mi + acc_row(gg, lane);
+                    const u64 t = 64 * R * ((u64)(32 * wb) + x) + 32 * mi + acc_row(gg, lane);
                     if (t < 8 * (u64)P) pc[t] = acc[i][mi][gg];
                 }
         }
         return;
     }
     // ---- epilogue: exact column sums -> limb values -> lo / shifted hi ----
-    // Lane (x, h) holds, for each of its blocks, columns t = 64 W + 32 mi + 8 m + 4 h + ii
-    // (W = 32 wb + x): limb jl = 4 mi + m of W's eight, digits u = 4 h + ii.
+    // Lane (x, h) holds, for each of its blocks, columns t = 64 R W + 32 mi + 8 m + 4 h + ii
+    // (W = 32 wb + x): limb jl = 4 mi + m of W's 8 R, digits u = 4 h + ii.  M-blocks
+    // pair up (mi = 2 s, 2 s + 1): lane h keeps limb 8 s + 4 h + m and takes the other
+    // half of its digits from the partner lane (lane xor 32).
     const u64 *la = lpa + pair * (na + 1), *lb = lpb + pair * (nb + 1);
     const u64 nda = 8 * na, ndb = 8 * nb;
     u64 *lo_out = LO + pair * (u64)P, *hs_out = HS + pair * (u64)P;
@@ -490,40 +496,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const i64 wb = wb0 + (i64)wave * NW + i;
         if (wb >= nWb) continue;
         const u64 W = (u64)(32 * wb) + x;
-        u64 plo[2][4], phi[2][4];
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
+        for (int s = 0; s < R; ++s) {
+            u64 plo[2][4], phi[2][4];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int mi = 2 * s + e;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const i64 j = (i64)(8 * R * W) + 4 * mi + m;
+                    const ColTerm A1 = col_term(pa, la, na, j), A2 = col_term(pa, la, na, j - (i64)nb);
+                    const ColTerm B1 = col_term(pb, lb, nb, j), B2 = col_term(pb, lb, nb, j - (i64)na);
+                    u128 v = 0;
+#pragma unroll
+                    for (int ii = 0; ii < 4; ++ii) {
+                        const u32 u = 4 * h + ii;
+                        const u64 t = 8 * (u64)j + u;
+                        const i64 cf =
+                            column_exact((i64)acc[i][mi][4 * m + ii], false, t, u, nda, ndb, A1, A2, B1, B2);
+                        v += (u128)(u64)cf << (8 * u);
+                    }
+                    plo[e][m] = (u64)v;
+                    phi[e][m] = (u64)(v >> 64);
+                }
+            }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const i64 j = (i64)(8 * W) + 4 * mi + m;
-                const ColTerm A1 = col_term(pa, la, na, j), A2 = col_term(pa, la, na, j - (i64)nb);
-                const ColTerm B1 = col_term(pb, lb, nb, j), B2 = col_term(pb, lb, nb, j - (i64)na);
-                u128 v = 0;
-#pragma unroll
-                for (int ii = 0; ii < 4; ++ii) {
-                    const u32 u = 4 * h + ii;
-                    const u64 t = 8 * (u64)j + u;
-                    const i64 cf = column_exact((i64)acc[i][mi][4 * m + ii], false, t, u, nda, ndb, A1, A2, B1, B2);
-                    v += (u128)(u64)cf << (8 * u);
+                const u64 slo = h ? plo[0][m] : plo[1][m];
+                const u64 shi = h ? phi[0][m] : phi[1][m];
+                const u64 rlo = __shfl_xor(slo, 32);
+                const u64 rhi = __shfl_xor(shi, 32);
+                const u64 klo = h ? plo[1][m] : plo[0][m];
+                const u64 khi = h ? phi[1][m] : phi[0][m];
+                const u128 V = (((u128)khi << 64) | klo) + (((u128)rhi << 64) | rlo);
+                const u64 j = 8 * R * W + 8 * s + 4 * h + m;
+                if (j < (u64)P) {
+                    lo_out[j] = (u64)V;
+                    if (j + 1 < (u64)P) hs_out[j + 1] = (u64)(V >> 64);
+                    if (j == 0) hs_out[0] = 0;
                 }
-                plo[mi][m] = (u64)v;
-                phi[mi][m] = (u64)(v >> 64);
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const u64 slo = h ? plo[0][m] : plo[1][m];
-            const u64 shi = h ? phi[0][m] : phi[1][m];
-            const u64 rlo = __shfl_xor(slo, 32);
-            const u64 rhi = __shfl_xor(shi, 32);
-            const u64 klo = h ? plo[1][m] : plo[0][m];
-            const u64 khi = h ? phi[1][m] : phi[0][m];
-            const u128 V = (((u128)khi << 64) | klo) + (((u128)rhi << 64) | rlo);
-            const u64 j = 8 * W + 4 * h + m;
-            if (j < (u64)P) {
-                lo_out[j] = (u64)V;
-                if (j + 1 < (u64)P) hs_out[j + 1] = (u64)(V >> 64);
-                if (j == 0) hs_out[0] = 0;
             }
         }
     }
@@ -605,11 +616,9 @@ struct MfmaPlan {
     u32 nslices;
 };
 static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
-    constexpr int NW = 2;
     const u64 P = na + nb;
-    const u64 nWb = (P + 255) / 256;
-    MfmaPlan mp{(nWb + 4 * NW - 1) / (4 * NW), 1};
-    const u64 steps = (8 * nb + 62) / 64 + 1;
+    MfmaPlan mp{(P + 2047) / 2048, 1};  // a workgroup covers 2048 output limbs
+    const u64 steps = (8 * nb + 62) / 64 + (u64)ctx->tune.mfma_rows;  // d from 1 - R to dmax
     const u64 blocks = mp.ngroups * npairs;
     const u64 target = (u64)std::max(1, ctx->num_cu) * 4;
     // digit products in a column: at most the shorter operand's digit count
@@ -717,21 +726,23 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         hipLaunchKernelGGL(k_prep_scan, dim3((u32)prep_blocks), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
                            (u32)nseg);
         if ((st = bn_launch_status()) != BN_OK) return st;
-        constexpr int NW = 2;
+        // (blocks per wave, Toeplitz row groups): both shapes cover 2048 output limbs
+        // per workgroup and stage the same LDS window
+        const int R = ctx->tune.mfma_rows;
+        const int NW = 2 / R;
         const u32 D = (u32)ctx->tune.mfma_chunk;
         const u64 blocks = mp.ngroups * npairs * mp.nslices;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
-        const size_t lds = (size_t)64 * (D + 3) + (size_t)80 * (128 * NW + D);
+        const size_t lds = (size_t)64 * (D + 2 + R) + (size_t)80 * (128 * NW * R + D);
+        int *part = split ? reinterpret_cast<int *>(ws + L.part) : nullptr;
+        auto kern = R == 2 ? (split ? k_mul_large_mfma<1, 2, true> : k_mul_large_mfma<1, 2, false>)
+                           : (split ? k_mul_large_mfma<2, 1, true> : k_mul_large_mfma<2, 1, false>);
+        hipLaunchKernelGGL(kern, dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb, npairs, lpa, lpb, D,
+                           (u32)mp.ngroups, split ? mp.nslices : 1u, LO, HS, part);
         if (split) {
-            int *part = reinterpret_cast<int *>(ws + L.part);
-            hipLaunchKernelGGL((k_mul_large_mfma<NW, true>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb, npairs,
-                               lpa, lpb, D, (u32)mp.ngroups, mp.nslices, LO, HS, part);
             if ((st = bn_launch_status()) != BN_OK) return st;
             hipLaunchKernelGGL(k_fold_mfma_cols, dim3((u32)fold_blocks), dim3(256), 0, s, part, mp.nslices, a, b, lpa,
                                lpb, na, nb, npairs, LO, HS);
-        } else {
-            hipLaunchKernelGGL((k_mul_large_mfma<NW, false>), dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb,
-                               npairs, lpa, lpb, D, (u32)mp.ngroups, 1u, LO, HS, nullptr);
         }
         if ((st = bn_launch_status()) != BN_OK) return st;
     }

@@ -247,7 +247,8 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         fprintf(f, "    \"addsub.batch_waves\": %d,\n    \"addsub.batch_rows\": %d,\n", t.batch_waves, t.batch_rows);
         fprintf(f, "    \"addsub.chain_waves\": %d,\n    \"addsub.chain_rows\": %d,\n", t.chain_waves, t.chain_rows);
         fprintf(f, "    \"mul.crossover_limbs\": %lld,\n", (long long)t.mul_crossover_limbs);
-        fprintf(f, "    \"mul.mad_xchunk\": %d,\n    \"mul.mfma_chunk\": %d\n}\n", t.mad_xchunk, t.mfma_chunk);
+        fprintf(f, "    \"mul.mad_xchunk\": %d,\n    \"mul.mfma_chunk\": %d,\n    \"mul.mfma_rows\": %d\n}\n",
+                t.mad_xchunk, t.mfma_chunk, t.mfma_rows);
         fclose(f);
     }
     return BN_OK;
