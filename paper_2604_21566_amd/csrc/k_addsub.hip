@@ -467,9 +467,11 @@ constexpr int UNALIGNED_CHAIN_WAVES = 4, UNALIGNED_CHAIN_ROWS = 4;
 
 bool flat_scan_shape_ok(int waves, int rows) { return pick<false, false>(waves, rows) != nullptr; }
 
-// Shape for a launch over segments of n limbs: the independent-tile shape when its
-// tile length is a multiple of n, else the chained (look-back) shape.
-static void flat_scan_shape(const bn_ctx *ctx, u64 n, bool vec, int &waves, int &rows, bool &chain) {
+// Shape for a launch over N limbs in segments of n: the independent-tile shape when
+// its tile length is a multiple of n, else the chained (look-back) shape, with its
+// rows halved (aligned operands) until the launch has at least 8 tiles per CU -- a
+// 2^20-limb chained launch in 4096-limb tiles would leave most of the device idle.
+static void flat_scan_shape(const bn_ctx *ctx, u64 n, u64 N, bool vec, int &waves, int &rows, bool &chain) {
     const int bw = vec ? ctx->tune.batch_waves : UNALIGNED_BATCH_WAVES;
     const int br = vec ? ctx->tune.batch_rows : UNALIGNED_BATCH_ROWS;
     const u64 tl = (u64)bw * br * 128;
@@ -480,6 +482,8 @@ static void flat_scan_shape(const bn_ctx *ctx, u64 n, bool vec, int &waves, int 
     } else {
         waves = vec ? ctx->tune.chain_waves : UNALIGNED_CHAIN_WAVES;
         rows = vec ? ctx->tune.chain_rows : UNALIGNED_CHAIN_ROWS;
+        const u64 want = 8 * (u64)std::max(1, ctx->num_cu);
+        while (vec && rows > 1 && (N + (u64)waves * rows * 128 - 1) / ((u64)waves * rows * 128) < want) rows /= 2;
     }
 }
 
@@ -490,7 +494,7 @@ size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N) {
     for (int v = 0; v < 2; ++v) {
         int waves = 1, rows = 1;
         bool chain = false;
-        flat_scan_shape(ctx, n, v == 1, waves, rows, chain);
+        flat_scan_shape(ctx, n, N, v == 1, waves, rows, chain);
         const u64 TL = (u64)waves * rows * 128;
         tiles = std::max<u64>(tiles, (N + TL - 1) / TL);
     }
@@ -523,7 +527,7 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     int waves, rows;
     bool chain;
     if (ext == 0) {
-        flat_scan_shape(ctx, n, vec, waves, rows, chain);
+        flat_scan_shape(ctx, n, N, vec, waves, rows, chain);
     } else {
         chain = (128 % n) != 0;
         waves = chain ? (vec ? 4 : UNALIGNED_CHAIN_WAVES) : 1;

@@ -221,8 +221,12 @@ def test_lookback_histogram_counts_every_chained_tile(bnctx, op, n, npairs):
     old = bn.bn_get_param(bnctx, "debug.flags")
     waves = bn.bn_get_param(bnctx, "addsub.chain_waves")
     rows = bn.bn_get_param(bnctx, "addsub.chain_rows")
-    TL = waves * rows * 128
     N = n * npairs
+    # the launch halves the tuned rows until it has at least 8 tiles per CU
+    want = 8 * torch.cuda.get_device_properties(0).multi_processor_count
+    while rows > 1 and -(-N // (waves * rows * 128)) < want:
+        rows //= 2
+    TL = waves * rows * 128
     ntiles = -(-N // TL)
     expect = sum(1 for t in range(1, ntiles) if (t * TL) % n != 0)
     a, b = wl.c3(op, n=N, worst=True)
