@@ -127,17 +127,52 @@ __global__ void k_fold_mad(const u64 *__restrict__ colLo, const u64 *__restrict_
 // limbs in the workgroup.
 constexpr u32 PREP_SEG = 1024;  // limbs per segment: 256 threads x 4 limbs
 
+// Entries per operand in a prefix table: n + 1, rounded up to even so that every
+// operand's table starts 16-byte aligned.
+__host__ __device__ __forceinline__ u64 lp_stride(u64 n) { return (n + 2) & ~1ull; }
+
 __device__ __forceinline__ const u64 *prep_operand(const u64 *a, const u64 *b, u64 na, u64 nb, u64 op_pair, u64 &n,
                                                    u64 *lpa, u64 *lpb, u64 *&lp) {
     const u64 pair = op_pair >> 1;
     if (op_pair & 1) {
         n = nb;
-        lp = lpb + pair * (nb + 1);
+        lp = lpb + pair * lp_stride(nb);
         return b + pair * nb;
     }
     n = na;
-    lp = lpa + pair * (na + 1);
+    lp = lpa + pair * lp_stride(na);
     return a + pair * na;
+}
+
+// Limbs base .. base+3 of x (zero past n): two 16-byte loads when they are all in
+// range and aligned (a wave then reads one contiguous 2 KiB run), else one by one.
+__device__ __forceinline__ void load4(const u64 *__restrict__ x, u64 base, u64 n, u64 (&v)[4]) {
+    typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+    if (base + 4 <= n && (((uintptr_t)(x + base)) & 15u) == 0) {
+        const u64x2 lo = *reinterpret_cast<const u64x2 *>(x + base);
+        const u64x2 hi = *reinterpret_cast<const u64x2 *>(x + base + 2);
+        v[0] = lo.x;
+        v[1] = lo.y;
+        v[2] = hi.x;
+        v[3] = hi.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = base + k < n ? x[base + k] : 0ull;
+    }
+}
+
+// lp[base .. base+3] = v (entries at or past n are not written), 16-byte stores when
+// aligned.
+__device__ __forceinline__ void store4(u64 *__restrict__ lp, u64 base, u64 n, const u64 (&v)[4]) {
+    typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+    if (base + 4 <= n && (((uintptr_t)(lp + base)) & 15u) == 0) {
+        *reinterpret_cast<u64x2 *>(lp + base) = u64x2{v[0], v[1]};
+        *reinterpret_cast<u64x2 *>(lp + base + 2) = u64x2{v[2], v[3]};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (base + k < n) lp[base + k] = v[k];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
@@ -149,10 +184,11 @@ __global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, 
     const u64 op_pair = blockIdx.x / nseg, sg = blockIdx.x % nseg;
     const u64 *x = prep_operand(a, b, na, nb, op_pair, n, lpa, lpb, lp);
     const u64 base = sg * PREP_SEG + 4 * (u64)threadIdx.x;
+    u64 v[4];
+    load4(x, base, n, v);
     u32 sum = 0;  // at most 1024 limbs x 2040
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (base + k < n) sum += bytesum64(x[base + k]);
+    for (int k = 0; k < 4; ++k) sum += bytesum64(v[k]);
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sum;
     __syncthreads();
@@ -176,10 +212,12 @@ __global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, co
     for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
     if (lane == 0) shp[w] = pre;
     const u64 base = seg0 + 4 * (u64)threadIdx.x;
+    u64 limbs[4];
+    load4(x, base, n, limbs);
     u32 v[4], sum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        v[k] = base + k < n ? bytesum64(x[base + k]) : 0u;
+        v[k] = bytesum64(limbs[k]);
         sum += v[k];
     }
     // exclusive scan of the per-thread sums over the workgroup
@@ -192,12 +230,14 @@ __global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, co
     __syncthreads();
     u64 run = shp[0] + shp[1] + shp[2] + shp[3] + inc - sum;
     for (int i = 0; i < w; ++i) run += sh[i];
+    u64 out[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (base + k < n) lp[base + k] = run;
+        out[k] = run;
         run += v[k];
         if (base + k + 1 == n) lp[n] = run;
     }
+    store4(lp, base, n, out);
     if (n == 0 && threadIdx.x == 0) lp[0] = 0;
 }
 
@@ -488,7 +528,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // (W = 32 wb + x): limb jl = 4 mi + m of W's 8 R, digits u = 4 h + ii.  M-blocks
     // pair up (mi = 2 s, 2 s + 1): lane h keeps limb 8 s + 4 h + m and takes the other
     // half of its digits from the partner lane (lane xor 32).
-    const u64 *la = lpa + pair * (na + 1), *lb = lpb + pair * (nb + 1);
+    const u64 *la = lpa + pair * lp_stride(na), *lb = lpb + pair * lp_stride(nb);
     const u64 nda = 8 * na, ndb = 8 * nb;
     u64 *lo_out = LO + pair * (u64)P, *hs_out = HS + pair * (u64)P;
 #pragma unroll
@@ -549,7 +589,7 @@ __global__ void k_fold_mfma_cols(const int *__restrict__ part, u32 nslices, cons
     for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
         const u64 p = idx / P, j = idx - p * P;
         const u64 *pa = a + p * na, *pb = b + p * nb;
-        const u64 *la = lpa + p * (na + 1), *lb = lpb + p * (nb + 1);
+        const u64 *la = lpa + p * lp_stride(na), *lb = lpb + p * lp_stride(nb);
         const int *pc = part + p * 8 * P + 8 * j;
         const ColTerm A1 = col_term(pa, la, na, (i64)j), A2 = col_term(pa, la, na, (i64)j - (i64)nb);
         const ColTerm B1 = col_term(pb, lb, nb, (i64)j), B2 = col_term(pb, lb, nb, (i64)j - (i64)na);
@@ -592,9 +632,9 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, u32 nslice
             off = align256(off + (size_t)nslices * npairs * 8 * P * 4);
         }
         L.lpa = off;
-        off = align256(off + npairs * (na + 1) * 8);
+        off = align256(off + npairs * lp_stride(na) * 8);
         L.lpb = off;
-        off = align256(off + npairs * (nb + 1) * 8);
+        off = align256(off + npairs * lp_stride(nb) * 8);
         L.seg = off;
         off = align256(off + npairs * 2 * ((std::max(na, nb) + PREP_SEG - 1) / PREP_SEG + 1) * 4);
     }
