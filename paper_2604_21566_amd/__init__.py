@@ -130,8 +130,10 @@ def bn_version() -> str:
 
 
 # ------------------------------------------------------------------ marshalling ----
-def _ptr(t, what: str):
-    """Device pointer of a contiguous int64/uint64 torch tensor (None -> NULL)."""
+def _ptr(t, what: str, need: int | None = None):
+    """Device pointer of a contiguous int64/uint64 torch tensor (None -> NULL).  `need`:
+    the limbs the call will touch through this pointer; a smaller tensor is refused
+    here, because a device pointer carries no extent that the library could check."""
     if t is None:
         return None
     import torch
@@ -143,6 +145,8 @@ def _ptr(t, what: str):
         raise TypeError(f"{what}: limbs must be int64/uint64, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{what}: tensor must be contiguous")
+    if need is not None and t.numel() < need:
+        raise ValueError(f"{what}: tensor holds {t.numel()} limbs, the call touches {need}")
     return t.data_ptr() if t.numel() else None
 
 
@@ -226,22 +230,28 @@ def bn_load_tuning(ctx, path: str):
 # ------------------------------------------------------------------ add / sub ----
 def bn_add(ctx, r, a, b, carry_out=None, stream=None):
     """r = a + b (one pair, n = a.numel() limbs); carry_out: 1-limb tensor or None."""
-    _ck(lib().bn_add(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), a.numel(), _ptr(carry_out, "carry"),
+    n = a.numel()
+    _ck(lib().bn_add(ctx, _ptr(r, "r", n), _ptr(a, "a"), _ptr(b, "b", n), n, _ptr(carry_out, "carry", 1),
                      _stream(stream)), "bn_add")
 
 
 def bn_sub(ctx, r, a, b, borrow_out=None, stream=None):
-    _ck(lib().bn_sub(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), a.numel(), _ptr(borrow_out, "borrow"),
+    n = a.numel()
+    _ck(lib().bn_sub(ctx, _ptr(r, "r", n), _ptr(a, "a"), _ptr(b, "b", n), n, _ptr(borrow_out, "borrow", 1),
                      _stream(stream)), "bn_sub")
 
 
 def bn_add_n_batch(ctx, r, a, b, n: int, npairs: int, carry_out=None, stream=None):
-    _ck(lib().bn_add_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(carry_out, "carry"),
+    N = n * npairs
+    _ck(lib().bn_add_n_batch(ctx, _ptr(r, "r", N), _ptr(a, "a", N), _ptr(b, "b", N), n, npairs,
+                             _ptr(carry_out, "carry", npairs),
                              _stream(stream)), "bn_add_n_batch")
 
 
 def bn_sub_n_batch(ctx, r, a, b, n: int, npairs: int, borrow_out=None, stream=None):
-    _ck(lib().bn_sub_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(borrow_out, "borrow"),
+    N = n * npairs
+    _ck(lib().bn_sub_n_batch(ctx, _ptr(r, "r", N), _ptr(a, "a", N), _ptr(b, "b", N), n, npairs,
+                             _ptr(borrow_out, "borrow", npairs),
                              _stream(stream)), "bn_sub_n_batch")
 
 
@@ -251,43 +261,54 @@ def _form(form):
 
 
 def bn_mul(ctx, r, a, b, form=BN_MUL_AUTO, stream=None):
-    _ck(lib().bn_mul(ctx, _ptr(r, "r"), _ptr(a, "a"), a.numel(), _ptr(b, "b"), b.numel(), _form(form),
+    _ck(lib().bn_mul(ctx, _ptr(r, "r", a.numel() + b.numel()), _ptr(a, "a"), a.numel(), _ptr(b, "b"), b.numel(),
+                     _form(form),
                      _stream(stream)), "bn_mul")
 
 
 def bn_mul_n_batch(ctx, r, a, b, na: int, nb: int, npairs: int, form=BN_MUL_AUTO, stream=None):
-    _ck(lib().bn_mul_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), na, nb, npairs, _form(form),
+    _ck(lib().bn_mul_n_batch(ctx, _ptr(r, "r", (na + nb) * npairs), _ptr(a, "a", na * npairs),
+                             _ptr(b, "b", nb * npairs), na, nb, npairs, _form(form),
                              _stream(stream)), "bn_mul_n_batch")
 
 
 def bn_add_nc_n_batch(ctx, r, a, b, n: int, npairs: int, carry_in, carry_out=None, stream=None):
-    _ck(lib().bn_add_nc_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(carry_in, "carry_in"),
-                                _ptr(carry_out, "carry_out"), _stream(stream)), "bn_add_nc_n_batch")
+    N = n * npairs
+    _ck(lib().bn_add_nc_n_batch(ctx, _ptr(r, "r", N), _ptr(a, "a", N), _ptr(b, "b", N), n, npairs,
+                                _ptr(carry_in, "carry_in", npairs), _ptr(carry_out, "carry_out", npairs),
+                                _stream(stream)), "bn_add_nc_n_batch")
 
 
 def bn_sub_nc_n_batch(ctx, r, a, b, n: int, npairs: int, borrow_in, borrow_out=None, stream=None):
-    _ck(lib().bn_sub_nc_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs,
-                                _ptr(borrow_in, "borrow_in"), _ptr(borrow_out, "borrow_out"), _stream(stream)),
+    N = n * npairs
+    _ck(lib().bn_sub_nc_n_batch(ctx, _ptr(r, "r", N), _ptr(a, "a", N), _ptr(b, "b", N), n, npairs,
+                                _ptr(borrow_in, "borrow_in", npairs), _ptr(borrow_out, "borrow_out", npairs),
+                                _stream(stream)),
         "bn_sub_nc_n_batch")
 
 
 def bn_add_unequal(ctx, r, a, na: int, b, nb: int, carry_out=None, stream=None):
-    _ck(lib().bn_add_unequal(ctx, _ptr(r, "r"), _ptr(a, "a"), na, _ptr(b, "b"), nb, _ptr(carry_out, "carry_out"),
+    _ck(lib().bn_add_unequal(ctx, _ptr(r, "r", na), _ptr(a, "a", na), na, _ptr(b, "b", nb), nb,
+                             _ptr(carry_out, "carry_out", 1),
                              _stream(stream)), "bn_add_unequal")
 
 
 def bn_sub_unequal(ctx, r, a, na: int, b, nb: int, borrow_out=None, stream=None):
-    _ck(lib().bn_sub_unequal(ctx, _ptr(r, "r"), _ptr(a, "a"), na, _ptr(b, "b"), nb, _ptr(borrow_out, "borrow_out"),
+    _ck(lib().bn_sub_unequal(ctx, _ptr(r, "r", na), _ptr(a, "a", na), na, _ptr(b, "b", nb), nb,
+                             _ptr(borrow_out, "borrow_out", 1),
                              _stream(stream)), "bn_sub_unequal")
 
 
 def bn_sub_abs_n_batch(ctx, r, a, b, n: int, npairs: int, sign=None, stream=None):
-    _ck(lib().bn_sub_abs_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, _ptr(sign, "sign"),
+    N = n * npairs
+    _ck(lib().bn_sub_abs_n_batch(ctx, _ptr(r, "r", N), _ptr(a, "a", N), _ptr(b, "b", N), n, npairs,
+                                 _ptr(sign, "sign", npairs),
                                  _stream(stream)), "bn_sub_abs_n_batch")
 
 
 def bn_mul_karatsuba_n_batch(ctx, r, a, b, n: int, npairs: int, levels: int, form=BN_MUL_AUTO, stream=None):
-    _ck(lib().bn_mul_karatsuba_n_batch(ctx, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), n, npairs, int(levels),
+    _ck(lib().bn_mul_karatsuba_n_batch(ctx, _ptr(r, "r", 2 * n * npairs), _ptr(a, "a", n * npairs),
+                                       _ptr(b, "b", n * npairs), n, npairs, int(levels),
                                        _form(form), _stream(stream)), "bn_mul_karatsuba_n_batch")
 
 
@@ -301,10 +322,24 @@ def _pairs(desc):
     return arr, len(d)
 
 
+# pool extents (limbs) each live plan's calls touch: (a, b, r, pairs)
+_PLAN_EXTENTS: dict = {}
+
+
+def _extents(desc, mul: bool):
+    d = np.asarray(desc, dtype=np.int64).reshape(-1, 5)
+    if len(d) == 0:
+        return (0, 0, 0, 0)
+    a_off, b_off, r_off, na, nb = d.T
+    r_len = na + nb if mul else na
+    return (int((a_off + na).max()), int((b_off + nb).max()), int((r_off + r_len).max()), len(d))
+
+
 def bn_plan_mul_ragged(ctx, desc, form=BN_MUL_AUTO):
     arr, n = _pairs(desc)
     plan = _vp()
     _ck(lib().bn_plan_mul_ragged(ctx, arr, n, _form(form), ctypes.byref(plan)), "bn_plan_mul_ragged")
+    _PLAN_EXTENTS[plan.value] = _extents(desc, True)
     return plan
 
 
@@ -312,36 +347,46 @@ def bn_plan_add_ragged(ctx, desc):
     arr, n = _pairs(desc)
     plan = _vp()
     _ck(lib().bn_plan_add_ragged(ctx, arr, n, ctypes.byref(plan)), "bn_plan_add_ragged")
+    _PLAN_EXTENTS[plan.value] = _extents(desc, False)
     return plan
 
 
 def bn_plan_destroy(plan):
+    _PLAN_EXTENTS.pop(getattr(plan, "value", None), None)
     _ck(lib().bn_plan_destroy(plan), "bn_plan_destroy")
 
 
+def _pools(plan, r_pool, a_pool, b_pool):
+    ea, eb, er, _ = _PLAN_EXTENTS.get(getattr(plan, "value", None), (None, None, None, None))
+    return _ptr(r_pool, "r", er), _ptr(a_pool, "a", ea), _ptr(b_pool, "b", eb)
+
+
 def bn_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, stream=None):
-    _ck(lib().bn_mul_ragged(ctx, plan, _ptr(r_pool, "r"), _ptr(a_pool, "a"), _ptr(b_pool, "b"), _stream(stream)),
-        "bn_mul_ragged")
+    _ck(lib().bn_mul_ragged(ctx, plan, *_pools(plan, r_pool, a_pool, b_pool), _stream(stream)), "bn_mul_ragged")
 
 
 def bn_add_ragged(ctx, plan, r_pool, a_pool, b_pool, carry_out=None, stream=None):
-    _ck(lib().bn_add_ragged(ctx, plan, _ptr(r_pool, "r"), _ptr(a_pool, "a"), _ptr(b_pool, "b"),
-                            _ptr(carry_out, "carry"), _stream(stream)), "bn_add_ragged")
+    npairs = _PLAN_EXTENTS.get(getattr(plan, "value", None), (0, 0, 0, None))[3]
+    _ck(lib().bn_add_ragged(ctx, plan, *_pools(plan, r_pool, a_pool, b_pool), _ptr(carry_out, "carry", npairs),
+                            _stream(stream)), "bn_add_ragged")
 
 
 # ------------------------------------------------------------------ graphs ----
 def bn_graph_capture_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, stream):
     g = _vp()
-    _ck(lib().bn_graph_capture_mul_ragged(ctx, plan, _ptr(r_pool, "r"), _ptr(a_pool, "a"), _ptr(b_pool, "b"),
-                                          _stream(stream), ctypes.byref(g)), "bn_graph_capture_mul_ragged")
+    _ck(lib().bn_graph_capture_mul_ragged(ctx, plan, *_pools(plan, r_pool, a_pool, b_pool), _stream(stream),
+                                          ctypes.byref(g)), "bn_graph_capture_mul_ragged")
     return g
 
 
 def bn_graph_capture_batch(ctx, op: int, r, a, b, na: int, nb: int, npairs: int, carry_out=None,
                            form=BN_MUL_AUTO, stream=None):
     g = _vp()
-    _ck(lib().bn_graph_capture_batch(ctx, op, _ptr(r, "r"), _ptr(a, "a"), _ptr(b, "b"), na, nb, npairs,
-                                     _ptr(carry_out, "carry"), _form(form), _stream(stream), ctypes.byref(g)),
+    rn = (na + nb) * npairs if op == 2 else na * npairs
+    _ck(lib().bn_graph_capture_batch(ctx, op, _ptr(r, "r", rn), _ptr(a, "a", na * npairs),
+                                     _ptr(b, "b", (nb if op == 2 else na) * npairs), na, nb, npairs,
+                                     _ptr(carry_out, "carry", npairs), _form(form), _stream(stream),
+                                     ctypes.byref(g)),
         "bn_graph_capture_batch")
     return g
 

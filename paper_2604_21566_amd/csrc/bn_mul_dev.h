@@ -250,6 +250,40 @@ __device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u32 u, u6
     return m + 128 * (sa + sb) - 16384 * cnt;
 }
 
+// The same decode for the four digits u = 4 h + i (i < 4) of a limb that one lane of
+// the large MFMA kernel holds.  Per term, the in-limb digit sums 0..u come from one
+// running sum over the lane's four bytes (plus the sum of the low four bytes when
+// h = 1) instead of a masked byte sum per column.
+__device__ __forceinline__ void limb_partials4(u64 limb, u32 h, u32 (&p)[4]) {
+    const u32 lo = (u32)limb, hi = (u32)(limb >> 32);
+    const u32 w = h ? hi : lo;
+    u32 run = h ? __builtin_amdgcn_sad_u8(lo, 0u, 0u) : 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        run += (w >> (8 * i)) & 0xffu;
+        p[i] = run;
+    }
+}
+// S(u) = PX(8 q1 + u + 1) - PX(8 q2 + u + 1) for the lane's four digits u
+__device__ __forceinline__ void window4(const ColTerm &T1, const ColTerm &T2, u32 h, i64 (&s)[4]) {
+    u32 p1[4], p2[4];
+    limb_partials4(T1.limb, h, p1);
+    limb_partials4(T2.limb, h, p2);
+    const i64 d = (i64)(T1.pre - T2.pre);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = d + (i64)p1[i] - (i64)p2[i];
+}
+// Column sum from its raw int32 register (true sum modulo 2^32, see column_exact) and
+// its window sums.
+__device__ __forceinline__ i64 column_exact_w(int raw, u64 t, u64 nda, u64 ndb, i64 sa, i64 sb) {
+    const i64 ilo = t + 1 > ndb ? (i64)(t + 1 - ndb) : 0;
+    const i64 ihi = t < nda - 1 ? (i64)t : (i64)nda - 1;
+    const i64 cnt = ihi >= ilo ? ihi - ilo + 1 : 0;
+    i64 m = (i64)raw;
+    if (m < -16256 * cnt) m += (i64)1 << 32;
+    return m + 128 * (sa + sb) - 16384 * cnt;
+}
+
 // Accumulator element (reg g of lane l) -> (row rr, column x) of the 32x32 tile.
 __device__ __forceinline__ u32 acc_row(int g, int lane) { return (u32)((g & 3) + 4 * (lane >> 5) + 8 * (g >> 2)); }
 

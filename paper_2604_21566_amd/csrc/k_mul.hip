@@ -547,17 +547,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                     const i64 j = (i64)(8 * R * W) + 4 * mi + m;
                     const ColTerm A1 = col_term(pa, la, na, j), A2 = col_term(pa, la, na, j - (i64)nb);
                     const ColTerm B1 = col_term(pb, lb, nb, j), B2 = col_term(pb, lb, nb, j - (i64)na);
-                    u128 v = 0;
+                    i64 sa[4], sb[4];
+                    window4(A1, A2, h, sa);
+                    window4(B1, B2, h, sb);
+                    // the lane's four columns: each sum is below 2^34 (at most 131586
+                    // products of at most 255^2), so their value shifted by 8 ii fits 64 bits
+                    u64 wsum = 0;
 #pragma unroll
                     for (int ii = 0; ii < 4; ++ii) {
-                        const u32 u = 4 * h + ii;
-                        const u64 t = 8 * (u64)j + u;
-                        const i64 cf =
-                            column_exact((i64)acc[i][mi][4 * m + ii], false, t, u, nda, ndb, A1, A2, B1, B2);
-                        v += (u128)(u64)cf << (8 * u);
+                        const u64 t = 8 * (u64)j + 4 * h + ii;
+                        const i64 cf = column_exact_w(acc[i][mi][4 * m + ii], t, nda, ndb, sa[ii], sb[ii]);
+                        wsum += (u64)cf << (8 * ii);
                     }
-                    plo[e][m] = (u64)v;
-                    phi[e][m] = (u64)(v >> 64);
+                    plo[e][m] = h ? wsum << 32 : wsum;
+                    phi[e][m] = h ? wsum >> 32 : 0;
                 }
             }
 #pragma unroll

@@ -220,6 +220,16 @@ def test_ragged_add(bnctx):
 def test_mul_errors(bnctx):
     announce("mul argument errors")
     t = torch.zeros(64, dtype=torch.int64, device="cuda")
+    # tensors smaller than the extents a call touches are refused by the binding
+    # before anything reaches the device
+    with pytest.raises(ValueError):
+        bn.bn_mul_n_batch(bnctx, t[:15], t[16:24], t[24:32], 4, 4, 2)   # r needs 16 limbs
+    with pytest.raises(ValueError):
+        bn.bn_mul_n_batch(bnctx, t[:16], t[16:23], t[24:32], 4, 4, 2)   # a needs 8
+    with pytest.raises(ValueError):
+        bn.bn_add_n_batch(bnctx, t[:8], t[8:16], t[16:24], 4, 2, t[24:25])  # 2 carries
+    with pytest.raises(ValueError):
+        bn.bn_mul_karatsuba_n_batch(bnctx, t[:15], t[32:40], t[40:48], 4, 2, 1)  # r needs 16
     with pytest.raises(bn.BnError) as e:
         bn.bn_mul(bnctx, t[16:24], t[0:4], t[8:12], form=7)
     assert e.value.status == bn.BN_EINVAL
