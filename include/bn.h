@@ -224,7 +224,11 @@ typedef struct bn_graph bn_graph;
 bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool,
                                       const uint64_t *a_pool, const uint64_t *b_pool,
                                       bn_stream stream, bn_graph **graph);
-/* Same for a uniform add/sub/mul batch (op: 0 add, 1 sub, 2 mul). */
+/* Same for a uniform add/sub/mul batch (op: 0 add, 1 sub, 2 mul; na = nb = n for
+ * add/sub).  Arguments and errors as for the eager call; for a multiplication whose
+ * output overlaps an operand the staging buffer is reserved here too, and the graph
+ * holds the device-to-device copy as a memcpy node.  The replays share the context's
+ * workspace: replays and eager calls on one context must not overlap in time. */
 bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_t *a, const uint64_t *b,
                                  size_t na, size_t nb, size_t npairs, uint64_t *carry_out, int form,
                                  bn_stream stream, bn_graph **graph);
