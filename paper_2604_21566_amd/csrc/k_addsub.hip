@@ -319,10 +319,44 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     }
     __syncthreads();
 
+    // The tile's real carry-in by look-back (wave 0), its inclusive status published,
+    // and the carry into every wave of the tile.
+    auto resolve_cin = [&]() {
+        if (w == 0) {
+            u32 cin = 0;
+            const u64 first_pos = __shfl(pos0, 0);
+            if (t > 0 && first_pos != 0) {
+                u64 dist;
+                cin = lookback<SUB, EXT>(status, t, epoch, spin_limit, &ctl->err, a, b, G, dist);
+                if ((dbg & 2u) && lane == 0)
+                    __hip_atomic_fetch_add(ctl->hist + (63 - __clzll((long long)dist)), 1ull, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (lane == 0) {
+                if (sh_pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
+                u32 c = cin;
+#pragma unroll
+                for (int i = 0; i < WAVES; ++i) {
+                    sh_cin_true[i] = c;
+                    c = sh_g[i] | (sh_p[i] & c);
+                }
+            }
+        }
+    };
+    // A tile that propagates its carry-in through every limb would have every limb
+    // rewritten after an optimistic store, so it looks back first (its A status is
+    // already published, so the tiles behind it can walk past it meanwhile).
+    const bool early = chain && sh_pt;
+    if (early) {
+        resolve_cin();
+        __syncthreads();
+    }
+
     // ---- phase 4: apply the carries, store sums and per-segment carry-outs ----
     // Stored optimistically: in a chained launch the tile's real carry-in is not
-    // known yet; phase 5 rewrites the few limbs it changes (DoT's rare fix-up).
-    const u32 c_assumed = sh_cin[w];
+    // known yet (unless looked up early above); phase 5 rewrites the few limbs it
+    // changes (DoT's rare fix-up).
+    const u32 c_assumed = early ? sh_cin_true[w] : sh_cin[w];
     {
         u64 c = c_assumed;
         u64 pos = pos0, q = q0;
@@ -365,27 +399,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     if (!chain) return;
 
     // ---- phase 5: the tile's real carry-in (look-back), publish, repair ----
-    if (w == 0) {
-        u32 cin = 0;
-        const u64 first_pos = __shfl(pos0, 0);
-        if (t > 0 && first_pos != 0) {
-            u64 dist;
-            cin = lookback<SUB, EXT>(status, t, epoch, spin_limit, &ctl->err, a, b, G, dist);
-            if ((dbg & 2u) && lane == 0)
-                __hip_atomic_fetch_add(ctl->hist + (63 - __clzll((long long)dist)), 1ull, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            if (sh_pt && !poison) st_relaxed(status + t, (epoch << 2) | (cin ? ST_I1 : ST_I0));
-            u32 c = cin;
-#pragma unroll
-            for (int i = 0; i < WAVES; ++i) {
-                sh_cin_true[i] = c;
-                c = sh_g[i] | (sh_p[i] & c);
-            }
-        }
+    if (!early) {
+        resolve_cin();
+        __syncthreads();  // also orders the optimistic stores before their rewrites
     }
-    __syncthreads();  // also orders the optimistic stores before their rewrites
     const u32 c_true = sh_cin_true[w];
     if (c_true != c_assumed) {
         // Replay the rows with both carries; lanes whose carry differs rewrite the
