@@ -176,6 +176,74 @@ def test_graph_replay_matches_eager(bnctx):
         bn.bn_graph_destroy(g)
 
 
+@pytest.mark.parametrize("op", ["add", "sub"])
+def test_graph_replay_chained(bnctx, op):
+    """A captured chained launch (tiles look back; the graph reads its epoch from the
+    control block and a bump kernel moves it on) replayed four times, with eager
+    chained launches (host epochs) on the same context in between.  All-propagate
+    pairs: every tile but the first of a pair waits for its predecessor's carry."""
+    n, npairs = 300001, 2
+    announce("graph replay, chained", op, f"n={n}", f"npairs={npairs}")
+    if op == "add":
+        a = np.full(n * npairs, 2 ** 64 - 1, np.uint64)
+        b = np.zeros(n * npairs, np.uint64)
+        b[::n] = 1
+        want, wc = oracle.add_batch(a, b, n)
+    else:
+        a = np.zeros(n * npairs, np.uint64)
+        a[n - 1::n] = 1
+        b = np.zeros(n * npairs, np.uint64)
+        b[::n] = 1
+        want, wc = oracle.sub_batch(a, b, n)
+    ta, tb = D(a), D(b)
+    tr = torch.empty_like(ta)
+    tc = torch.empty(npairs, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    g = bn.bn_graph_capture_batch(bnctx, 0 if op == "add" else 1, tr, ta, tb, n, 0, npairs, tc, stream=s)
+    try:
+        for rep in range(4):
+            tr.fill_(7)
+            tc.fill_(7)
+            torch.cuda.synchronize()
+            bn.bn_graph_launch(g, s)
+            s.synchronize()
+            assert (H(tr) == want).all() and (H(tc) == wc).all(), f"replay {rep}"
+            # eager chained work on the same context between replays
+            (bn.bn_add_n_batch if op == "add" else bn.bn_sub_n_batch)(bnctx, tr, ta, tb, n, npairs, tc)
+            torch.cuda.synchronize()
+            assert (H(tr) == want).all() and (H(tc) == wc).all(), f"eager after replay {rep}"
+    finally:
+        bn.bn_graph_destroy(g)
+
+
+def test_graph_replay_large_product(bnctx):
+    """A captured large product (column workspace, fold, chained carry pass) replayed
+    three times with eager products in between."""
+    na, nb, npairs = 700, 600, 3
+    announce("graph replay, large product", f"na={na}", f"nb={nb}", f"npairs={npairs}")
+    g0 = np.random.default_rng(9)
+    a = g0.integers(0, 2 ** 64 - 1, na * npairs, dtype=np.uint64, endpoint=True)
+    b = g0.integers(0, 2 ** 64 - 1, nb * npairs, dtype=np.uint64, endpoint=True)
+    want = oracle.mul_batch(a, b, na, nb, npairs)
+    ta, tb = D(a), D(b)
+    for form in ("mad", "mfma"):
+        tr = torch.empty((na + nb) * npairs, dtype=torch.int64, device="cuda")
+        s = torch.cuda.Stream()
+        g = bn.bn_graph_capture_batch(bnctx, 2, tr, ta, tb, na, nb, npairs, None, form, stream=s)
+        try:
+            for rep in range(3):
+                tr.fill_(7)
+                torch.cuda.synchronize()
+                bn.bn_graph_launch(g, s)
+                s.synchronize()
+                assert (H(tr) == want).all(), f"{form} replay {rep}"
+                bn.bn_mul_n_batch(bnctx, tr, ta, tb, na, nb, npairs, form)
+                torch.cuda.synchronize()
+                assert (H(tr) == want).all(), f"{form} eager after replay {rep}"
+        finally:
+            bn.bn_graph_destroy(g)
+
+
 def test_self_help_lookback_forced_from_host(bnctx):
     """Tile 0 never publishes (debug flag): its successor polls a few times, then
     computes tile 0's carry from the operands itself.  The kernel exits normally,
