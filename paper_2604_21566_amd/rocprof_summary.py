@@ -90,7 +90,7 @@ def traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
     fb, wb = fm * 1024 * fscale, wm * 1024 * wscale
     alg = C2_PAIRS * C2_LIMBS * 24 + C2_PAIRS * 8
     print("# HBM traffic of the add/sub scan kernel on the batched workload (2^20 pairs x 64 limbs)")
-    print("# commands (run from the repository root on the GPU box):")
+    print("# commands (run from the repository root on an MI355X host):")
     print(f"#   {fetch_cmd}")
     print(f"#   {write_cmd}")
     print("#   python -m paper_2604_21566_amd.rocprof_summary traffic <fetch csv> <write csv> ...")
