@@ -446,7 +446,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 // ------------------------------------------------------------------ params ----
 static const char *kParamNames =
     "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,"
-    "mul.crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,lookback.spin_limit,debug.flags";
+    "mul.crossover_limbs,mul.small_crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,lookback.spin_limit,debug.flags";
 
 const char *bn_param_names(void) { return kParamNames; }
 
@@ -469,6 +469,9 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
     } else if (k == "mul.crossover_limbs") {
         if (v < 1) return BN_EINVAL;
         t.mul_crossover_limbs = v;
+    } else if (k == "mul.small_crossover_limbs") {
+        if (v < 1) return BN_EINVAL;
+        t.mul_small_crossover_limbs = v;
     } else if (k == "mul.mad_xchunk") {
         if (v < 64 || v > (1 << 20) || (v % 8)) return BN_EINVAL;
         t.mad_xchunk = (int)v;
@@ -499,6 +502,7 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "addsub.chain_waves") *v = t.chain_waves;
     else if (k == "addsub.chain_rows") *v = t.chain_rows;
     else if (k == "mul.crossover_limbs") *v = t.mul_crossover_limbs;
+    else if (k == "mul.small_crossover_limbs") *v = t.mul_small_crossover_limbs;
     else if (k == "mul.mad_xchunk") *v = t.mad_xchunk;
     else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;
     else if (k == "mul.mfma_rows") *v = t.mfma_rows;
@@ -530,7 +534,12 @@ bn_status bn_load_tuning(bn_ctx *ctx, const char *path) {
         char *end = nullptr;
         const long long v = strtoll(s.c_str() + c, &end, 10);
         if (end == s.c_str() + c) {
-            // non-integer value (e.g. a string annotation): skip it
+            // non-integer value (e.g. a string annotation): skip it, quoted text whole
+            if (c < s.size() && s[c] == '"') {
+                const size_t q = s.find('"', c + 1);
+                if (q == std::string::npos) return BN_EINVAL;
+                c = q + 1;
+            }
             i = s.find_first_of(",}", c);
             if (i == std::string::npos) break;
             continue;

@@ -291,40 +291,56 @@ __device__ __forceinline__ u32 acc_row(int g, int lane) { return (u32)((g & 3) +
 // ------------------------------------------------- small products, MFMA form ----
 constexpr u64 BN_XOR80 = 0x8080808080808080ull;
 
-// Per-limb digit-sum prefix of one operand (n <= 255 limbs) by one wave:
-// lp[k] = sum of the digits of limbs [0, k), k = 0..n.
-__device__ __forceinline__ void wave_prefix_digits(const u64 *__restrict__ limbs, u32 n, u32 *lp) {
+// Balanced signed digits of one operand (n <= 255 limbs) by one wave: digits d_i in
+// [-128, 127] with sum d_i 256^i = the operand, one extra digit for the carry out of
+// the top.  Adding 128 to every byte with full carries gives bytes b_i + 128 + c_i
+// (mod 256) and carries c_{i+1} = [b_i + c_i >= 128] -- the recurrence of the
+// balanced conversion -- so the two's-complement bytes of the digits are the bytes of
+// (x + 0x8080...80) xor 0x8080...80 over n + 1 limbs (limb n holds the top carry as
+// its digit 0; limbs above it come out zero).  Lane l returns limbs 4l .. 4l+3 of
+// that over 256 limbs: one 256-limb addition of a constant, carries resolved with a
+// ballot scan as in wave_normalise_store.
+__device__ __forceinline__ void wave_balanced_digits(const u64 *__restrict__ limbs, u32 n, u64 (&out)[4]) {
     const int lane = threadIdx.x & 63;
-    u32 s[4];
-    u32 tot = 0;
+    u64 s[4];
+    bool g[4], p[4];
+    bool G = false, PP = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const u32 m = 4 * lane + k;
-        s[k] = m < n ? bytesum64(limbs[m]) : 0u;
-        tot += s[k];
+        const u64 v = m < n ? limbs[m] : 0ull;
+        s[k] = v + BN_XOR80;
+        g[k] = s[k] < v;
+        p[k] = s[k] == ~0ull;
+        G = g[k] || (p[k] && G);
+        PP = PP && p[k];
     }
-    u32 v = tot;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const u32 t = __shfl_up(v, off);
-        if (lane >= off) v += t;
-    }
-    u32 run = v - tot;
+    const u64 Gm = __ballot(G), Pm = __ballot(PP);
+    const u64 C = ((Gm << 1) + Pm) ^ Pm;
+    bool c = (C >> lane) & 1ull;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const u32 m = 4 * lane + k;
-        if (m <= n) lp[m] = run;
-        run += s[k];
+        out[k] = (s[k] + (u64)c) ^ BN_XOR80;
+        c = g[k] || (p[k] && c);
     }
 }
 
 // LDS words (u64) needed per wave by the small MFMA form.
-constexpr int SMALL_MFMA_LDS_U64 = 272 + 256 + 128 + 128;  // bz, aR, lpa (256 u32), lpb (256 u32)
+constexpr int SMALL_MFMA_LDS_U64 = 272 + 256;  // bz, aR
 
 // One product of P = na + nb <= 256 limbs on the MFMA form, one wave.
 // lds: SMALL_MFMA_LDS_U64 words private to the wave.
-__device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b, u32 nb,
-                                    u64 *__restrict__ r, u64 *lds) {
+//
+// The digits are balanced (wave_balanced_digits), so every MFMA column sum is the
+// exact signed column sum C_t of the product, sum_t C_t 256^t = a b, and no
+// correction is needed: limb j's value is V_j = sum_{u<8} C_{8j+u} 2^(8u).  For the
+// carry pass every V_j (j < P) gets K 2^64 added and every V_j (0 < j < P) K
+// subtracted: that adds K X^P in total, which vanishes modulo X^P, and keeps every
+// high word non-negative (|V_j| < 2^84, K = 2^40), so the unsigned in-wave carry pass
+// returns a b mod X^P = a b.  Column sums are exact int32: at most 2049 products of
+// absolute value at most 2^14.
+__device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b,
+                                                    u32 nb, u64 *__restrict__ r, u64 *lds) {
     // the Toeplitz steps run over the digits of b: make b the shorter operand
     if (nb > na) {
         const u64 *t = a;
@@ -340,19 +356,24 @@ __device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u
     int lane;
     asm volatile("v_and_b32 %0, 63, %1" : "=v"(lane) : "v"((int)threadIdx.x));
     const u32 x = lane & 31, h = lane >> 5;
-    const u32 nda = 8 * na, ndb = 8 * nb, P = na + nb;
-    const u32 nca = (na + 3) / 4;  // 32-digit chunks of a
-    u64 *bz = lds;                 // [0,4) zero pad, [4, 4+nb) b' limbs, then zeros
-    u64 *aR = lds + 272;           // reversed signed digits of a, 4*nca limbs
-    u32 *lpa = reinterpret_cast<u32 *>(lds + 528);
-    u32 *lpb = lpa + 256;
-    for (u32 k = lane; k < nb + 16; k += 64) bz[k] = (k >= 4 && k < 4 + nb) ? (b[k - 4] ^ BN_XOR80) : 0ull;
-    for (u32 k = lane; k < 4 * nca; k += 64) {
-        const u32 m = 4 * nca - 1 - k;
-        aR[k] = m < na ? __builtin_bswap64(a[m] ^ BN_XOR80) : 0ull;
+    const u32 P = na + nb;
+    const u32 ndb = 8 * nb + 1;       // digits of b, with the carry digit
+    const u32 nca = (na + 1 + 3) / 4;  // 32-digit chunks of a (with the carry digit)
+    u64 *bz = lds;                     // [0,4) zero pad, [4, 4+nb+1) b digits, then zeros
+    u64 *aR = lds + 272;               // a digits, chunk-reversed, 4*nca limbs
+    {
+        u64 db[4], da[4];
+        wave_balanced_digits(b, nb, db);
+        wave_balanced_digits(a, na, da);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const u32 m = 4 * lane + k;
+            bz[4 + m] = db[k];                                          // m < 256: inside [4, 260)
+            if (m < 4 * nca) aR[4 * nca - 1 - m] = __builtin_bswap64(da[k]);
+        }
+        if (lane < 4) bz[lane] = 0ull;
+        if (lane < 12) bz[260 + lane] = 0ull;
     }
-    wave_prefix_digits(a, na, lpa);
-    wave_prefix_digits(b, nb, lpb);
     wave_sync();
 
     const u32 dmax = (ndb + 30) / 32;
@@ -376,44 +397,31 @@ __device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u
     }
 
     // Limb j = 4 W + m holds digit columns t = 32 W + 8 m + u (u < 8); lane (x, h) has
-    // u = 4h .. 4h+3 of limbs 4 (32 blk + x) + m.  Each lane folds its half, then
-    // partners (lane xor 32) swap halves so that lane l ends up owning limbs 4l .. 4l+3.
-    u64 plo[2][4], phi[2][4];
+    // u = 4h .. 4h+3 of limbs 4 (32 blk + x) + m.  Each lane folds its four columns of
+    // every limb (signed, below 2^51 in magnitude), then partners (lane xor 32) swap
+    // halves so that lane l ends up owning limbs 4l .. 4l+3 (block h).
+    i64 half[2][4];
 #pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
+    for (int blk = 0; blk < 2; ++blk)
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const i64 j = 4 * (32 * blk + (i64)x) + m;
-            u128 v = 0;
-            if (j < (i64)P) {
-                const ColTerm A1 = col_term(a, lpa, na, j), A2 = col_term(a, lpa, na, j - (i64)nb);
-                const ColTerm B1 = col_term(b, lpb, nb, j), B2 = col_term(b, lpb, nb, j - (i64)na);
+            i64 w = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int g = 4 * m + i;
-                    const u32 u = 4 * h + i;
-                    const int raw = blk ? acc1[g] : acc0[g];  // exact: at most 1024 products
-                    const i64 cf = column_exact(raw, true, 8 * (u64)j + u, u, nda, ndb, A1, A2, B1, B2);
-                    v += (u128)(u64)cf << (8 * u);
-                }
-            }
-            plo[blk][m] = (u64)v;
-            phi[blk][m] = (u64)(v >> 64);
+            for (int i = 0; i < 4; ++i) w += (i64)(blk ? acc1[4 * m + i] : acc0[4 * m + i]) * ((i64)1 << (8 * i));
+            half[blk][m] = w;
         }
-    }
+    constexpr i64 K = (i64)1 << 40;
     u64 vlo[4], vhi[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const u64 slo = h ? plo[0][m] : plo[1][m];
-        const u64 shi = h ? phi[0][m] : phi[1][m];
-        const u64 rlo = __shfl_xor(slo, 32);
-        const u64 rhi = __shfl_xor(shi, 32);
-        const u64 klo = h ? plo[1][m] : plo[0][m];
-        const u64 khi = h ? phi[1][m] : phi[0][m];
-        const u128 s = (((u128)khi << 64) | klo) + (((u128)rhi << 64) | rlo);
-        vlo[m] = (u64)s;
-        vhi[m] = (u64)(s >> 64);
+        const i64 own = h ? half[1][m] : half[0][m];
+        const i64 rcv = __shfl_xor(h ? half[0][m] : half[1][m], 32);
+        // digits 0..3 weigh 2^0, digits 4..7 weigh 2^32
+        const i64 lo4 = h ? rcv : own, hi4 = h ? own : rcv;
+        const u32 j = 4 * (u32)lane + m;
+        __int128 v = (__int128)lo4 + ((__int128)hi4 << 32) + ((__int128)K << 64) - (j > 0 ? K : 0);
+        vlo[m] = (u64)v;
+        vhi[m] = (u64)((unsigned __int128)v >> 64);
     }
     wave_normalise_store<4>(vlo, vhi, P, r);
 }
-

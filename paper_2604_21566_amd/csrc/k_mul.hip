@@ -680,7 +680,10 @@ static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
 
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
     if (form != BN_MUL_AUTO) return form;
-    return (i64)std::min(na, nb) >= ctx->tune.mul_crossover_limbs ? BN_MUL_MFMA : BN_MUL_MAD;
+    // products of at most 256 limbs run on the one-wave kernels, larger ones on the
+    // column-workspace kernels: each pair of kernels has its own crossover
+    const i64 x = na + nb <= 256 ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
+    return (i64)std::min(na, nb) >= x ? BN_MUL_MFMA : BN_MUL_MAD;
 }
 
 size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form) {

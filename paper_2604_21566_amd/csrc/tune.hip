@@ -214,10 +214,11 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         }
     }
 
-    // 2) mad vs MFMA crossover: square products, equal total work per size
-    i64 crossover = -1;
-    bool mfma_wins_all_after = true;
-    for (u64 n = 8; n <= 4096; n *= 2) {
+    // 2) mad vs MFMA crossovers: square products, equal total work per size; sizes up
+    // to 128 limbs run on the one-wave kernels, larger ones on the column kernels, and
+    // each range gets the smallest size from which MFMA wins at every larger size
+    i64 crossover = -1, small_crossover = -1;
+    for (u64 n = 4; n <= 4096; n *= 2) {
         u64 npairs = std::max<u64>(1, std::min<u64>((1ull << 26) / (n * n), NBIG / n));
         npairs = std::min<u64>(npairs, 65535);
         const float tm = time_ms([&] { launch_mul_batch(ctx, r, a, b, n, n, npairs, BN_MUL_MAD, nullptr); }, 3);
@@ -226,15 +227,15 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         snprintf(line, sizeof line, "    \"sweep.n%llu\": \"mad %.4f ms, mfma %.4f ms, pairs %llu\",\n",
                  (unsigned long long)n, tm, tf, (unsigned long long)npairs);
         log += line;
+        i64 &x = 2 * n <= 256 ? small_crossover : crossover;
         if (tf < tm) {
-            if (crossover < 0) crossover = (i64)n;
-        } else if (crossover >= 0) {
-            mfma_wins_all_after = false;
-            crossover = -1;
+            if (x < 0) x = (i64)n;
+        } else {
+            x = -1;
         }
     }
-    (void)mfma_wins_all_after;
     t.mul_crossover_limbs = crossover > 0 ? crossover : (i64)1 << 40;
+    t.mul_small_crossover_limbs = small_crossover > 0 ? small_crossover : (i64)1 << 40;
     (void)hipDeviceSynchronize();
     (void)hipFree(a);
     (void)hipFree(b);
@@ -247,6 +248,7 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         fprintf(f, "    \"addsub.batch_waves\": %d,\n    \"addsub.batch_rows\": %d,\n", t.batch_waves, t.batch_rows);
         fprintf(f, "    \"addsub.chain_waves\": %d,\n    \"addsub.chain_rows\": %d,\n", t.chain_waves, t.chain_rows);
         fprintf(f, "    \"mul.crossover_limbs\": %lld,\n", (long long)t.mul_crossover_limbs);
+        fprintf(f, "    \"mul.small_crossover_limbs\": %lld,\n", (long long)t.mul_small_crossover_limbs);
         fprintf(f, "    \"mul.mad_xchunk\": %d,\n    \"mul.mfma_chunk\": %d,\n    \"mul.mfma_rows\": %d\n}\n",
                 t.mad_xchunk, t.mfma_chunk, t.mfma_rows);
         fclose(f);

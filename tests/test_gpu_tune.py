@@ -14,7 +14,7 @@ from paper_2604_21566_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 KEYS = ("addsub.batch_waves", "addsub.batch_rows", "addsub.chain_waves", "addsub.chain_rows",
-        "mul.crossover_limbs", "mul.mad_xchunk", "mul.mfma_chunk")
+        "mul.crossover_limbs", "mul.small_crossover_limbs", "mul.mad_xchunk", "mul.mfma_chunk", "mul.mfma_rows")
 
 
 def test_autotune_roundtrip(tmp_path):
