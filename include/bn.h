@@ -244,8 +244,8 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *                                      waves in {1,2,4,8}, rows of 128 limbs in {1,2,4,8,16},
  *                                      except 8 waves x 16 rows
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
- *                                      (na + nb > 256: the column-workspace kernels)
- *   "mul.small_crossover_limbs"        the same for na + nb <= 256 (one wave per product)
+ *                                      (na + nb > 1024: the column-workspace kernels)
+ *   "mul.small_crossover_limbs"        the same for na + nb <= 1024 (one wave per product)
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
  *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large
  *                                      MFMA kernel: even, 16..256

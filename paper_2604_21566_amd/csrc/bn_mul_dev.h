@@ -291,23 +291,24 @@ __device__ __forceinline__ u32 acc_row(int g, int lane) { return (u32)((g & 3) +
 // ------------------------------------------------- small products, MFMA form ----
 constexpr u64 BN_XOR80 = 0x8080808080808080ull;
 
-// Balanced signed digits of one operand (n <= 255 limbs) by one wave: digits d_i in
-// [-128, 127] with sum d_i 256^i = the operand, one extra digit for the carry out of
-// the top.  Adding 128 to every byte with full carries gives bytes b_i + 128 + c_i
-// (mod 256) and carries c_{i+1} = [b_i + c_i >= 128] -- the recurrence of the
-// balanced conversion -- so the two's-complement bytes of the digits are the bytes of
+// Balanced signed digits of one operand by one wave: digits d_i in [-128, 127] with
+// sum d_i 256^i = the operand, one extra digit for the carry out of the top.  Adding
+// 128 to every byte with full carries gives bytes b_i + 128 + c_i (mod 256) and
+// carries c_{i+1} = [b_i + c_i >= 128] -- the recurrence of the balanced conversion --
+// so the two's-complement bytes of the digits are the bytes of
 // (x + 0x8080...80) xor 0x8080...80 over n + 1 limbs (limb n holds the top carry as
-// its digit 0; limbs above it come out zero).  Lane l returns limbs 4l .. 4l+3 of
-// that over 256 limbs: one 256-limb addition of a constant, carries resolved with a
-// ballot scan as in wave_normalise_store.
-__device__ __forceinline__ void wave_balanced_digits(const u64 *__restrict__ limbs, u32 n, u64 (&out)[4]) {
+// its digit 0; limbs above it come out zero).  Lane l returns limbs LPL l .. LPL l +
+// LPL - 1 of that over 64 LPL limbs (n < 64 LPL): one addition of a constant, carries
+// resolved with a ballot scan as in wave_normalise_store.
+template <int LPL>
+__device__ __forceinline__ void wave_balanced_digits(const u64 *__restrict__ limbs, u32 n, u64 (&out)[LPL]) {
     const int lane = threadIdx.x & 63;
-    u64 s[4];
-    bool g[4], p[4];
+    u64 s[LPL];
+    bool g[LPL], p[LPL];
     bool G = false, PP = true;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const u32 m = 4 * lane + k;
+    for (int k = 0; k < LPL; ++k) {
+        const u32 m = LPL * lane + k;
         const u64 v = m < n ? limbs[m] : 0ull;
         s[k] = v + BN_XOR80;
         g[k] = s[k] < v;
@@ -319,28 +320,75 @@ __device__ __forceinline__ void wave_balanced_digits(const u64 *__restrict__ lim
     const u64 C = ((Gm << 1) + Pm) ^ Pm;
     bool c = (C >> lane) & 1ull;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < LPL; ++k) {
         out[k] = (s[k] + (u64)c) ^ BN_XOR80;
         c = g[k] || (p[k] && c);
     }
 }
 
-// LDS words (u64) needed per wave by the small MFMA form.
-constexpr int SMALL_MFMA_LDS_U64 = 272 + 256;  // bz, aR
+// One row of 256 limbs of the deferred carry pass: lane l owns limbs base + 4l + k
+// with values lo[k] + 2^64 hi[k] (hi >= 0, small); `carry` and `prev_hi` (the high
+// word of the limb below the row) come in from the row below and go out to the row
+// above.  Writes the limbs below P.
+__device__ __forceinline__ void wave_normalise_row(const u64 (&lo)[4], const u64 (&hi)[4], u32 base, u32 P, u64 *r,
+                                                   u64 &carry, u64 &prev_hi) {
+    const int lane = threadIdx.x & 63;
+    u64 prev = __shfl_up(hi[3], 1);
+    if (lane == 0) prev = prev_hi;
+    u64 x[4];
+    bool g[4], p[4];
+    bool G = false, PP = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const u64 h = (k == 0) ? prev : hi[k - 1];
+        x[k] = lo[k] + h;
+        g[k] = x[k] < h;
+        p[k] = x[k] == ~0ull;
+        G = g[k] || (p[k] && G);
+        PP = PP && p[k];
+    }
+    const u64 Gm = __ballot(G), Pm = __ballot(PP);
+    const u64 C = (((Gm << 1) | carry) + Pm) ^ Pm;
+    bool c = (C >> lane) & 1ull;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const u32 j = base + 4 * (u32)lane + k;
+        if (j < P) r[j] = x[k] + (u64)c;
+        c = g[k] || (p[k] && c);
+    }
+    carry = (Gm >> 63) | ((Pm >> 63) & (C >> 63));
+    prev_hi = (u64)(u32)__builtin_amdgcn_readlane((int)(u32)hi[3], 63) |
+              ((u64)(u32)__builtin_amdgcn_readlane((int)(u32)(hi[3] >> 32), 63) << 32);
+}
 
-// One product of P = na + nb <= 256 limbs on the MFMA form, one wave.
-// lds: SMALL_MFMA_LDS_U64 words private to the wave.
+// Shapes of the one-wave MFMA product with NB column blocks of 128 output limbs
+// (products of up to 128 NB limbs).
+template <int NB>
+struct SmallMfma {
+    static constexpr int LPL = 2 * NB;       // limbs per lane in the digit conversion
+    // b digits: 4 zero limbs, nb + 1 <= 64 NB + 1 limbs and the read-ahead; the size
+    // also places the a digits (measured: 152 words for NB = 2 made the a reads 8%
+    // slower than 272)
+    static constexpr int BZ = 128 * NB + 16;
+    static constexpr int AR = 64 * LPL;      // a digits, chunk-reversed (na + 1 <= 128 NB limbs)
+    static constexpr int LDS_U64 = BZ + AR;  // per wave
+};
+
+// One product of P = na + nb <= 128 NB limbs on the MFMA form, one wave.
+// lds: SmallMfma<NB>::LDS_U64 words private to the wave.
 //
 // The digits are balanced (wave_balanced_digits), so every MFMA column sum is the
 // exact signed column sum C_t of the product, sum_t C_t 256^t = a b, and no
 // correction is needed: limb j's value is V_j = sum_{u<8} C_{8j+u} 2^(8u).  For the
 // carry pass every V_j (j < P) gets K 2^64 added and every V_j (0 < j < P) K
 // subtracted: that adds K X^P in total, which vanishes modulo X^P, and keeps every
-// high word non-negative (|V_j| < 2^84, K = 2^40), so the unsigned in-wave carry pass
-// returns a b mod X^P = a b.  Column sums are exact int32: at most 2049 products of
+// high word non-negative (|V_j| < 2^86, K = 2^40), so the unsigned carry pass returns
+// a b mod X^P = a b.  Column sums are exact int32: at most 8 * 512 + 1 products of
 // absolute value at most 2^14.
+template <int NB>
 __device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u32 na, const u64 *__restrict__ b,
                                                     u32 nb, u64 *__restrict__ r, u64 *lds) {
+    using S = SmallMfma<NB>;
     // the Toeplitz steps run over the digits of b: make b the shorter operand
     if (nb > na) {
         const u64 *t = a;
@@ -357,71 +405,72 @@ __device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u
     asm volatile("v_and_b32 %0, 63, %1" : "=v"(lane) : "v"((int)threadIdx.x));
     const u32 x = lane & 31, h = lane >> 5;
     const u32 P = na + nb;
-    const u32 ndb = 8 * nb + 1;       // digits of b, with the carry digit
+    const u32 ndb = 8 * nb + 1;        // digits of b, with the carry digit
     const u32 nca = (na + 1 + 3) / 4;  // 32-digit chunks of a (with the carry digit)
     u64 *bz = lds;                     // [0,4) zero pad, [4, 4+nb+1) b digits, then zeros
-    u64 *aR = lds + 272;               // a digits, chunk-reversed, 4*nca limbs
+    u64 *aR = lds + S::BZ;             // a digits, chunk-reversed, 4*nca limbs
     {
-        u64 db[4], da[4];
-        wave_balanced_digits(b, nb, db);
-        wave_balanced_digits(a, na, da);
+        u64 db[S::LPL], da[S::LPL];
+        wave_balanced_digits<S::LPL>(b, nb, db);
+        wave_balanced_digits<S::LPL>(a, na, da);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const u32 m = 4 * lane + k;
-            bz[4 + m] = db[k];                                          // m < 256: inside [4, 260)
+        for (int k = 0; k < S::LPL; ++k) {
+            const u32 m = S::LPL * lane + k;
+            if (4 + m < (u32)S::BZ) bz[4 + m] = db[k];
             if (m < 4 * nca) aR[4 * nca - 1 - m] = __builtin_bswap64(da[k]);
         }
         if (lane < 4) bz[lane] = 0ull;
-        if (lane < 12) bz[260 + lane] = 0ull;
     }
     wave_sync();
 
     const u32 dmax = (ndb + 30) / 32;
-    const bool two = P > 128;
+    const u32 nblk = (P + 127) / 128;  // column blocks that hold output limbs
     const u32 *bz32 = reinterpret_cast<const u32 *>(bz);
-    v16i acc0 = {0}, acc1 = {0};
+    v16i acc[NB];
+#pragma unroll
+    for (int blk = 0; blk < NB; ++blk) acc[blk] = v16i{0};
     for (u32 d = 0; d <= dmax; ++d) {
         const v4i T = toeplitz_frag(bz32, 32 * d + x + 1 + 16 * h);
-        {
-            const int c = (int)x - (int)d;
-            v4i A = {0, 0, 0, 0};
-            if (c >= 0 && c < (int)nca) A = *reinterpret_cast<const v4i *>(aR + 4 * nca - 4 * (c + 1) + 2 * h);
-            acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(T, A, acc0, 0, 0, 0);
-        }
-        if (two) {
-            const int c = 32 + (int)x - (int)d;
-            v4i A = {0, 0, 0, 0};
-            if (c >= 0 && c < (int)nca) A = *reinterpret_cast<const v4i *>(aR + 4 * nca - 4 * (c + 1) + 2 * h);
-            acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(T, A, acc1, 0, 0, 0);
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) {
+            if (blk == 0 || (u32)blk < nblk) {  // block 0 always holds output limbs
+                const int c = 32 * blk + (int)x - (int)d;
+                v4i A = {0, 0, 0, 0};
+                if (c >= 0 && c < (int)nca) A = *reinterpret_cast<const v4i *>(aR + 4 * nca - 4 * (c + 1) + 2 * h);
+                acc[blk] = __builtin_amdgcn_mfma_i32_32x32x32_i8(T, A, acc[blk], 0, 0, 0);
+            }
         }
     }
 
     // Limb j = 4 W + m holds digit columns t = 32 W + 8 m + u (u < 8); lane (x, h) has
     // u = 4h .. 4h+3 of limbs 4 (32 blk + x) + m.  Each lane folds its four columns of
-    // every limb (signed, below 2^51 in magnitude), then partners (lane xor 32) swap
-    // halves so that lane l ends up owning limbs 4l .. 4l+3 (block h).
-    i64 half[2][4];
+    // every limb (signed, below 2^52 in magnitude), then partners (lane xor 32) swap
+    // halves so that lane l ends up owning limbs 256 s + 4 l + m of blocks 2 s + h;
+    // the carry pass then runs over rows of 256 limbs.
+    constexpr i64 K = (i64)1 << 40;
+    u64 carry = 0, prev_hi = 0;
 #pragma unroll
-    for (int blk = 0; blk < 2; ++blk)
+    for (int sr = 0; sr < NB / 2; ++sr) {
+        u64 vlo[4], vhi[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            i64 w = 0;
+            i64 part[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) w += (i64)(blk ? acc1[4 * m + i] : acc0[4 * m + i]) * ((i64)1 << (8 * i));
-            half[blk][m] = w;
+            for (int e = 0; e < 2; ++e) {
+                i64 w = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w += (i64)acc[2 * sr + e][4 * m + i] * ((i64)1 << (8 * i));
+                part[e] = w;
+            }
+            const i64 own = h ? part[1] : part[0];
+            const i64 rcv = __shfl_xor(h ? part[0] : part[1], 32);
+            // digits 0..3 weigh 2^0, digits 4..7 weigh 2^32
+            const i64 lo4 = h ? rcv : own, hi4 = h ? own : rcv;
+            const u32 j = 256 * sr + 4 * (u32)lane + m;
+            const __int128 v = (__int128)lo4 + ((__int128)hi4 << 32) + ((__int128)K << 64) - (j > 0 ? K : 0);
+            vlo[m] = (u64)v;
+            vhi[m] = (u64)((unsigned __int128)v >> 64);
         }
-    constexpr i64 K = (i64)1 << 40;
-    u64 vlo[4], vhi[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const i64 own = h ? half[1][m] : half[0][m];
-        const i64 rcv = __shfl_xor(h ? half[0][m] : half[1][m], 32);
-        // digits 0..3 weigh 2^0, digits 4..7 weigh 2^32
-        const i64 lo4 = h ? rcv : own, hi4 = h ? own : rcv;
-        const u32 j = 4 * (u32)lane + m;
-        __int128 v = (__int128)lo4 + ((__int128)hi4 << 32) + ((__int128)K << 64) - (j > 0 ? K : 0);
-        vlo[m] = (u64)v;
-        vhi[m] = (u64)((unsigned __int128)v >> 64);
+        wave_normalise_row(vlo, vhi, 256 * sr, P, r, carry, prev_hi);
     }
-    wave_normalise_store<4>(vlo, vhi, P, r);
 }

@@ -1,8 +1,8 @@
 // k_mul.hip -- multiplication kernels and the uniform-batch dispatcher.
 //
-// Small products (na + nb <= 256 limbs, and up to 1024 limbs in the mad form): one
-// wave per pair does everything -- column products, fold, and the in-wave carry
-// pass -- with no workspace.
+// Small products (na + nb <= 512 limbs on the MFMA form, <= 1024 on the mad form): one
+// wave per pair does everything -- column products, fold, and the in-wave carry pass
+// -- with no workspace.
 // Large products: a product kernel accumulates column sums into a workspace with
 // atomics (work items = output-column block x slice of the contraction range, so
 // every item has about the same work), a fold kernel turns column sums into
@@ -15,7 +15,11 @@
 namespace {
 
 constexpr u64 XOR80 = 0x8080808080808080ull;
-constexpr u64 SMALL_MAD_MAX_P = 1024;  // one-wave mad products: up to 16 limbs of output per lane
+constexpr u64 SMALL_MAX_P = 1024;       // one-wave mad products: up to 16 limbs of output per lane
+constexpr u64 SMALL_MFMA_MAX_P = 512;   // one-wave MFMA products: up to four 128-limb column blocks
+
+// Products that run on one wave each (no workspace).
+bool mul_one_wave(u64 P, int form) { return P <= (form == BN_MUL_MFMA ? SMALL_MFMA_MAX_P : SMALL_MAX_P); }
 
 // -------------------------------------------------------------- small kernels ----
 
@@ -23,7 +27,7 @@ constexpr u64 SMALL_MAD_MAX_P = 1024;  // one-wave mad products: up to 16 limbs 
 template <int FORM, int L>
 __global__ __launch_bounds__(256) void k_mul_small(u64 *__restrict__ r, const u64 *__restrict__ a,
                                                    const u64 *__restrict__ b, u32 na, u32 nb, u64 npairs) {
-    __shared__ u64 lds[FORM == BN_MUL_MFMA ? 4 * SMALL_MFMA_LDS_U64 : 1];
+    __shared__ u64 lds[FORM == BN_MUL_MFMA ? 4 * SmallMfma<L>::LDS_U64 : 1];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const u64 p = (u64)blockIdx.x * 4 + w;
     if (p >= npairs) return;
@@ -31,7 +35,7 @@ __global__ __launch_bounds__(256) void k_mul_small(u64 *__restrict__ r, const u6
     const u64 *pb = b + p * nb;
     u64 *pr = r + p * (u64)(na + nb);
     if (FORM == BN_MUL_MFMA)
-        mul_item_mfma_small(pa, na, pb, nb, pr, lds + w * SMALL_MFMA_LDS_U64);
+        mul_item_mfma_small<L>(pa, na, pb, nb, pr, lds + w * SmallMfma<L>::LDS_U64);
     else
         mul_item_mad<L>(pa, na, pb, nb, pr);
 }
@@ -682,14 +686,14 @@ int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
     if (form != BN_MUL_AUTO) return form;
     // products of at most 256 limbs run on the one-wave kernels, larger ones on the
     // column-workspace kernels: each pair of kernels has its own crossover
-    const i64 x = na + nb <= 256 ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
+    const i64 x = na + nb <= SMALL_MAX_P ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
     return (i64)std::min(na, nb) >= x ? BN_MUL_MFMA : BN_MUL_MAD;
 }
 
 size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form) {
     if (na == 0 || nb == 0 || npairs == 0) return 0;
     form = mul_pick_form(ctx, na, nb, form);
-    if (na + nb <= 256 || (form == BN_MUL_MAD && na + nb <= SMALL_MAD_MAX_P)) return 0;
+    if (mul_one_wave(na + nb, form)) return 0;
     return large_layout(na, nb, npairs, form, form == BN_MUL_MFMA ? mfma_plan(ctx, na, nb, npairs).nslices : 1u).total;
 }
 
@@ -699,10 +703,13 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
     const u64 P = na + nb;
     if (na == 0 || nb == 0) return launch_fill_u64(r, P * npairs, 0, s);
     form = mul_pick_form(ctx, na, nb, form);
-    if (P <= 256 || (form == BN_MUL_MAD && P <= SMALL_MAD_MAX_P)) {
+    if (mul_one_wave(P, form)) {
         const u64 blocks = (npairs + 3) / 4;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
-        if (form == BN_MUL_MFMA)
+        if (form == BN_MUL_MFMA && P <= 256)
+            hipLaunchKernelGGL((k_mul_small<BN_MUL_MFMA, 2>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
+                               (u32)nb, npairs);
+        else if (form == BN_MUL_MFMA)
             hipLaunchKernelGGL((k_mul_small<BN_MUL_MFMA, 4>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
                                (u32)nb, npairs);
         else if (P <= 64)

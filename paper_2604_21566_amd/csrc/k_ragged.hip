@@ -15,7 +15,7 @@
 
 namespace {
 
-constexpr int RAGGED_LDS_U64 = SMALL_MFMA_LDS_U64;
+constexpr int RAGGED_LDS_U64 = SmallMfma<2>::LDS_U64;
 
 __global__ __launch_bounds__(256) void k_mul_ragged_mad(const RItem *__restrict__ items, u32 nitems,
                                                         u64 *__restrict__ r, const u64 *__restrict__ a,
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_mul_ragged_mfma(const RItem *__restrict
     const u32 W = gridDim.x * 4;
     for (u32 it = blockIdx.x * 4 + w; it < nitems; it += W) {
         const RItem m = items[it];
-        mul_item_mfma_small(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
+        mul_item_mfma_small<2>(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
         wave_sync();
     }
 }
