@@ -33,10 +33,15 @@ CFLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 
+# Per-file flags.  The large MFMA kernel's step loop (81 instructions) runs 1-2% faster
+# on a 64-byte boundary than where the code before it happens to leave it; aligning
+# loops explicitly keeps that from moving with unrelated edits.
+EXTRA = {"k_mul.hip": ["-falign-loops=64"]}
+
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{p.stdout}\n{p.stderr}")

@@ -395,7 +395,7 @@ bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t
     size_t need = 0, status = 0;
     for (const RItem &it : plan->large) {
         need = std::max(need, mul_workspace_bytes(ctx, it.na, it.nb, 1, (int)it.form));
-        status = std::max(status, flat_scan_status_bytes(ctx, (u64)it.na + it.nb, (u64)it.na + it.nb));
+        status = std::max(status, mul_status_bytes(ctx, it.na, it.nb, 1, (int)it.form));
     }
     bn_status st;
     if ((st = bn_ensure(ctx, ctx->work, need, nullptr)) != BN_OK) return st;
@@ -416,8 +416,7 @@ bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_
         if (mul_in_place(r, a, b, na, nb, npairs) &&
             (st = bn_ensure(ctx, ctx->mstage, (na + nb) * npairs * 8, nullptr)) != BN_OK)
             return st;
-        if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)(na + nb), (u64)(na + nb) * npairs), nullptr)) !=
-            BN_OK)
+        if ((st = bn_ensure(ctx, ctx->status, mul_status_bytes(ctx, na, nb, npairs, form), nullptr)) != BN_OK)
             return st;
         return capture(stream, graph,
                        [&]() { return bn_mul_n_batch(ctx, r, a, b, na, nb, npairs, form, stream); });

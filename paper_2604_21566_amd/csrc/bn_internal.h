@@ -109,11 +109,13 @@ bn_status bn_launch_status();
 // Flat segmented add/sub over N = n * npairs limbs; a segment (pair) starts every n limbs.
 bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                            u64 *carry, hipStream_t s);
-// The same with a per-segment carry-in (cin, device, bit 0; NULL for none) and/or b
-// taken as zero (bzero; b unused): r = a +- b +- cin.
+// The same with a per-segment carry-in (cin, device, bit 0; NULL for none) and/or every
+// limb of b taken as bval (bconst; b unused): r = a +- b +- cin.  bconst without cin is
+// built for addition only.
 bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
-                               const u64 *cin, bool bzero, u64 *carry, hipStream_t s);
+                               const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s);
 size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N);
+size_t flat_scan_ext_status_bytes(u64 n, u64 N);  // the same for launch_flat_scan_ext
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s);
 
 // ---- add/sub extras (k_addsub_ext.hip) ----
@@ -128,6 +130,7 @@ bn_status launch_sub_abs(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n,
 bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 na, u64 nb, u64 npairs,
                            int form, hipStream_t s);
 size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form);
+size_t mul_status_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form);  // chained-scan status words
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form);
 
 // ---- Karatsuba levels (k_karatsuba.hip) ----

@@ -8,13 +8,15 @@
 //   * mad form  : 32-bit digits, v_mad_u64_u32 with a carry-out into a 96-bit
 //                 column accumulator (the paper's IFMA lo/hi products become one
 //                 32x32->64 multiply-add per digit pair);
-//   * MFMA form : 8-bit digits (the byte view of the limb array, as the paper
-//                 splits 64-bit limbs to fit its multiplier), the digit
-//                 convolution written as a block-Toeplitz matrix product on
+//   * MFMA form : 8-bit digits (the paper splits 64-bit limbs to fit its
+//                 multiplier; here the digits are balanced signed bytes of the
+//                 operand, one more than its byte count), the digit convolution
+//                 written as a block-Toeplitz matrix product on
 //                 v_mfma_i32_32x32x32_i8 with int32 accumulation.
 // The deferred carry pass (Algorithm 2, phase 5) is: fold each limb's column sums
 // into V_j = lo_j + 2^64 hi_j, then r = sum_j lo_j X^j + sum_j hi_j X^(j+1), i.e.
-// one big-integer addition whose carries are single bits (g/p scan).
+// one big-integer addition whose carries are single bits (g/p scan).  Signed limb
+// values are stored biased, V_j + K 2^64 - [j > 0] K, offsets that sum to K X^P.
 #pragma once
 
 #include "bn_internal.h"
@@ -43,10 +45,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ u32 bytesum64(u64 v) {
-    return __builtin_amdgcn_sad_u8((u32)v, 0u, __builtin_amdgcn_sad_u8((u32)(v >> 32), 0u, 0u));
 }
 
 // Deferred carry pass inside one wave.  Lane l owns limbs j = l*L + k (k < L) with
@@ -201,87 +199,6 @@ __device__ __forceinline__ v4i toeplitz_combine(const TWords &t, u32 s) {
     f.z = (int)__builtin_amdgcn_alignbyte(t.w3, t.w2, s);
     f.w = (int)__builtin_amdgcn_alignbyte(t.w4, t.w3, s);
     return f;
-}
-
-// Exact unsigned column sums from the MFMA sums of signed digits, eight columns at a
-// time: the columns t = 8 j + u (u < 8) of limb j.  With nda, ndb the digit counts,
-// ilo = max(0, t + 1 - ndb) and ihi = min(t, nda - 1), the digits meeting in column t
-// are a[ilo..ihi] and b[t-ihi..t-ilo], cnt = ihi - ilo + 1 of each (0 past the
-// product), and
-//     C = M + 128 (S_a + S_b) - 16384 cnt,
-//     S_a = PA(min(t + 1, nda)) - PA(max(0, t + 1 - ndb)),
-//     S_b = PB(min(t + 1, ndb)) - PB(max(0, t + 1 - nda)),
-// with PA, PB the digit prefix sums.  Every argument is t + 1 + (0, -ndb, 0, -nda),
-// i.e. 8 q + u + 1 for q = j, j - nb, j, j - na: one prefix-table entry and one limb
-// per term give all eight columns, PX(8 q + u + 1) = lp[q] + (digits 0..u of limb q),
-// with limbs outside the operand read as zero and lp clamped to [0, n] (which is
-// exactly the clamping of the arguments above).
-struct ColTerm {
-    u64 pre;   // lp[q] (clamped)
-    u64 limb;  // limb q (0 outside the operand)
-};
-template <class LP>
-__device__ __forceinline__ ColTerm col_term(const u64 *__restrict__ x, const LP *lp, u64 n, i64 q) {
-    ColTerm c;
-    c.pre = (u64)lp[q < 0 ? 0 : (q > (i64)n ? (i64)n : q)];
-    c.limb = (q >= 0 && q < (i64)n) ? x[q] : 0ull;
-    return c;
-}
-// digits 0..u of a limb
-__device__ __forceinline__ u64 low_digits(u64 limb, u32 u) {
-    return bytesum64(u >= 7 ? limb : (limb & ((1ull << (8 * (u + 1))) - 1)));
-}
-// Column sum of column t = 8 j + u from its raw MFMA sum.  When the accumulation was
-// plain int32 (wide == false) the register holds the true sum M modulo 2^32; M lies in
-// [-16256 cnt, 16384 cnt], an interval narrower than 2^32 for cnt <= 131586, so M is
-// recovered exactly.
-__device__ __forceinline__ i64 column_exact(i64 raw, bool wide, u64 t, u32 u, u64 nda, u64 ndb, const ColTerm &A1,
-                                            const ColTerm &A2, const ColTerm &B1, const ColTerm &B2) {
-    const i64 ilo = t + 1 > ndb ? (i64)(t + 1 - ndb) : 0;
-    const i64 ihi = t < nda - 1 ? (i64)t : (i64)nda - 1;
-    const i64 cnt = ihi >= ilo ? ihi - ilo + 1 : 0;
-    i64 m = raw;
-    if (!wide) {
-        m = (i64)(int)(u32)raw;
-        if (m < -16256 * cnt) m += (i64)1 << 32;
-    }
-    const i64 sa = (i64)((A1.pre + low_digits(A1.limb, u)) - (A2.pre + low_digits(A2.limb, u)));
-    const i64 sb = (i64)((B1.pre + low_digits(B1.limb, u)) - (B2.pre + low_digits(B2.limb, u)));
-    return m + 128 * (sa + sb) - 16384 * cnt;
-}
-
-// The same decode for the four digits u = 4 h + i (i < 4) of a limb that one lane of
-// the large MFMA kernel holds.  Per term, the in-limb digit sums 0..u come from one
-// running sum over the lane's four bytes (plus the sum of the low four bytes when
-// h = 1) instead of a masked byte sum per column.
-__device__ __forceinline__ void limb_partials4(u64 limb, u32 h, u32 (&p)[4]) {
-    const u32 lo = (u32)limb, hi = (u32)(limb >> 32);
-    const u32 w = h ? hi : lo;
-    u32 run = h ? __builtin_amdgcn_sad_u8(lo, 0u, 0u) : 0u;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        run += (w >> (8 * i)) & 0xffu;
-        p[i] = run;
-    }
-}
-// S(u) = PX(8 q1 + u + 1) - PX(8 q2 + u + 1) for the lane's four digits u
-__device__ __forceinline__ void window4(const ColTerm &T1, const ColTerm &T2, u32 h, i64 (&s)[4]) {
-    u32 p1[4], p2[4];
-    limb_partials4(T1.limb, h, p1);
-    limb_partials4(T2.limb, h, p2);
-    const i64 d = (i64)(T1.pre - T2.pre);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) s[i] = d + (i64)p1[i] - (i64)p2[i];
-}
-// Column sum from its raw int32 register (true sum modulo 2^32, see column_exact) and
-// its window sums.
-__device__ __forceinline__ i64 column_exact_w(int raw, u64 t, u64 nda, u64 ndb, i64 sa, i64 sb) {
-    const i64 ilo = t + 1 > ndb ? (i64)(t + 1 - ndb) : 0;
-    const i64 ihi = t < nda - 1 ? (i64)t : (i64)nda - 1;
-    const i64 cnt = ihi >= ilo ? ihi - ilo + 1 : 0;
-    i64 m = (i64)raw;
-    if (m < -16256 * cnt) m += (i64)1 << 32;
-    return m + 128 * (sa + sb) - 16384 * cnt;
 }
 
 // Accumulator element (reg g of lane l) -> (row rr, column x) of the 32x32 tile.

@@ -93,11 +93,13 @@ struct ScanGeom {
     u64 epoch;     // chained launches: this launch's epoch, or 0 to read it from the control block
     const u64 *cin;  // EXT_CIN: per-segment carry (borrow) into the segment's first limb (bit 0)
     u64 nseg;        // segments (pairs)
+    u64 bval;        // EXT_BCONST: the value of every limb of b
 };
 
-// Kernel variants beyond the plain a +- b: a per-segment carry-in, and b = 0 (the
-// carry-in alone propagates through a).
-constexpr int EXT_CIN = 1, EXT_BZERO = 2;
+// Kernel variants beyond the plain a +- b: a per-segment carry-in, and b given as one
+// limb value repeated (b = 0: the carry-in alone propagates through a; b = 0x80...80:
+// the balanced-digit conversion of a product's operands).
+constexpr int EXT_CIN = 1, EXT_BCONST = 2;
 
 template <int EXT>
 __device__ __forceinline__ bool seg_cin(const ScanGeom &G, u64 q) {
@@ -121,9 +123,9 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
         divmod_u64(i0, G.n, G.nshift, q, pos);
         bool g0 = false, p0 = false, g1 = false, p1 = false;
         u64 s;
-        const bool bz = (EXT & EXT_BZERO) != 0;
-        if (i0 < hi) limb_gp<SUB>(a[i0], bz ? 0ull : b[i0], s, g0, p0);
-        if (i0 + 1 < hi) limb_gp<SUB>(a[i0 + 1], bz ? 0ull : b[i0 + 1], s, g1, p1);
+        const bool bc = (EXT & EXT_BCONST) != 0;
+        if (i0 < hi) limb_gp<SUB>(a[i0], bc ? G.bval : b[i0], s, g0, p0);
+        if (i0 + 1 < hi) limb_gp<SUB>(a[i0 + 1], bc ? G.bval : b[i0 + 1], s, g1, p1);
         // a segment's first limb takes the segment's carry-in, not its neighbour's carry
         g0 = g0 || (pos == 0 && p0 && seg_cin<EXT>(G, q));
         g1 = g1 || (pos + 1 == G.n && i0 + 1 < hi && p1 && seg_cin<EXT>(G, q + 1));
@@ -223,15 +225,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     // stores keep them from displacing other lines in the caches (measured +10%).
     const bool full = VEC && (t + 1) * TL <= N;
     u64 x0[ROWS], x1[ROWS], y0[ROWS], y1[ROWS];
-    constexpr bool BZ = (EXT & EXT_BZERO) != 0;
+    constexpr bool BC = (EXT & EXT_BCONST) != 0;
     if (full) {
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const u64v2 va = __builtin_nontemporal_load(reinterpret_cast<const u64v2 *>(a + idx0 + (u64)j * 128));
             x0[j] = va.x;
             x1[j] = va.y;
-            if (BZ) {
-                y0[j] = y1[j] = 0;
+            if (BC) {
+                y0[j] = y1[j] = G.bval;
             } else {
                 const u64v2 vb = __builtin_nontemporal_load(reinterpret_cast<const u64v2 *>(b + idx0 + (u64)j * 128));
                 y0[j] = vb.x;
@@ -243,9 +245,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
         for (int j = 0; j < ROWS; ++j) {
             const u64 idx = idx0 + (u64)j * 128;
             x0[j] = idx < N ? a[idx] : 0;
-            y0[j] = (!BZ && idx < N) ? b[idx] : 0;
+            y0[j] = idx < N ? (BC ? G.bval : b[idx]) : 0;
             x1[j] = idx + 1 < N ? a[idx + 1] : 0;
-            y1[j] = (!BZ && idx + 1 < N) ? b[idx + 1] : 0;
+            y1[j] = idx + 1 < N ? (BC ? G.bval : b[idx + 1]) : 0;
         }
     }
 
@@ -518,6 +520,12 @@ size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N) {
     return (size_t)tiles * sizeof(u64);
 }
 
+size_t flat_scan_ext_status_bytes(u64 n, u64 N) {
+    if (n == 0 || 128 % n == 0) return 0;  // independent tiles: no status words
+    const u64 TL = 4 * 128;  // the smallest chained tile
+    return (size_t)((N + TL - 1) / TL) * sizeof(u64);
+}
+
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s) {
     if (count == 0) return BN_OK;
     u64 blocks = (count + 255) / 256;
@@ -526,21 +534,28 @@ bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s) {
     return bn_launch_status();
 }
 
-// The extended variants (carry-in, b = 0) come in fixed shapes: 1 x 1 independent
-// tiles, 4 x 8 (4 x 4 unaligned) chained tiles.
+// The extended variants (carry-in, constant b) come in fixed shapes: 1 x 1 independent
+// tiles, 4 x 8 (4 x 4 unaligned) chained tiles; aligned chained launches of the
+// constant-b variant alone (the operand conversion of products) also take 4 x 4, 4 x 2
+// and 4 x 1 tiles, so that a small launch still spreads over the device.
 template <bool SUB, int EXT>
-static scan_fn pick_ext(bool vec, bool chain) {
+static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
+    if (vec && chain && EXT == EXT_BCONST) {
+        if (rows == 1) return k_flat_scan<SUB, 4, 1, true, true, EXT>;
+        if (rows == 2) return k_flat_scan<SUB, 4, 2, true, true, EXT>;
+        if (rows == 4) return k_flat_scan<SUB, 4, 4, true, true, EXT>;
+    }
     if (vec) return chain ? k_flat_scan<SUB, 4, 8, true, true, EXT> : k_flat_scan<SUB, 1, 1, true, false, EXT>;
     return chain ? k_flat_scan<SUB, UNALIGNED_CHAIN_WAVES, UNALIGNED_CHAIN_ROWS, false, true, EXT>
                  : k_flat_scan<SUB, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false, EXT>;
 }
 
 bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
-                               const u64 *cin, bool bzero, u64 *carry, hipStream_t s) {
+                               const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s) {
     const u64 N = n * npairs;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
-    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bzero ? nullptr : b)) & 15u) == 0;
-    const int ext = (cin ? EXT_CIN : 0) | (bzero ? EXT_BZERO : 0);
+    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst ? nullptr : b)) & 15u) == 0;
+    const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0);
     int waves, rows;
     bool chain;
     if (ext == 0) {
@@ -549,6 +564,10 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         chain = (128 % n) != 0;
         waves = chain ? (vec ? 4 : UNALIGNED_CHAIN_WAVES) : 1;
         rows = chain ? (vec ? 8 : UNALIGNED_CHAIN_ROWS) : 1;
+        if (ext == EXT_BCONST && chain && vec) {  // at least 8 tiles per CU where rows allow
+            const u64 want = 8 * (u64)std::max(1, ctx->num_cu);
+            while (rows > 1 && (N + (u64)waves * rows * 128 - 1) / ((u64)waves * rows * 128) < want) rows /= 2;
+        }
     }
     const u64 TL = (u64)waves * rows * 128;
     const u64 ntiles = (N + TL - 1) / TL;
@@ -560,8 +579,10 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     scan_fn f = nullptr;
     if (ext == EXT_CIN)
         f = sub ? pick_ext<true, EXT_CIN>(vec, chain) : pick_ext<false, EXT_CIN>(vec, chain);
-    else if (ext == (EXT_CIN | EXT_BZERO))
-        f = sub ? pick_ext<true, EXT_CIN | EXT_BZERO>(vec, chain) : pick_ext<false, EXT_CIN | EXT_BZERO>(vec, chain);
+    else if (ext == (EXT_CIN | EXT_BCONST))
+        f = sub ? pick_ext<true, EXT_CIN | EXT_BCONST>(vec, chain) : pick_ext<false, EXT_CIN | EXT_BCONST>(vec, chain);
+    else if (ext == EXT_BCONST && !sub)
+        f = pick_ext<false, EXT_BCONST>(vec, chain, rows);
     else if (ext != 0)
         return BN_EINVAL;
     else if (vec)
@@ -580,7 +601,7 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (chain && hipStreamIsCapturing(s, &cs) != hipSuccess) return BN_EHIP;
     const bool captured = cs != hipStreamCaptureStatusNone;
-    ScanGeom G{N, n, -1, TL, (chain && !captured) ? ++ctx->host_epoch : 0, cin, npairs};
+    ScanGeom G{N, n, -1, TL, (chain && !captured) ? ++ctx->host_epoch : 0, cin, npairs, bval};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
                        ctx->ctl, (u64 *)ctx->status.ptr, ctx->tune.spin_limit, ctx->tune.debug_flags);
@@ -592,5 +613,5 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
 
 bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *carry,
                            hipStream_t s) {
-    return launch_flat_scan_ext(ctx, sub, r, a, b, n, npairs, nullptr, false, carry, s);
+    return launch_flat_scan_ext(ctx, sub, r, a, b, n, npairs, nullptr, false, 0, carry, s);
 }

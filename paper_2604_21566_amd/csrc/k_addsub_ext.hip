@@ -19,7 +19,7 @@ __global__ void k_select_pairs(u64 *__restrict__ r, const u64 *__restrict__ alt,
 
 bn_status launch_addsub_nc(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                            const u64 *cin, u64 *carry, hipStream_t s) {
-    return launch_flat_scan_ext(ctx, sub, r, a, b, n, npairs, cin, false, carry, s);
+    return launch_flat_scan_ext(ctx, sub, r, a, b, n, npairs, cin, false, 0, carry, s);
 }
 
 // r[0, na) = a +- b with b zero-extended to na limbs (na >= nb): the low nb limbs
@@ -31,7 +31,7 @@ bn_status launch_addsub_unequal(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64
     bn_status st;
     if (na == nb) return launch_flat_scan(ctx, sub, r, a, b, na, 1, carry, s);
     if (nb > 0 && (st = launch_flat_scan(ctx, sub, r, a, b, nb, 1, tmp, s)) != BN_OK) return st;
-    return launch_flat_scan_ext(ctx, sub, r + nb, a + nb, nullptr, na - nb, 1, nb > 0 ? tmp : zero, true, carry, s);
+    return launch_flat_scan_ext(ctx, sub, r + nb, a + nb, nullptr, na - nb, 1, nb > 0 ? tmp : zero, true, 0, carry, s);
 }
 
 // r = |a - b| per pair, sign[p] = [a_p < b_p].  b - a goes to a scratch array first,

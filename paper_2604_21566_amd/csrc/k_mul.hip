@@ -15,6 +15,7 @@
 namespace {
 
 constexpr u64 XOR80 = 0x8080808080808080ull;
+constexpr u64 MUL_BIAS = 1ull << 62;  // K of the biased signed limb values
 constexpr u64 SMALL_MAX_P = 1024;       // one-wave mad products: up to 16 limbs of output per lane
 constexpr u64 SMALL_MFMA_MAX_P = 512;   // one-wave MFMA products: up to four 128-limb column blocks
 
@@ -124,126 +125,12 @@ __global__ void k_fold_mad(const u64 *__restrict__ colLo, const u64 *__restrict_
 }
 
 // ---------------------------------------------------------- large: MFMA form ----
-// Per-limb digit-sum prefix tables lp[k] = sum of the digits of limbs [0, k) of every
-// operand of the batch (for the unsigned-sum corrections of the fold), 64-bit so that
-// any operand length is exact.  Two small kernels over segments of PREP_SEG limbs:
-// segment totals, then each segment adds the totals before it and scans its own
-// limbs in the workgroup.
-constexpr u32 PREP_SEG = 1024;  // limbs per segment: 256 threads x 4 limbs
-
-// Entries per operand in a prefix table: n + 1, rounded up to even so that every
-// operand's table starts 16-byte aligned.
-__host__ __device__ __forceinline__ u64 lp_stride(u64 n) { return (n + 2) & ~1ull; }
-
-__device__ __forceinline__ const u64 *prep_operand(const u64 *a, const u64 *b, u64 na, u64 nb, u64 op_pair, u64 &n,
-                                                   u64 *lpa, u64 *lpb, u64 *&lp) {
-    const u64 pair = op_pair >> 1;
-    if (op_pair & 1) {
-        n = nb;
-        lp = lpb + pair * lp_stride(nb);
-        return b + pair * nb;
-    }
-    n = na;
-    lp = lpa + pair * lp_stride(na);
-    return a + pair * na;
-}
-
-// Limbs base .. base+3 of x (zero past n): two 16-byte loads when they are all in
-// range and aligned (a wave then reads one contiguous 2 KiB run), else one by one.
-__device__ __forceinline__ void load4(const u64 *__restrict__ x, u64 base, u64 n, u64 (&v)[4]) {
-    typedef u64 u64x2 __attribute__((ext_vector_type(2)));
-    if (base + 4 <= n && (((uintptr_t)(x + base)) & 15u) == 0) {
-        const u64x2 lo = *reinterpret_cast<const u64x2 *>(x + base);
-        const u64x2 hi = *reinterpret_cast<const u64x2 *>(x + base + 2);
-        v[0] = lo.x;
-        v[1] = lo.y;
-        v[2] = hi.x;
-        v[3] = hi.y;
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = base + k < n ? x[base + k] : 0ull;
-    }
-}
-
-// lp[base .. base+3] = v (entries at or past n are not written), 16-byte stores when
-// aligned.
-__device__ __forceinline__ void store4(u64 *__restrict__ lp, u64 base, u64 n, const u64 (&v)[4]) {
-    typedef u64 u64x2 __attribute__((ext_vector_type(2)));
-    if (base + 4 <= n && (((uintptr_t)(lp + base)) & 15u) == 0) {
-        *reinterpret_cast<u64x2 *>(lp + base) = u64x2{v[0], v[1]};
-        *reinterpret_cast<u64x2 *>(lp + base + 2) = u64x2{v[2], v[3]};
-    } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (base + k < n) lp[base + k] = v[k];
-    }
-}
-
-__global__ __launch_bounds__(256) void k_prep_totals(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                     u64 nb, u64 *__restrict__ lpa, u64 *__restrict__ lpb,
-                                                     u32 *__restrict__ seg_tot, u32 nseg) {
-    __shared__ u32 sh[4];
-    u64 n;
-    u64 *lp;
-    const u64 op_pair = blockIdx.x / nseg, sg = blockIdx.x % nseg;
-    const u64 *x = prep_operand(a, b, na, nb, op_pair, n, lpa, lpb, lp);
-    const u64 base = sg * PREP_SEG + 4 * (u64)threadIdx.x;
-    u64 v[4];
-    load4(x, base, n, v);
-    u32 sum = 0;  // at most 1024 limbs x 2040
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sum += bytesum64(v[k]);
-    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) seg_tot[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
-}
-
-__global__ __launch_bounds__(256) void k_prep_scan(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na,
-                                                   u64 nb, u64 *__restrict__ lpa, u64 *__restrict__ lpb,
-                                                   const u32 *__restrict__ seg_tot, u32 nseg) {
-    __shared__ u64 sh[4], shp[4];
-    u64 n;
-    u64 *lp;
-    const u64 op_pair = blockIdx.x / nseg, sg = blockIdx.x % nseg;
-    const u64 *x = prep_operand(a, b, na, nb, op_pair, n, lpa, lpb, lp);
-    const u64 seg0 = sg * PREP_SEG;
-    if (seg0 >= n && !(n == 0 && sg == 0)) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // digits of all earlier segments (strided over the workgroup, then reduced)
-    u64 pre = 0;
-    for (u64 s2 = threadIdx.x; s2 < sg; s2 += 256) pre += seg_tot[op_pair * nseg + s2];
-    for (int off = 32; off > 0; off >>= 1) pre += __shfl_xor(pre, off);
-    if (lane == 0) shp[w] = pre;
-    const u64 base = seg0 + 4 * (u64)threadIdx.x;
-    u64 limbs[4];
-    load4(x, base, n, limbs);
-    u32 v[4], sum = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        v[k] = bytesum64(limbs[k]);
-        sum += v[k];
-    }
-    // exclusive scan of the per-thread sums over the workgroup
-    u32 inc = sum;
-    for (int off = 1; off < 64; off <<= 1) {
-        const u32 t = __shfl_up(inc, off);
-        if (lane >= off) inc += t;
-    }
-    if (lane == 63) sh[w] = inc;
-    __syncthreads();
-    u64 run = shp[0] + shp[1] + shp[2] + shp[3] + inc - sum;
-    for (int i = 0; i < w; ++i) run += sh[i];
-    u64 out[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        out[k] = run;
-        run += v[k];
-        if (base + k + 1 == n) lp[n] = run;
-    }
-    store4(lp, base, n, out);
-    if (n == 0 && threadIdx.x == 0) lp[0] = 0;
-}
+// Operands enter as balanced signed digits: the flat scan adds 0x80...80 to every
+// operand of the batch (one pass over a, one over b, each limb read and written once),
+// and digit i is byte i of the sum xor 0x80, read as int8 in [-128, 127]; the scan's
+// carry out of a pair is that operand's extra top digit (index 8 n, value 0 or 1).  The
+// digits sum to the operand exactly (the same conversion as the one-wave kernel), so
+// every MFMA column sum is the true signed column sum and needs no correction.
 
 // k-th group in decreasing-work order when work over groups [0, n) is symmetric and
 // unimodal about the centre (true for the columns of a product): centre first, then
@@ -281,7 +168,8 @@ constexpr int AZ_SLOT_U64 = 10;  // one 64-digit chunk per 80-byte LDS slot: ds_
 // are used while a column holds at most 131586 digit products: its register holds
 // the true signed sum M modulo 2^32 and M lies in [-16256 cnt, 16384 cnt], narrower
 // than 2^32, so the epilogue decodes it exactly, folds the 64 R columns of each W
-// into 8 R limb values and writes lo and shifted hi.  Split launches keep every slice
+// into 8 R signed limb values and writes them biased (see the epilogue) as lo and
+// shifted hi.  Split launches keep every slice
 // at most 2046 steps when columns are longer (2046 * 64 * 2^14 < 2^31, exact) and
 // write the slice sums to per-slice int32 arrays that a fold kernel adds.
 // Workgroups are ordered by decreasing work.
@@ -322,9 +210,8 @@ __device__ __forceinline__ void mfma_step(v16i (&acc)[NW][2 * R], const v4i (&F)
 // Two workgroups fit a CU's LDS, so two waves per SIMD: registers are not the limit.
 template <int NW, int R, bool SPLIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mul_large_mfma(
-    const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na, u64 nb, u64 npairs, const u64 *__restrict__ lpa,
-    const u64 *__restrict__ lpb, u32 D, u32 ngroups, u32 nslices, u64 *__restrict__ LO, u64 *__restrict__ HS,
-    int *__restrict__ part) {
+    const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na, u64 nb, u64 npairs, const u64 *__restrict__ tops,
+    u32 D, u32 ngroups, u32 nslices, u64 *__restrict__ LO, u64 *__restrict__ HS, int *__restrict__ part) {
     extern __shared__ u64 lds[];
     u64 *bz = lds;                         // 8 (D + 2 + R) words of signed b digits
     u64 *az = lds + 8 * ((u64)D + 2 + R);  // (128 NW R + D) chunk slots of reversed signed a digits
@@ -337,14 +224,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const u64 pair = bq % npairs;
     const u32 g = middle_out((u32)(bq / npairs), ngroups);
     const i64 P = (i64)(na + nb);
-    const i64 nca = (i64)((na + 7) / 8);
+    // a and b (the converted operands) have 8 n + 1 digits each, the last one the top
+    // carry, stored in tops[pair] (a) and tops[npairs + pair] (b)
+    const i64 nca = (8 * (i64)na + 64) / 64;  // 64-digit chunks of a
     // steps d in [dmin, dmax] reach b digits: rows r < 64 R of step d read digits from
     // 64 (d - 1) + 1 up to 64 d + 64 R - 1
-    const i64 dmin = 1 - R, dmax = (8 * (i64)nb + 62) / 64;
+    const i64 dmin = 1 - R, dmax = (8 * (i64)nb + 63) / 64;
     const i64 nWb = (P + 256 * R - 1) / (256 * R);
     const i64 wb0 = (i64)g * 4 * NW;
     const i64 W0g = 32 * wb0, Wend = W0g + 128 * NW - 1;
     const u64 *pa = a + pair * na, *pb = b + pair * nb;
+    const u64 top_a = tops[pair], top_b = tops[npairs + pair];
 
     // a chunk c = R W - d meets column group W at step d
     i64 wlo = INT64_MAX, whi = INT64_MIN;
@@ -395,7 +285,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         __syncthreads();
         // Staging, SG elements per thread at a time: unconditional loads from clamped
         // indices first (no branch between a load and its use, so one wait per group),
-        // then out-of-range elements replaced by zero and the signed offset applied.
+        // then the bytes turned into signed digits (xor 0x80), the limb past the operand
+        // replaced by the top digit and the others out of range by zero.
         constexpr int SG = 8;
         for (u32 k0 = threadIdx.x; k0 < nbz; k0 += 256 * SG) {
             u64 v[SG];
@@ -408,7 +299,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             for (int j = 0; j < SG; ++j) {
                 const u32 k = k0 + 256 * j;
                 const i64 m = 8 * (d0 - 1) + (i64)k;
-                if (k < nbz) bz[k] = (m >= 0 && m < (i64)nb) ? (v[j] ^ XOR80) : 0ull;
+                if (k < nbz) bz[k] = (m >= 0 && m < (i64)nb) ? (v[j] ^ XOR80) : (m == (i64)nb ? top_b : 0ull);
             }
         }
         for (u32 k0 = threadIdx.x; k0 < 8 * nslots; k0 += 256 * SG) {
@@ -425,7 +316,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                 const i64 m = 8 * (cbase + (i64)(k >> 3)) + 7 - (i64)(k & 7);
                 if (k < 8 * nslots)
                     az[AZ_SLOT_U64 * (k >> 3) + (k & 7)] =
-                        (m >= 0 && m < (i64)na) ? __builtin_bswap64(v[j] ^ XOR80) : 0ull;
+                        (m >= 0 && m < (i64)na) ? __builtin_bswap64(v[j] ^ XOR80)
+                                                : (m == (i64)na ? __builtin_bswap64(top_a) : 0ull);
             }
         }
         __syncthreads();
@@ -527,13 +419,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
         return;
     }
-    // ---- epilogue: exact column sums -> limb values -> lo / shifted hi ----
+    // ---- epilogue: exact column sums -> signed limb values -> lo / shifted hi ----
     // Lane (x, h) holds, for each of its blocks, columns t = 64 R W + 32 mi + 8 m + 4 h + ii
     // (W = 32 wb + x): limb jl = 4 mi + m of W's 8 R, digits u = 4 h + ii.  M-blocks
     // pair up (mi = 2 s, 2 s + 1): lane h keeps limb 8 s + 4 h + m and takes the other
-    // half of its digits from the partner lane (lane xor 32).
-    const u64 *la = lpa + pair * lp_stride(na), *lb = lpb + pair * lp_stride(nb);
-    const u64 nda = 8 * na, ndb = 8 * nb;
+    // half of its digits from the partner lane (lane xor 32).  A column sum lies in
+    // [-16256 cnt, 16384 cnt] with cnt <= cmax digit pairs; the register holds it
+    // modulo 2^32, and only the upper end can pass 2^31 (cmax <= 131586), so one
+    // comparison with -16256 cmax recovers it.  The limb value V_j = sum_u C_(8j+u) 256^u
+    // is signed, |V_j| < 2^90; it is stored as V_j + K 2^64 - [j > 0] K (K = 2^62, so
+    // lo and hi are unsigned): the offsets telescope to K X^P, zero modulo X^P, so the
+    // carry pass still gives the product.
+    const i64 lowest = -16256 * (8 * (i64)std::min(na, nb) + 1);
     u64 *lo_out = LO + pair * (u64)P, *hs_out = HS + pair * (u64)P;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
@@ -542,41 +439,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const u64 W = (u64)(32 * wb) + x;
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-            u64 plo[2][4], phi[2][4];
+            // the lane's four columns of limb (e, m): |sum| < 2^32 2^24 (4/3) < 2^57
+            i64 w[2][4];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const int mi = 2 * s + e;
+            for (int e = 0; e < 2; ++e)
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const i64 j = (i64)(8 * R * W) + 4 * mi + m;
-                    const ColTerm A1 = col_term(pa, la, na, j), A2 = col_term(pa, la, na, j - (i64)nb);
-                    const ColTerm B1 = col_term(pb, lb, nb, j), B2 = col_term(pb, lb, nb, j - (i64)na);
-                    i64 sa[4], sb[4];
-                    window4(A1, A2, h, sa);
-                    window4(B1, B2, h, sb);
-                    // the lane's four columns: each sum is below 2^34 (at most 131586
-                    // products of at most 255^2), so their value shifted by 8 ii fits 64 bits
-                    u64 wsum = 0;
+                    i64 ws = 0;
 #pragma unroll
                     for (int ii = 0; ii < 4; ++ii) {
-                        const u64 t = 8 * (u64)j + 4 * h + ii;
-                        const i64 cf = column_exact_w(acc[i][mi][4 * m + ii], t, nda, ndb, sa[ii], sb[ii]);
-                        wsum += (u64)cf << (8 * ii);
+                        i64 c = (i64)acc[i][2 * s + e][4 * m + ii];
+                        if (c < lowest) c += (i64)1 << 32;
+                        ws += c * ((i64)1 << (8 * ii));
                     }
-                    plo[e][m] = h ? wsum << 32 : wsum;
-                    phi[e][m] = h ? wsum >> 32 : 0;
+                    w[e][m] = ws;
                 }
-            }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const u64 slo = h ? plo[0][m] : plo[1][m];
-                const u64 shi = h ? phi[0][m] : phi[1][m];
-                const u64 rlo = __shfl_xor(slo, 32);
-                const u64 rhi = __shfl_xor(shi, 32);
-                const u64 klo = h ? plo[1][m] : plo[0][m];
-                const u64 khi = h ? phi[1][m] : phi[0][m];
-                const u128 V = (((u128)khi << 64) | klo) + (((u128)rhi << 64) | rlo);
+                const i64 keep = h ? w[1][m] : w[0][m];
+                const i64 got = (i64)__shfl_xor((u64)(h ? w[0][m] : w[1][m]), 32);
+                const i64 lo4 = h ? got : keep, hi4 = h ? keep : got;  // digits 0..3, 4..7
                 const u64 j = 8 * R * W + 8 * s + 4 * h + m;
+                const u128 V = (u128)(__int128)lo4 + ((u128)(__int128)hi4 << 32) + ((u128)MUL_BIAS << 64) -
+                               (j > 0 ? (u128)MUL_BIAS : (u128)0);
                 if (j < (u64)P) {
                     lo_out[j] = (u64)V;
                     if (j + 1 < (u64)P) hs_out[j + 1] = (u64)(V >> 64);
@@ -587,29 +472,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
-// Slice sums from the split MFMA kernel -> exact unsigned column sums -> limb lo /
-// shifted hi.
-__global__ void k_fold_mfma_cols(const int *__restrict__ part, u32 nslices, const u64 *__restrict__ a,
-                                 const u64 *__restrict__ b, const u64 *__restrict__ lpa, const u64 *__restrict__ lpb,
-                                 u64 na, u64 nb, u64 npairs, u64 *__restrict__ LO, u64 *__restrict__ HS) {
-    const u64 P = na + nb, total = P * npairs, sstride = npairs * 8 * P;
+// Slice sums from the split MFMA kernel (each exact as int32) -> signed limb values
+// -> biased lo / shifted hi, as the unsplit epilogue stores them.
+__global__ void k_fold_mfma_cols(const int *__restrict__ part, u32 nslices, u64 P, u64 npairs, u64 *__restrict__ LO,
+                                 u64 *__restrict__ HS) {
+    const u64 total = P * npairs, sstride = npairs * 8 * P;
     for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
-        const u64 p = idx / P, j = idx - p * P;
-        const u64 *pa = a + p * na, *pb = b + p * nb;
-        const u64 *la = lpa + p * lp_stride(na), *lb = lpb + p * lp_stride(nb);
-        const int *pc = part + p * 8 * P + 8 * j;
-        const ColTerm A1 = col_term(pa, la, na, (i64)j), A2 = col_term(pa, la, na, (i64)j - (i64)nb);
-        const ColTerm B1 = col_term(pb, lb, nb, (i64)j), B2 = col_term(pb, lb, nb, (i64)j - (i64)na);
+        const u64 j = idx % P;
+        const int *pc = part + 8 * idx;
         i64 m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (u32 sl = 0; sl < nslices; ++sl)
 #pragma unroll
             for (int u = 0; u < 8; ++u) m[u] += pc[sl * sstride + u];
-        u128 V = 0;
+        // |m| <= 2^14 (8 min(na, nb) + 1) < 2^39 for any operand that fits the device
+        __int128 v = 0;
 #pragma unroll
-        for (u32 u = 0; u < 8; ++u) {
-            const i64 cf = column_exact(m[u], true, 8 * j + u, u, 8 * na, 8 * nb, A1, A2, B1, B2);
-            V += (u128)(u64)cf << (8 * u);
-        }
+        for (int u = 0; u < 8; ++u) v += (__int128)m[u] * ((__int128)1 << (8 * u));
+        const u128 V = (u128)v + ((u128)MUL_BIAS << 64) - (j > 0 ? (u128)MUL_BIAS : (u128)0);
         LO[idx] = (u64)V;
         if (j + 1 < P) HS[idx + 1] = (u64)(V >> 64);
         if (j == 0) HS[idx] = 0;
@@ -618,7 +497,7 @@ __global__ void k_fold_mfma_cols(const int *__restrict__ part, u32 nslices, cons
 
 // ---------------------------------------------------------------- workspace ----
 struct LargeLayout {
-    size_t colLo, colHi, part, lpa, lpb, seg, LO, HS, total;
+    size_t colLo, colHi, part, ca, cb, tops, LO, HS, total;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -638,12 +517,12 @@ static LargeLayout large_layout(u64 na, u64 nb, u64 npairs, int form, u32 nslice
             L.part = off;
             off = align256(off + (size_t)nslices * npairs * 8 * P * 4);
         }
-        L.lpa = off;
-        off = align256(off + npairs * lp_stride(na) * 8);
-        L.lpb = off;
-        off = align256(off + npairs * lp_stride(nb) * 8);
-        L.seg = off;
-        off = align256(off + npairs * 2 * ((std::max(na, nb) + PREP_SEG - 1) / PREP_SEG + 1) * 4);
+        L.ca = off;  // converted operands (balanced digits), same layout as a and b
+        off = align256(off + npairs * na * 8);
+        L.cb = off;
+        off = align256(off + npairs * nb * 8);
+        L.tops = off;  // their top digits: a's for every pair, then b's
+        off = align256(off + npairs * 2 * 8);
     }
     L.LO = off;
     off = align256(off + npairs * P * 8);
@@ -665,11 +544,12 @@ struct MfmaPlan {
 static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
     const u64 P = na + nb;
     MfmaPlan mp{(P + 2047) / 2048, 1};  // a workgroup covers 2048 output limbs
-    const u64 steps = (8 * nb + 62) / 64 + (u64)ctx->tune.mfma_rows;  // d from 1 - R to dmax
+    const u64 steps = (8 * nb + 63) / 64 + (u64)ctx->tune.mfma_rows;  // d from 1 - R to dmax
     const u64 blocks = mp.ngroups * npairs;
     const u64 target = (u64)std::max(1, ctx->num_cu) * 4;
-    // digit products in a column: at most the shorter operand's digit count
-    const u64 maxcnt = 8 * std::min(na, nb);
+    // digit products in a column: at most the shorter operand's digit count (8 n + 1
+    // balanced digits)
+    const u64 maxcnt = 8 * std::min(na, nb) + 1;
     u64 S = 1;
     if (blocks < target) S = std::max<u64>(1, std::min<u64>((target + blocks - 1) / blocks, (steps + 127) / 128));
     // a slice sum is added to the workspace as a plain int32: |sum| <= 2^14 cnt must stay
@@ -695,6 +575,16 @@ size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int fo
     form = mul_pick_form(ctx, na, nb, form);
     if (mul_one_wave(na + nb, form)) return 0;
     return large_layout(na, nb, npairs, form, form == BN_MUL_MFMA ? mfma_plan(ctx, na, nb, npairs).nslices : 1u).total;
+}
+
+size_t mul_status_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form) {
+    if (na == 0 || nb == 0 || npairs == 0) return 0;
+    form = mul_pick_form(ctx, na, nb, form);
+    if (mul_one_wave(na + nb, form)) return 0;
+    size_t bytes = flat_scan_status_bytes(ctx, na + nb, (na + nb) * npairs);  // the carry pass
+    if (form == BN_MUL_MFMA)  // the operand conversions
+        bytes = std::max({bytes, flat_scan_ext_status_bytes(na, na * npairs), flat_scan_ext_status_bytes(nb, nb * npairs)});
+    return bytes;
 }
 
 bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 na, u64 nb, u64 npairs, int form,
@@ -767,18 +657,15 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         hipLaunchKernelGGL(k_fold_mad, dim3((u32)fold_blocks), dim3(256), 0, s, colLo, colHi, P, total, LO, HS);
         if ((st = bn_launch_status()) != BN_OK) return st;
     } else {
-        u64 *lpa = reinterpret_cast<u64 *>(ws + L.lpa);
-        u64 *lpb = reinterpret_cast<u64 *>(ws + L.lpb);
-        u32 *seg = reinterpret_cast<u32 *>(ws + L.seg);
-        const u64 nseg = (std::max(na, nb) + PREP_SEG - 1) / PREP_SEG;
-        const u64 prep_blocks = nseg * 2 * npairs;
-        if (prep_blocks > 0x7fffffffull) return BN_ERANGE;
-        hipLaunchKernelGGL(k_prep_totals, dim3((u32)prep_blocks), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
-                           (u32)nseg);
-        if ((st = bn_launch_status()) != BN_OK) return st;
-        hipLaunchKernelGGL(k_prep_scan, dim3((u32)prep_blocks), dim3(256), 0, s, a, b, na, nb, lpa, lpb, seg,
-                           (u32)nseg);
-        if ((st = bn_launch_status()) != BN_OK) return st;
+        u64 *ca = reinterpret_cast<u64 *>(ws + L.ca);
+        u64 *cb = reinterpret_cast<u64 *>(ws + L.cb);
+        u64 *tops = reinterpret_cast<u64 *>(ws + L.tops);
+        // balanced digits: every operand + 0x80...80, the carries out as top digits
+        if ((st = launch_flat_scan_ext(ctx, false, ca, a, nullptr, na, npairs, nullptr, true, XOR80, tops, s)) != BN_OK)
+            return st;
+        if ((st = launch_flat_scan_ext(ctx, false, cb, b, nullptr, nb, npairs, nullptr, true, XOR80, tops + npairs,
+                                       s)) != BN_OK)
+            return st;
         // (blocks per wave, Toeplitz row groups): both shapes cover 2048 output limbs
         // per workgroup and stage the same LDS window
         const int R = ctx->tune.mfma_rows;
@@ -790,12 +677,12 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         int *part = split ? reinterpret_cast<int *>(ws + L.part) : nullptr;
         auto kern = R == 2 ? (split ? k_mul_large_mfma<1, 2, true> : k_mul_large_mfma<1, 2, false>)
                            : (split ? k_mul_large_mfma<2, 1, true> : k_mul_large_mfma<2, 1, false>);
-        hipLaunchKernelGGL(kern, dim3((u32)blocks), dim3(256), lds, s, a, b, na, nb, npairs, lpa, lpb, D,
+        hipLaunchKernelGGL(kern, dim3((u32)blocks), dim3(256), lds, s, ca, cb, na, nb, npairs, tops, D,
                            (u32)mp.ngroups, split ? mp.nslices : 1u, LO, HS, part);
         if (split) {
             if ((st = bn_launch_status()) != BN_OK) return st;
-            hipLaunchKernelGGL(k_fold_mfma_cols, dim3((u32)fold_blocks), dim3(256), 0, s, part, mp.nslices, a, b, lpa,
-                               lpb, na, nb, npairs, LO, HS);
+            hipLaunchKernelGGL(k_fold_mfma_cols, dim3((u32)fold_blocks), dim3(256), 0, s, part, mp.nslices, P, npairs,
+                               LO, HS);
         }
         if ((st = bn_launch_status()) != BN_OK) return st;
     }

@@ -85,9 +85,7 @@ N_MUL = 1 << 20
 
 @pytest.mark.parametrize("form", ["mfma", "mad"])
 def test_product_closed_forms_max_size(bnctx, release, form):
-    """(2^(64n) - 1)^2 = X^(2n) - 2 X^n + 1 and 0 x 0 = 0 for n = 2^20 limbs; the zero
-    operand is the worst case of the signed-digit bound (every digit product is
-    +2^14, column sums up to 2^37)."""
+    """(2^(64n) - 1)^2 = X^(2n) - 2 X^n + 1 and 0 x 0 = 0 for n = 2^20 limbs."""
     _need_free(24 * GIB)
     n = N_MUL
     announce("max size product closed forms", form, f"n={n}")
@@ -104,15 +102,23 @@ def test_product_closed_forms_max_size(bnctx, release, form):
 
 
 @pytest.mark.parametrize("form", ["mfma", "mad"])
-def test_product_random_max_size(bnctx, release, form):
-    """Random 2^20 x 2^20 limbs: residues modulo three primes and 2^64 - 1, and the
-    low 256 limbs against the oracle's product of the low 256 limbs."""
+@pytest.mark.parametrize("kind", ["random", "most_negative_digits"])
+def test_product_random_max_size(bnctx, release, form, kind):
+    """2^20 x 2^20 limbs, random or the square of 0x7f...7f80 (every balanced digit
+    -128: each digit product is +2^14, column sums up to 2^37): residues modulo three
+    primes and 2^64 - 1, and the low 256 limbs against the oracle's product of the
+    low 256 limbs."""
     _need_free(24 * GIB)
     n = N_MUL
-    announce("max size product random", form, f"n={n}")
+    announce("max size product", kind, form, f"n={n}")
     g = np.random.default_rng(11)
-    ah = g.integers(0, 2 ** 64 - 1, n, dtype=np.uint64, endpoint=True)
-    bh = g.integers(0, 2 ** 64 - 1, n, dtype=np.uint64, endpoint=True)
+    if kind == "random":
+        ah = g.integers(0, 2 ** 64 - 1, n, dtype=np.uint64, endpoint=True)
+        bh = g.integers(0, 2 ** 64 - 1, n, dtype=np.uint64, endpoint=True)
+    else:
+        ah = np.full(n, 0x7F7F7F7F7F7F7F7F, np.uint64)
+        ah[0] = 0x7F7F7F7F7F7F7F80
+        bh = ah.copy()
     r = torch.full((2 * n,), 7, dtype=torch.int64, device="cuda")
     bn.bn_mul_n_batch(bnctx, r, bn.to_device(ah), bn.to_device(bh), n, n, 1, form)
     torch.cuda.synchronize()

@@ -240,16 +240,40 @@ def test_mul_errors(bnctx):
     assert (H(r) == 0).all()
 
 
+def most_negative_digits(n):
+    """The n-limb operand whose balanced digits are all -128 (top digit 1):
+    2^(64 n) - 0x80...80 = 0x7f...7f80.  Squared, every digit product is +2^14 and a
+    middle column reaches 2^14 (8 n) -- past int32 from n = 16384 limbs."""
+    x = np.full(n, 0x7F7F7F7F7F7F7F7F, np.uint64)
+    x[0] = 0x7F7F7F7F7F7F7F80
+    return x
+
+
 @pytest.mark.parametrize("form", ["mfma", "mad"])
 def test_beyond_single_range_bound(bnctx, form):
     """min(na, nb) > 16448 limbs: a column can hold more than 131586 digit products, so
-    the MFMA form must cut the contraction into slices of at most 2047 steps.  Includes
-    the zero x zero pair (every signed digit product is +2^14) and all-ones."""
+    the MFMA form must cut the contraction into slices of at most 2046 steps.  Includes
+    the most-negative-digit square (every signed digit product is +2^14), zero and
+    all-ones."""
     n = 16500
     g = np.random.default_rng(77)
-    a = np.concatenate([np.zeros(n, np.uint64), np.full(n, 2 ** 64 - 1, np.uint64), _rand(g, n)])
-    b = np.concatenate([np.zeros(n, np.uint64), np.full(n, 2 ** 64 - 1, np.uint64), _rand(g, n)])
-    _check(bnctx, a, b, n, n, 3, form)
+    w = most_negative_digits(n)
+    a = np.concatenate([w, np.zeros(n, np.uint64), np.full(n, 2 ** 64 - 1, np.uint64), _rand(g, n)])
+    b = np.concatenate([w, np.zeros(n, np.uint64), np.full(n, 2 ** 64 - 1, np.uint64), _rand(g, n)])
+    _check(bnctx, a, b, n, n, 4, form)
+
+
+@pytest.mark.parametrize("n", [16384, 16448])
+def test_int32_wrap_decode(bnctx, n):
+    """Unsplit MFMA launches up to 16448 limbs: the most-negative-digit square drives a
+    column to 2^14 (8 n) >= 2^31, which the int32 register holds wrapped and the
+    epilogue recovers (16448: the largest n with at most 131586 digit pairs a column).
+    Paired with a random operand in the other pair."""
+    g = np.random.default_rng(n)
+    w = most_negative_digits(n)
+    a = np.concatenate([w, w])
+    b = np.concatenate([w, _rand(g, n)])
+    _check(bnctx, a, b, n, n, 2, "mfma")
 
 
 @pytest.mark.parametrize("form", ["mfma", "mad"])
