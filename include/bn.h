@@ -149,7 +149,7 @@ bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const 
 
 #define BN_MUL_AUTO 0 /* pick per size from the tuning table (mad below the crossover) */
 #define BN_MUL_MAD 1  /* 32x32->64-bit v_mad_u64_u32 column products */
-#define BN_MUL_MFMA 2 /* 8-bit digit convolution on int8 MFMA, int32 accumulation */
+#define BN_MUL_MFMA 2 /* balanced signed 8-bit digit convolution on int8 MFMA, int32 accumulation */
 
 /* r[0 .. na+nb) = a * b (Theorem 2), exactly na+nb limbs, leading zeros kept.
  * Column products (all independent), then one deferred carry-normalise pass
