@@ -54,6 +54,37 @@ __global__ __launch_bounds__(256) void k_mul_ragged_mfma(const RItem *__restrict
     }
 }
 
+// Both forms in one persistent launch (a batch with mad and MFMA items): the item's
+// form picks the path, wave-uniformly.  One launch instead of two back to back lets
+// the waves that finish their share of one form go on with the other, so the two
+// tails overlap.  Without a bound the two paths' registers add up to four waves per
+// SIMD; capped at five (the MFMA kernel's own occupancy) they fit without spills.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_mul_ragged_mixed(const RItem *__restrict__ items, u32 nitems,
+                                                          u64 *__restrict__ r, const u64 *__restrict__ a,
+                                                          const u64 *__restrict__ b) {
+    __shared__ u64 lds[4 * RAGGED_LDS_U64];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const u32 W = gridDim.x * 4;
+    for (u32 it = blockIdx.x * 4 + w; it < nitems; it += W) {
+        const RItem m = items[it];
+        const u64 *pa = a + m.a_off;
+        const u64 *pb = b + m.b_off;
+        u64 *pr = r + m.r_off;
+        if (m.form == BN_MUL_MFMA) {
+            mul_item_mfma_small<2>(pa, m.na, pb, m.nb, pr, lds + w * RAGGED_LDS_U64);
+            wave_sync();
+        } else {
+            const u32 P = m.na + m.nb;
+            if (P <= 64)
+                mul_item_mad<1>(pa, m.na, pb, m.nb, pr);
+            else if (P <= 128)
+                mul_item_mad<2>(pa, m.na, pb, m.nb, pr);
+            else
+                mul_item_mad<4>(pa, m.na, pb, m.nb, pr);
+        }
+    }
+}
+
 // Ragged add: one wave per pair, walking the pair in rows of 128 limbs (lane l
 // holds limbs 2l, 2l+1 of a row); the carry crosses rows through the wave-uniform
 // carry-out of the row's ballot scan.
@@ -194,13 +225,17 @@ bn_status plan_add_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, bn_p
 
 bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, hipStream_t s) {
     const u32 nmad = pl->nsmall_mad, nmfma = pl->nsmall - pl->nsmall_mad;
-    if (nmad) {
+    if (nmad && nmfma) {
+        hipLaunchKernelGGL(k_mul_ragged_mixed, dim3(persistent_blocks<k_mul_ragged_mixed>(ctx, pl->nsmall)), dim3(256), 0,
+                           s, pl->d_items, pl->nsmall, r, a, b);
+        bn_status st = bn_launch_status();
+        if (st != BN_OK) return st;
+    } else if (nmad) {
         hipLaunchKernelGGL(k_mul_ragged_mad, dim3(persistent_blocks<k_mul_ragged_mad>(ctx, nmad)), dim3(256), 0, s, pl->d_items, nmad,
                            r, a, b);
         bn_status st = bn_launch_status();
         if (st != BN_OK) return st;
-    }
-    if (nmfma) {
+    } else if (nmfma) {
         hipLaunchKernelGGL(k_mul_ragged_mfma, dim3(persistent_blocks<k_mul_ragged_mfma>(ctx, nmfma)), dim3(256), 0, s,
                            pl->d_items + nmad, nmfma, r, a, b);
         bn_status st = bn_launch_status();

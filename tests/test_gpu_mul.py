@@ -162,14 +162,15 @@ def test_ragged_unsorted_sparse_and_large_items(bnctx):
 
 
 def test_ragged_c4_full_graph_replay(bnctx):
-    """2^16 ragged pairs in one persistent launch captured in a HIP graph, replayed with
-    eager work in between; every replay equals the oracle."""
+    """2^16 ragged pairs in one persistent launch captured in a HIP graph (one form, or
+    both forms in one launch for auto), replayed with eager work in between; every
+    replay equals the oracle."""
     a, b, desc, rsz = _ragged_inputs(1 << 16)
     rr = oracle.mul_ragged(a, b, desc, rsz)
     ta, tb = D(a), D(b)
     tr = torch.zeros(rsz, dtype=torch.int64, device="cuda")
     s = torch.cuda.Stream()
-    for form in ("mad", "mfma"):
+    for form in ("mad", "mfma", "auto"):
         announce("ragged mul graph", form)
         plan = bn.bn_plan_mul_ragged(bnctx, desc, form)
         g = bn.bn_graph_capture_mul_ragged(bnctx, plan, tr, ta, tb, s)
