@@ -10,8 +10,12 @@
 // schoolbook kernels in one launch, and the levels are combined bottom-up.  Batches
 // are stored by kind: children [0, N) are the (A_L, B_L) halves, [N, 2N) the
 // (A_H, B_H) halves and [2N, 3N) the absolute differences, so every add/sub of the
-// split and of the combine is a uniform batch over contiguous arrays and runs on the
-// flat scan kernel; the few copies in between are plain streaming kernels.
+// split and of the combine is a uniform batch over contiguous arrays.  Both are a
+// streaming pass and one carry scan: the signs of A_H - A_L and B_H - B_L come first
+// (a compare from the top limb down, which random halves settle in their top limb),
+// then every limb of |A_H - A_L| and of P0 + P1 X^2 + (P0 + P1 - P2) X is a signed
+// sum of a few limbs, stored biased as a low word and a small high word, and one
+// flat carry scan adds the two.
 #include "bn_internal.h"
 
 #include <algorithm>
@@ -19,53 +23,85 @@
 
 namespace {
 
-// For both operands x in {a, b}: lo_x[q] = x[q][0, k), hi_x[q] = x[q][k, 2k), the two
-// halves of N operands of 2k limbs (the halves go to dst_x and dst_x + N k).
-__global__ void k_split_halves(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 N, u64 k,
-                               u64 *__restrict__ da, u64 *__restrict__ db) {
+typedef unsigned __int128 u128;
+
+// neg_x[q] = [hi < lo] for the halves lo = x[q][0, k), hi = x[q][k, 2k) of the N
+// operands of a and of b: one wave per operand, 64 limbs at a time from the top; the
+// highest limb where the halves differ decides (equal halves: 0).
+__global__ __launch_bounds__(256) void k_split_sign(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 N,
+                                                    u64 k, u64 *__restrict__ negA, u64 *__restrict__ negB) {
+    const int lane = threadIdx.x & 63;
+    const u64 gw = blockIdx.x * 4ull + (u64)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (gw >= 2 * N) return;
+    const bool is_b = gw >= N;
+    const u64 q = is_b ? gw - N : gw;
+    const u64 *x = (is_b ? b : a) + 2 * k * q;
+    u64 lt = 0;
+    for (i64 top = (i64)k; top > 0; top -= 64) {
+        const i64 i = top - 64 + lane;
+        const u64 lo = i >= 0 ? x[i] : 0, hi = i >= 0 ? x[k + i] : 0;
+        const u64 diff = __ballot(hi != lo);
+        if (diff) {
+            const int j = 63 - __builtin_clzll(diff);
+            lt = (__ballot(hi < lo) >> j) & 1ull;
+            break;
+        }
+    }
+    if (lane == 0) (is_b ? negB : negA)[q] = lt;
+}
+
+// For both operands: the children lo and hi (copies, to dst_x and dst_x + N k) and the
+// terms of |hi - lo| = s (hi - lo), s = -1 when neg_x[q]: at limb i the value
+// s (hi_i - lo_i) + 2^64 - [i > 0] lies in [0, 2^65); its low word goes to L_x, its
+// high word (0 or 1) to H_x one limb up.  The offsets add up to X^k (zero modulo X^k),
+// so L_x + H_x is |hi - lo|.
+__global__ void k_split_terms(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 N, u64 k,
+                              u64 *__restrict__ da, u64 *__restrict__ db, const u64 *__restrict__ negA,
+                              const u64 *__restrict__ negB, u64 *__restrict__ L, u64 *__restrict__ H) {
     const u64 total = N * k;
     for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
         const u64 q = idx / k, i = idx - q * k;
-        da[idx] = a[2 * k * q + i];
-        da[total + idx] = a[2 * k * q + k + i];
-        db[idx] = b[2 * k * q + i];
-        db[total + idx] = b[2 * k * q + k + i];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const u64 *x = (side ? b : a) + 2 * k * q;
+            u64 *d = side ? db : da;
+            const u64 lo = x[i], hi = x[k + i];
+            d[idx] = lo;
+            d[total + idx] = hi;
+            const bool neg = (side ? negB : negA)[q] != 0;
+            const u128 v = (u128)(neg ? lo : hi) - (neg ? hi : lo) + ((u128)1 << 64) - (i > 0 ? 1u : 0u);
+            u64 *l = L + side * total, *h = H + side * total;
+            l[idx] = (u64)v;
+            if (i + 1 < k) h[idx + 1] = (u64)(v >> 64);
+            if (i == 0) h[idx] = 0;
+        }
     }
 }
 
-// For both operands: dst_x[q] = neg_x[q] ? neg-difference : pos-difference, i.e.
-// |hi - lo| from hi - lo and lo - hi (k limbs each), neg_x[q] the borrow of hi - lo.
-__global__ void k_select_abs(u64 *__restrict__ dst_a, u64 *__restrict__ dst_b, const u64 *__restrict__ pos,
-                             const u64 *__restrict__ negd, const u64 *__restrict__ neg_a,
-                             const u64 *__restrict__ neg_b, u64 N, u64 k) {
-    const u64 total = N * k;
+// The terms of a level's result, per product q (4k limbs): at limb i,
+//     v_i = [i < 2k] P0_i + [i >= 2k] P1_(i-2k) + [k <= i < 3k] (P0_t + P1_t -+ PD_t),  t = i - k,
+// with -PD when the two differences have the same sign (P2 = +PD) and +PD otherwise.
+// v_i lies in (-2^64, 2^66); stored as v_i + 2^64 - [i > 0] (in [0, 2^67)): the low
+// word to L, the high word to H one limb up (H_0 = 0).  The offsets add up to
+// sum_i (X - [i > 0]) X^i = X^(4k), zero modulo X^(4k), and the product fits 4k limbs,
+// so L + H (one carry scan, single-bit carries: H <= 4) is the product.
+__global__ void k_combine_terms(u64 *__restrict__ L, u64 *__restrict__ H, const u64 *__restrict__ P0,
+                                const u64 *__restrict__ P1, const u64 *__restrict__ PD, const u64 *__restrict__ negA,
+                                const u64 *__restrict__ negB, u64 N, u64 k) {
+    const u64 four = 4 * k, total = N * four;
     for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
-        const u64 q = idx / k;
-        dst_a[idx] = neg_a[q] ? negd[idx] : pos[idx];
-        dst_b[idx] = neg_b[q] ? negd[total + idx] : pos[total + idx];
-    }
-}
-
-// Operands of the final addition of a level, per product q (4k limbs each):
-//   out[q] = P0 + P1 X^2              (the two halves side by side),
-//   Y[q]   = (P1 + P0 - P2) X         (2k limbs and a top limb at k .. 3k).
-// With S = P0 + P1 (carry cS), the middle term is S - PD (borrow bM) when s_x s_y > 0
-// and S + PD (carry cP) otherwise; it is never negative (it equals A_H B_L + A_L B_H).
-__global__ void k_assemble(u64 *__restrict__ out, u64 *__restrict__ Y, const u64 *__restrict__ P0,
-                           const u64 *__restrict__ P1, const u64 *__restrict__ Tplus, const u64 *__restrict__ Tminus,
-                           const u64 *__restrict__ cS, const u64 *__restrict__ cP, const u64 *__restrict__ bM,
-                           const u64 *__restrict__ negA, const u64 *__restrict__ negB, u64 N, u64 k) {
-    const u64 total = N * 4 * k;
-    for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
-        const u64 q = idx / (4 * k), i = idx - q * 4 * k;
-        out[idx] = i < 2 * k ? P0[2 * k * q + i] : P1[2 * k * q + i - 2 * k];
-        const bool same = negA[q] == negB[q];  // s_x s_y > 0: P2 = +PD
-        u64 y = 0;
-        if (i >= k && i < 3 * k)
-            y = same ? Tminus[2 * k * q + i - k] : Tplus[2 * k * q + i - k];
-        else if (i == 3 * k)
-            y = same ? cS[q] - bM[q] : cS[q] + cP[q];
-        Y[idx] = y;
+        const u64 q = idx / four, i = idx - q * four;
+        const u64 *p0 = P0 + 2 * k * q, *p1 = P1 + 2 * k * q;
+        u128 v = (u128)(i < 2 * k ? p0[i] : p1[i - 2 * k]) + ((u128)1 << 64) - (i > 0 ? 1u : 0u);
+        if (i >= k && i < 3 * k) {
+            const u64 t = i - k;
+            const u64 d = PD[2 * k * q + t];
+            v += (u128)p0[t] + p1[t];
+            v = negA[q] == negB[q] ? v - d : v + d;
+        }
+        L[idx] = (u64)v;
+        if (i + 1 < four) H[idx + 1] = (u64)(v >> 64);
+        if (i == 0) H[idx] = 0;
     }
 }
 
@@ -79,9 +115,8 @@ struct KLevel {
 };
 struct KPlan {
     std::vector<KLevel> lv;  // 0 .. levels
-    u64 d1, d2;              // hi - lo and lo - hi of a then b (2 N_l k each, largest level)
-    u64 S, Tp, Tm, Y;        // combine temporaries (largest level)
-    u64 cS, cP, bM;          // combine carries (largest level)
+    u64 d1, d2;              // split terms: low words, shifted high words (a then b, N_l k each)
+    u64 L, H;                // combine terms: low words and shifted high words (4 N_l k each)
     u64 total;               // u64 words
 };
 
@@ -94,7 +129,7 @@ KPlan karatsuba_plan(u64 n, u64 npairs, int levels) {
         return o;
     };
     p.lv.resize(levels + 1);
-    u64 N = npairs, m = n, maxNk = 0, maxN = 0;
+    u64 N = npairs, m = n, maxNk = 0;
     for (int l = 0; l <= levels; ++l) {
         KLevel &L = p.lv[l];
         L.N = N;
@@ -108,20 +143,14 @@ KPlan karatsuba_plan(u64 n, u64 npairs, int levels) {
             L.negA = take(N);
             L.negB = take(N);
             maxNk = std::max(maxNk, N * (m / 2));
-            maxN = std::max(maxN, N);
         }
         N *= 3;
         m /= 2;
     }
     p.d1 = take(2 * maxNk);  // hi - lo of a, then of b
     p.d2 = take(2 * maxNk);  // lo - hi of a, then of b
-    p.S = take(2 * maxNk);
-    p.Tp = take(2 * maxNk);
-    p.Tm = take(2 * maxNk);
-    p.Y = take(4 * maxNk);
-    p.cS = take(maxN);
-    p.cP = take(maxN);
-    p.bM = take(maxN);
+    p.L = take(4 * maxNk);
+    p.H = take(4 * maxNk);
     p.total = off;
     return p;
 }
@@ -148,20 +177,17 @@ bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, 
         const u64 *pb = l == 0 ? b : w + P.B;
         u64 *ca = w + C.A, *cb = w + C.B;  // [lows | highs | |differences|], N x k each
         const u64 Nk = N * k;
-        hipLaunchKernelGGL(k_split_halves, dim3(stream_blocks(Nk)), dim3(256), 0, s, pa, pb, N, k, ca, cb);
+        if ((2 * N + 3) / 4 > 0x7fffffffull) return BN_ERANGE;
+        hipLaunchKernelGGL(k_split_sign, dim3((u32)((2 * N + 3) / 4)), dim3(256), 0, s, pa, pb, N, k, w + P.negA,
+                           w + P.negB);
         if ((st = bn_launch_status()) != BN_OK) return st;
-        for (int side = 0; side < 2; ++side) {
-            u64 *dst = side ? cb : ca;
-            // high - low with its borrow (the sign), and low - high
-            if ((st = launch_flat_scan(ctx, true, w + p.d1 + side * Nk, dst + Nk, dst, k, N,
-                                       w + (side ? P.negB : P.negA), s)) != BN_OK)
-                return st;
-            if ((st = launch_flat_scan(ctx, true, w + p.d2 + side * Nk, dst, dst + Nk, k, N, nullptr, s)) != BN_OK)
-                return st;
-        }
-        hipLaunchKernelGGL(k_select_abs, dim3(stream_blocks(Nk)), dim3(256), 0, s, ca + 2 * Nk, cb + 2 * Nk, w + p.d1,
-                           w + p.d2, w + P.negA, w + P.negB, N, k);
+        hipLaunchKernelGGL(k_split_terms, dim3(stream_blocks(Nk)), dim3(256), 0, s, pa, pb, N, k, ca, cb, w + P.negA,
+                           w + P.negB, w + p.d1, w + p.d2);
         if ((st = bn_launch_status()) != BN_OK) return st;
+        for (int side = 0; side < 2; ++side)  // |hi - lo| = L + H, the children [2N, 3N)
+            if ((st = launch_flat_scan(ctx, false, (side ? cb : ca) + 2 * Nk, w + p.d1 + side * Nk, w + p.d2 + side * Nk,
+                                       k, N, nullptr, s)) != BN_OK)
+                return st;
     }
     // ---- the bottom batch on the schoolbook kernels ----
     const KLevel &Bt = p.lv[levels];
@@ -172,14 +198,11 @@ bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, 
         const u64 N = P.N, k = P.m / 2, twok = 2 * k;
         const u64 *P0 = w + C.R, *P1 = P0 + N * twok, *PD = P1 + N * twok;
         u64 *out = l == 0 ? r : w + P.R;
-        if ((st = launch_flat_scan(ctx, false, w + p.S, P0, P1, twok, N, w + p.cS, s)) != BN_OK) return st;
-        if ((st = launch_flat_scan(ctx, false, w + p.Tp, w + p.S, PD, twok, N, w + p.cP, s)) != BN_OK) return st;
-        if ((st = launch_flat_scan(ctx, true, w + p.Tm, w + p.S, PD, twok, N, w + p.bM, s)) != BN_OK) return st;
-        hipLaunchKernelGGL(k_assemble, dim3(stream_blocks(N * 4 * k)), dim3(256), 0, s, out, w + p.Y, P0, P1,
-                           w + p.Tp, w + p.Tm, w + p.cS, w + p.cP, w + p.bM, w + P.negA, w + P.negB, N, k);
+        hipLaunchKernelGGL(k_combine_terms, dim3(stream_blocks(N * 4 * k)), dim3(256), 0, s, w + p.L, w + p.H, P0, P1,
+                           PD, w + P.negA, w + P.negB, N, k);
         if ((st = bn_launch_status()) != BN_OK) return st;
-        // out = P0 + P1 X^2 + (P1 + P0 - P2) X; the product fits 4k limbs, so no carry out
-        if ((st = launch_flat_scan(ctx, false, out, out, w + p.Y, 4 * k, N, nullptr, s)) != BN_OK) return st;
+        // out = P0 + P1 X^2 + (P1 + P0 - P2) X = L + H; the product fits 4k limbs, so no carry out
+        if ((st = launch_flat_scan(ctx, false, out, w + p.L, w + p.H, 4 * k, N, nullptr, s)) != BN_OK) return st;
     }
     return BN_OK;
 }
