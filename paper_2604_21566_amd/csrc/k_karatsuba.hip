@@ -12,7 +12,7 @@
 // (A_H, B_H) halves and [2N, 3N) the absolute differences, so every add/sub of the
 // split and of the combine is a uniform batch over contiguous arrays.  Both are a
 // streaming pass and one carry scan: the signs of A_H - A_L and B_H - B_L come first
-// (a compare from the top limb down, which random halves settle in their top limb),
+// (the highest limb where the halves differ, found piece by piece),
 // then every limb of |A_H - A_L| and of P0 + P1 X^2 + (P0 + P1 - P2) X is a signed
 // sum of a few limbs, stored biased as a low word and a small high word, and one
 // flat carry scan adds the two.
@@ -26,28 +26,47 @@ namespace {
 typedef unsigned __int128 u128;
 
 // neg_x[q] = [hi < lo] for the halves lo = x[q][0, k), hi = x[q][k, 2k) of the N
-// operands of a and of b: one wave per operand, 64 limbs at a time from the top; the
-// highest limb where the halves differ decides (equal halves: 0).
-__global__ __launch_bounds__(256) void k_split_sign(const u64 *__restrict__ a, const u64 *__restrict__ b, u64 N,
-                                                    u64 k, u64 *__restrict__ negA, u64 *__restrict__ negB) {
-    const int lane = threadIdx.x & 63;
-    const u64 gw = blockIdx.x * 4ull + (u64)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (gw >= 2 * N) return;
-    const bool is_b = gw >= N;
-    const u64 q = is_b ? gw - N : gw;
-    const u64 *x = (is_b ? b : a) + 2 * k * q;
-    u64 lt = 0;
-    for (i64 top = (i64)k; top > 0; top -= 64) {
-        const i64 i = top - 64 + lane;
-        const u64 lo = i >= 0 ? x[i] : 0, hi = i >= 0 ? x[k + i] : 0;
-        const u64 diff = __ballot(hi != lo);
-        if (diff) {
-            const int j = 63 - __builtin_clzll(diff);
-            lt = (__ballot(hi < lo) >> j) & 1ull;
-            break;
-        }
+// operands of a and of b, in two steps with a fixed amount of work whatever the data
+// (equal halves, as in all-ones or zero operands, leave nothing to stop early on):
+// one workgroup per piece of SIGN_PIECE limbs of an operand finds the highest limb i
+// where the halves differ and writes key = (i + 1) * 2 + [hi_i < lo_i] (0: no
+// difference); then the largest key of an operand's pieces gives its sign.
+constexpr u64 SIGN_PIECE = 2048;  // 256 threads x 8 limbs
+
+__global__ __launch_bounds__(256) void k_split_sign_pieces(const u64 *__restrict__ a, const u64 *__restrict__ b,
+                                                           u64 N, u64 k, u64 npieces, u64 *__restrict__ keys) {
+    __shared__ u64 sh[4];
+    const u64 seg = blockIdx.x / npieces, piece = blockIdx.x - seg * npieces;
+    const bool is_b = seg >= N;
+    const u64 *x = (is_b ? b : a) + 2 * k * (is_b ? seg - N : seg);
+    const u64 base = piece * SIGN_PIECE;
+    u64 lo[8], hi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const u64 i = base + 256 * u + threadIdx.x;
+        lo[u] = i < k ? x[i] : 0;
+        hi[u] = i < k ? x[k + i] : 0;
     }
-    if (lane == 0) (is_b ? negB : negA)[q] = lt;
+    u64 key = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const u64 i = base + 256 * u + threadIdx.x;
+        if (hi[u] != lo[u]) key = std::max(key, ((i + 1) << 1) | (hi[u] < lo[u] ? 1u : 0u));
+    }
+    for (int off = 32; off > 0; off >>= 1) key = std::max(key, (u64)__shfl_xor(key, off));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) keys[blockIdx.x] = std::max(std::max(sh[0], sh[1]), std::max(sh[2], sh[3]));
+}
+
+__global__ void k_split_sign_reduce(const u64 *__restrict__ keys, u64 N, u64 npieces, u64 *__restrict__ negA,
+                                    u64 *__restrict__ negB) {
+    const u64 seg = blockIdx.x * (u64)blockDim.x + threadIdx.x;
+    if (seg >= 2 * N) return;
+    u64 m = 0;
+    for (u64 p = 0; p < npieces; ++p) m = std::max(m, keys[seg * npieces + p]);
+    if (seg < N) negA[seg] = m & 1;
+    else negB[seg - N] = m & 1;
 }
 
 // For both operands: the children lo and hi (copies, to dst_x and dst_x + N k) and the
@@ -117,6 +136,7 @@ struct KPlan {
     std::vector<KLevel> lv;  // 0 .. levels
     u64 d1, d2;              // split terms: low words, shifted high words (a then b, N_l k each)
     u64 L, H;                // combine terms: low words and shifted high words (4 N_l k each)
+    u64 keys;                // split: per-piece sign keys (2 N_l pieces_l, largest level)
     u64 total;               // u64 words
 };
 
@@ -129,7 +149,7 @@ KPlan karatsuba_plan(u64 n, u64 npairs, int levels) {
         return o;
     };
     p.lv.resize(levels + 1);
-    u64 N = npairs, m = n, maxNk = 0;
+    u64 N = npairs, m = n, maxNk = 0, maxkeys = 0;
     for (int l = 0; l <= levels; ++l) {
         KLevel &L = p.lv[l];
         L.N = N;
@@ -143,6 +163,7 @@ KPlan karatsuba_plan(u64 n, u64 npairs, int levels) {
             L.negA = take(N);
             L.negB = take(N);
             maxNk = std::max(maxNk, N * (m / 2));
+            maxkeys = std::max(maxkeys, 2 * N * ((m / 2 + SIGN_PIECE - 1) / SIGN_PIECE));
         }
         N *= 3;
         m /= 2;
@@ -151,6 +172,7 @@ KPlan karatsuba_plan(u64 n, u64 npairs, int levels) {
     p.d2 = take(2 * maxNk);  // lo - hi of a, then of b
     p.L = take(4 * maxNk);
     p.H = take(4 * maxNk);
+    p.keys = take(maxkeys);
     p.total = off;
     return p;
 }
@@ -177,9 +199,13 @@ bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, 
         const u64 *pb = l == 0 ? b : w + P.B;
         u64 *ca = w + C.A, *cb = w + C.B;  // [lows | highs | |differences|], N x k each
         const u64 Nk = N * k;
-        if ((2 * N + 3) / 4 > 0x7fffffffull) return BN_ERANGE;
-        hipLaunchKernelGGL(k_split_sign, dim3((u32)((2 * N + 3) / 4)), dim3(256), 0, s, pa, pb, N, k, w + P.negA,
-                           w + P.negB);
+        const u64 npieces = (k + SIGN_PIECE - 1) / SIGN_PIECE;
+        if (2 * N * npieces > 0x7fffffffull) return BN_ERANGE;
+        hipLaunchKernelGGL(k_split_sign_pieces, dim3((u32)(2 * N * npieces)), dim3(256), 0, s, pa, pb, N, k, npieces,
+                           w + p.keys);
+        if ((st = bn_launch_status()) != BN_OK) return st;
+        hipLaunchKernelGGL(k_split_sign_reduce, dim3((u32)((2 * N + 255) / 256)), dim3(256), 0, s, w + p.keys, N,
+                           npieces, w + P.negA, w + P.negB);
         if ((st = bn_launch_status()) != BN_OK) return st;
         hipLaunchKernelGGL(k_split_terms, dim3(stream_blocks(Nk)), dim3(256), 0, s, pa, pb, N, k, ca, cb, w + P.negA,
                            w + P.negB, w + p.d1, w + p.d2);
