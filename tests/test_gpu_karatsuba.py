@@ -72,6 +72,34 @@ def test_signs_and_carries(bnctx, form, levels):
     _check(bnctx, pa.reshape(-1), pb.reshape(-1), n, pa.shape[0], levels, form)
 
 
+@pytest.mark.parametrize("n", [12288, 12000])
+def test_sign_pieces(bnctx, n):
+    """Halves that differ in one limb only, at the ends and the boundaries of the
+    2048-limb pieces the split's sign pass works in (k = n/2 = 6144: three whole
+    pieces; 6000: a ragged last piece), in both directions: the sign must come from
+    the highest differing piece whatever the pieces above it hold (equal limbs)."""
+    k = n // 2
+    g = np.random.default_rng(n)
+    positions = [0, 5, 2047, 2048, 4095, 4096, k - 1]
+    A, B = [], []
+    for idx, pos in enumerate(positions):
+        lo = g.integers(1, MAX - 1, k, dtype=np.uint64, endpoint=True)
+        hi = lo.copy()
+        hi[pos] += np.uint64(1) if idx % 2 == 0 else np.uint64(0)
+        hi[pos] -= np.uint64(0) if idx % 2 == 0 else np.uint64(1)
+        A.append(np.concatenate([lo, hi]))
+        # b: the opposite direction at another piece boundary
+        lo2 = g.integers(1, MAX - 1, k, dtype=np.uint64, endpoint=True)
+        hi2 = lo2.copy()
+        p2 = positions[(idx + 3) % len(positions)]
+        hi2[p2] += np.uint64(0) if idx % 2 == 0 else np.uint64(1)
+        hi2[p2] -= np.uint64(1) if idx % 2 == 0 else np.uint64(0)
+        B.append(np.concatenate([lo2, hi2]))
+    a, b = np.concatenate(A), np.concatenate(B)
+    for levels in (1, 2):
+        _check(bnctx, a, b, n, len(positions), levels, "mfma")
+
+
 @pytest.mark.parametrize("levels", [1, 2])
 def test_c5_full(bnctx, levels):
     """64 pairs x 16384 limbs (incl. all-ones x all-ones and zero x zero): sampled pairs
