@@ -264,9 +264,11 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t value);
 bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *value);
 const char *bn_param_names(void);
 
-/* Time the candidate tile shapes and the mad/MFMA crossover on this device (scratch
- * operands allocated internally), store the winners in the context and, if
- * out_json != NULL, write them as a JSON object.  Synchronous; takes seconds. */
+/* Time the candidate add/sub tile shapes, the mad/MFMA crossovers (one for products of
+ * at most 1024 limbs, one for larger ones) and the large MFMA kernel's staging window
+ * on this device (scratch operands allocated internally), store the winners in the
+ * context and, if out_json != NULL, write them as a JSON object.  Synchronous; takes
+ * seconds. */
 bn_status bn_autotune(bn_ctx *ctx, const char *out_json);
 
 /* Measured device rates, the ceilings the rooflines are also stated against:

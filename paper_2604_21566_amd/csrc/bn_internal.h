@@ -133,6 +133,7 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
 size_t mul_workspace_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form);
 size_t mul_status_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form);  // chained-scan status words
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form);
+bool mul_small_range(u64 P);  // products of P limbs that take mul.small_crossover_limbs
 
 // ---- Karatsuba levels (k_karatsuba.hip) ----
 bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, int levels,

@@ -570,11 +570,13 @@ static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
     return mp;
 }
 
+bool mul_small_range(u64 P) { return P <= SMALL_MAX_P; }
+
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
     if (form != BN_MUL_AUTO) return form;
-    // products of at most 256 limbs run on the one-wave kernels, larger ones on the
-    // column-workspace kernels: each pair of kernels has its own crossover
-    const i64 x = na + nb <= SMALL_MAX_P ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
+    // products of at most 1024 limbs (mad: one wave; MFMA: one wave up to 512 limbs)
+    // and larger ones (column-workspace kernels) have a crossover each
+    const i64 x = mul_small_range(na + nb) ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
     return (i64)std::min(na, nb) >= x ? BN_MUL_MFMA : BN_MUL_MAD;
 }
 

@@ -214,9 +214,9 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         }
     }
 
-    // 2) mad vs MFMA crossovers: square products, equal total work per size; sizes up
-    // to 128 limbs run on the one-wave kernels, larger ones on the column kernels, and
-    // each range gets the smallest size from which MFMA wins at every larger size
+    // 2) mad vs MFMA crossovers: square products, equal total work per size; products
+    // in the one-wave range (mul_small_range) and larger ones each get the smallest
+    // size from which MFMA wins at every larger size of the range
     i64 crossover = -1, small_crossover = -1;
     for (u64 n = 4; n <= 4096; n *= 2) {
         u64 npairs = std::max<u64>(1, std::min<u64>((1ull << 26) / (n * n), NBIG / n));
@@ -227,7 +227,7 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         snprintf(line, sizeof line, "    \"sweep.n%llu\": \"mad %.4f ms, mfma %.4f ms, pairs %llu\",\n",
                  (unsigned long long)n, tm, tf, (unsigned long long)npairs);
         log += line;
-        i64 &x = 2 * n <= 256 ? small_crossover : crossover;
+        i64 &x = mul_small_range(2 * n) ? small_crossover : crossover;
         if (tf < tm) {
             if (x < 0) x = (i64)n;
         } else {
@@ -236,6 +236,27 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
     }
     t.mul_crossover_limbs = crossover > 0 ? crossover : (i64)1 << 40;
     t.mul_small_crossover_limbs = small_crossover > 0 ? small_crossover : (i64)1 << 40;
+
+    // 3) staging window of the large MFMA kernel: 64 products of 16384 limbs (1024
+    // workgroups, more than the device holds at once) for windows that let three
+    // (<= 234 steps) or two workgroups share a CU
+    {
+        const u64 n = 16384, npairs = 64;
+        float best = 1e30f;
+        int bd = t.mfma_chunk;
+        for (int D : {128, 192, 224, 234, 256}) {
+            t.mfma_chunk = D;
+            const float ms = time_ms([&] { launch_mul_batch(ctx, r, a, b, n, n, npairs, BN_MUL_MFMA, nullptr); }, 3);
+            char line[96];
+            snprintf(line, sizeof line, "    \"sweep.mfma_chunk%d\": \"%.4f ms\",\n", D, ms);
+            log += line;
+            if (ms < best) {
+                best = ms;
+                bd = D;
+            }
+        }
+        t.mfma_chunk = bd;
+    }
     (void)hipDeviceSynchronize();
     (void)hipFree(a);
     (void)hipFree(b);
