@@ -212,10 +212,11 @@ __device__ __forceinline__ void mfma_step(v16i (&acc)[NW][2 * R], const v4i (&F)
             acc[i][m] = __builtin_amdgcn_mfma_i32_32x32x32_i8(F[m + 1], A1[i], acc[i][m], 0, 0, 0);
 }
 
-// Three workgroups per CU (three waves per SIMD) when the staging window is at most
-// 234 steps (224 by default): the registers are capped at 168 for that, which spills
-// a few values of the set-up and the epilogue but nothing in the step loop, and the
-// third wave hides more of the LDS latency (3-8% faster than two waves with 256 steps).
+// Registers capped at 168, so that three workgroups share a CU (three waves per SIMD)
+// when the staging window is at most 234 steps (224 by default); a few values of the
+// set-up and the epilogue spill, nothing in the step loop.  The third wave pays at
+// mid sizes (4096 limbs: 224 steps 2% faster than 256); on 16384-limb products the
+// capped code is fastest with 256 steps at two workgroups per CU.
 template <int NW, int R, bool SPLIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_mul_large_mfma(
     const u64 *__restrict__ a, const u64 *__restrict__ b, u64 na, u64 nb, u64 npairs, const u64 *__restrict__ tops,
