@@ -248,8 +248,10 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "mul.small_crossover_limbs"        the same for na + nb <= 1024 (one wave per product)
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
  *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large
- *                                      MFMA kernel: even, 16..256 (default 224; up to 234,
- *                                      three workgroups share a CU)
+ *                                      MFMA kernel: even, 16..256 (up to 234, three workgroups
+ *                                      share a CU), or 0 (default): by size, 256 for unsplit
+ *                                      launches whose shorter operand has >= 10240 limbs,
+ *                                      224 otherwise
  *   "mul.mfma_rows"                    Toeplitz rows per column block of the large MFMA
  *                                      kernel, in groups of 64: 1 or 2 (default 2: the same
  *                                      LDS reads feed twice the MFMAs)

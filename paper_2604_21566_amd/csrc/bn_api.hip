@@ -475,7 +475,7 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
         if (v < 64 || v > (1 << 20) || (v % 8)) return BN_EINVAL;
         t.mad_xchunk = (int)v;
     } else if (k == "mul.mfma_chunk") {
-        if (v < 16 || v > 256 || (v & 1)) return BN_EINVAL;  // even (steps run in pairs); staging registers
+        if (v != 0 && (v < 16 || v > 256 || (v & 1))) return BN_EINVAL;  // even (steps run in pairs); staging registers
         t.mfma_chunk = (int)v;
     } else if (k == "mul.mfma_rows") {
         if (v != 1 && v != 2) return BN_EINVAL;

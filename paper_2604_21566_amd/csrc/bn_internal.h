@@ -51,8 +51,9 @@ struct Tuning {
     i64 mul_small_crossover_limbs = 24;  // BN_MUL_AUTO, na + nb <= 1024 (one-wave kernels): the same
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
-    int mfma_chunk = 224;              // Toeplitz steps staged in LDS per round (even, 16..256; three
-                                       // workgroups of the large MFMA kernel fit a CU up to 234)
+    int mfma_chunk = 0;                // Toeplitz steps staged in LDS per round (even, 16..256; three
+                                       // workgroups of the large MFMA kernel fit a CU up to 234);
+                                       // 0: by size (mfma_window in k_mul.hip)
     int mfma_rows = 2;                 // Toeplitz row groups of 64 per column block (1 or 2)
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)

@@ -573,6 +573,16 @@ static MfmaPlan mfma_plan(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
 
 bool mul_small_range(u64 P) { return P <= SMALL_MAX_P; }
 
+// Staging window of the large MFMA kernel: the tuned value, or by size: 224 steps
+// (three workgroups per CU) unless the launch is unsplit with long contractions
+// (shorter operand >= 10240 limbs), where the rounds of 256 steps at two workgroups
+// per CU are faster (interleaved measurements: 2048 - 8192 limbs 224 faster by 2-7%,
+// 12288 and 16384 limbs 256 faster by 2%, one split 16500-limb product 224 by 1%).
+static u32 mfma_window(const bn_ctx *ctx, u64 na, u64 nb, u32 nslices) {
+    if (ctx->tune.mfma_chunk) return (u32)ctx->tune.mfma_chunk;
+    return (std::min(na, nb) >= 10240 && nslices == 1) ? 256u : 224u;
+}
+
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
     if (form != BN_MUL_AUTO) return form;
     // products of at most 1024 limbs (mad: one wave; MFMA: one wave up to 512 limbs)
@@ -681,7 +691,7 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         // per workgroup and stage the same LDS window
         const int R = ctx->tune.mfma_rows;
         const int NW = 2 / R;
-        const u32 D = (u32)ctx->tune.mfma_chunk;
+        const u32 D = mfma_window(ctx, na, nb, split ? mp.nslices : 1u);
         const u64 blocks = mp.ngroups * npairs * mp.nslices;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
         const size_t lds = (size_t)64 * (D + 2 + R) + (size_t)80 * (128 * NW * R + D);

@@ -237,25 +237,41 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
     t.mul_crossover_limbs = crossover > 0 ? crossover : (i64)1 << 40;
     t.mul_small_crossover_limbs = small_crossover > 0 ? small_crossover : (i64)1 << 40;
 
-    // 3) staging window of the large MFMA kernel: 64 products of 16384 limbs (1024
-    // workgroups, more than the device holds at once) for windows that let three
-    // (<= 234 steps) or two workgroups share a CU
+    // 3) staging window of the large MFMA kernel: by size (0) or one fixed window, on
+    // 64 products of 16384 limbs and 576 of 4096 limbs (the bottom of two Karatsuba
+    // levels on C5), candidates interleaved over three rounds; the winner has the lowest
+    // sum of times relative to the best time of each shape, and a fixed window replaces
+    // the size rule only when it is better by more than 1% (the noise of this sweep)
     {
-        const u64 n = 16384, npairs = 64;
-        float best = 1e30f;
-        int bd = t.mfma_chunk;
-        for (int D : {128, 192, 224, 234, 256}) {
-            t.mfma_chunk = D;
-            const float ms = time_ms([&] { launch_mul_batch(ctx, r, a, b, n, n, npairs, BN_MUL_MFMA, nullptr); }, 3);
-            char line[96];
-            snprintf(line, sizeof line, "    \"sweep.mfma_chunk%d\": \"%.4f ms\",\n", D, ms);
+        const int cand[] = {0, 192, 224, 234, 256};
+        constexpr int NC = sizeof cand / sizeof cand[0];
+        const u64 shape[2][2] = {{16384, 64}, {4096, 576}};
+        float tms[2][NC] = {};
+        constexpr int ROUNDS = 3;
+        for (int round = 0; round < ROUNDS; ++round)
+            for (int sh = 0; sh < 2; ++sh)
+                for (int c = 0; c < NC; ++c) {
+                    t.mfma_chunk = cand[c];
+                    const u64 n = shape[sh][0], np = shape[sh][1];
+                    tms[sh][c] += time_ms([&] { launch_mul_batch(ctx, r, a, b, n, n, np, BN_MUL_MFMA, nullptr); }, 5);
+                }
+        float best[2] = {1e30f, 1e30f};
+        for (int sh = 0; sh < 2; ++sh)
+            for (int c = 0; c < NC; ++c) best[sh] = std::min(best[sh], tms[sh][c]);
+        int bc = 0;
+        float bscore = 1e30f;
+        for (int c = 0; c < NC; ++c) {
+            const float score = tms[0][c] / best[0] + tms[1][c] / best[1];
+            char line[128];
+            snprintf(line, sizeof line, "    \"sweep.mfma_chunk%d\": \"%.4f ms (16384 x 64), %.4f ms (4096 x 576)\",\n",
+                     cand[c], tms[0][c] / ROUNDS, tms[1][c] / ROUNDS);
             log += line;
-            if (ms < best) {
-                best = ms;
-                bd = D;
+            if (c == 0 || score < bscore - 0.02f) {
+                bscore = score;
+                bc = c;
             }
         }
-        t.mfma_chunk = bd;
+        t.mfma_chunk = cand[bc];
     }
     (void)hipDeviceSynchronize();
     (void)hipFree(a);

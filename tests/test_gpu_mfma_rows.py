@@ -52,12 +52,12 @@ def test_random(ctx1, na, nb):
            g.integers(0, MAX, nb * npairs, dtype=np.uint64, endpoint=True), na, nb, npairs)
 
 
-@pytest.mark.parametrize("chunk", [16, 50, 224, 234, 256])
+@pytest.mark.parametrize("chunk", [0, 16, 50, 224, 234, 256])
 @pytest.mark.parametrize("na,nb", [(1500, 1500), (3000, 700), (16384, 16384)])
 def test_round_lengths(ctx1, chunk, na, nb):
-    """Staged rounds of 16, 50, 224 (the default), 234 (the longest with three
-    workgroups per CU) and 256 steps (the last round ragged), unsplit and split (one or
-    two pairs leave too few workgroups, so the contraction is sliced)."""
+    """Staged rounds of 16, 50, 224, 234 (the longest with three workgroups per CU) and
+    256 steps (the last round ragged), and the by-size default (0), unsplit and split
+    (one or two pairs leave too few workgroups, so the contraction is sliced)."""
     old = bn.bn_get_param(ctx1, "mul.mfma_chunk")
     bn.bn_set_param(ctx1, "mul.mfma_chunk", chunk)
     try:
