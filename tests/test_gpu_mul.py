@@ -269,12 +269,25 @@ def test_int32_wrap_decode(bnctx, n):
     """Unsplit MFMA launches up to 16448 limbs: the most-negative-digit square drives a
     column to 2^14 (8 n) >= 2^31, which the int32 register holds wrapped and the
     epilogue recovers (16448: the largest n with at most 131586 digit pairs a column).
-    Paired with a random operand in the other pair."""
+    64 pairs give about four workgroups per CU, so the contraction is not split (the
+    workspace holds no slice sums, checked below; split slices are exact and never
+    wrap).  Pairs 0 and 1 (worst x worst, worst x random) against the oracle, every
+    pair by residues."""
+    npairs = 64
+    ws = bn.bn_workspace_size(bnctx, 1, n, n, npairs, bn.BN_MUL_MFMA)
+    # converted operands, their top digits, lo and shifted hi; a split would add at
+    # least two slices of int32 column sums (2 * npairs * 8 * 2n * 4 bytes)
+    assert ws < 8 * npairs * (n + n + 2 + 2 * 2 * n) + (1 << 20), ws
     g = np.random.default_rng(n)
     w = most_negative_digits(n)
-    a = np.concatenate([w, w])
-    b = np.concatenate([w, _rand(g, n)])
-    _check(bnctx, a, b, n, n, 2, "mfma")
+    a = np.concatenate([w, w] + [_rand(g, n) for _ in range(npairs - 2)])
+    b = np.concatenate([w, _rand(g, n)] + [_rand(g, n) for _ in range(npairs - 2)])
+    r = _mul_batch(bnctx, a, b, n, n, npairs, "mfma")
+    for p in (0, 1):
+        rr = oracle.mul(a[p * n:(p + 1) * n], b[p * n:(p + 1) * n])
+        bad = np.nonzero(r[p * 2 * n:(p + 1) * 2 * n] != rr)[0]
+        assert bad.size == 0, f"pair {p}: {bad.size} bad limbs, first at {bad[0]}"
+    assert _residues_ok(a, b, r, n, npairs) == -1
 
 
 @pytest.mark.parametrize("form", ["mfma", "mad"])
