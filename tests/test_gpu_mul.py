@@ -75,6 +75,27 @@ def test_large_pathological(bnctx, form, n):
 
 
 @pytest.mark.parametrize("form", ["mad", "mfma"])
+@pytest.mark.parametrize("na,nb,npairs", [(1000, 24, 3), (600, 700, 2), (3000, 2000, 1), (40, 30, 9)])
+def test_misaligned_operands(bnctx, form, na, nb, npairs):
+    """Operands and product one limb into their buffers (8-byte but not 16-byte
+    aligned): the operand conversion and carry scans take their 8-byte-load shapes;
+    the limb before the product stays untouched."""
+    announce("mul misaligned", form, f"na={na}", f"nb={nb}", f"npairs={npairs}")
+    g = np.random.default_rng(na + 7 * nb)
+    a, b = _rand(g, na * npairs), _rand(g, nb * npairs)
+    ta = torch.zeros(na * npairs + 1, dtype=torch.int64, device="cuda")
+    tb = torch.zeros(nb * npairs + 1, dtype=torch.int64, device="cuda")
+    ta[1:] = D(a)
+    tb[1:] = D(b)
+    tr = torch.full((npairs * (na + nb) + 1,), -1, dtype=torch.int64, device="cuda")
+    bn.bn_mul_n_batch(bnctx, tr[1:], ta[1:], tb[1:], na, nb, npairs, form)
+    torch.cuda.synchronize()
+    r = H(tr)
+    assert int(r[0]) == 2 ** 64 - 1
+    assert (r[1:] == oracle.mul_batch(a, b, na, nb, npairs)).all()
+
+
+@pytest.mark.parametrize("form", ["mad", "mfma"])
 def test_c1(bnctx, form):
     a, b = wl.c1("mul")
     _check(bnctx, a, b, 4, 4, 1088, form)
