@@ -407,13 +407,15 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         ms, _ = gpu_time(lambda: bn.bn_mul_ragged(ctx, plan, tr, ta, tb), 10, 2)
         bn.bn_plan_destroy(plan)
         c4["auto_direct_ms"] = ms
-        # per size bucket (larger operand length in [lo, 2 lo)), each bucket its own graph
+        # per size bucket (larger operand length in [lo, 2 lo), the last one [64, 128]: the
+        # 128-limb operands alone are a few hundred pairs, too few to time), each bucket
+        # its own graph
         big = np.maximum(desc[:, 3], desc[:, 4])
         buckets = {}
         crossover = None
         lo = 4
-        while lo <= 128:
-            sel = desc[(big >= lo) & (big < 2 * lo)] if lo < 128 else desc[big >= lo]
+        while lo <= 64:
+            sel = desc[(big >= lo) & (big < 2 * lo)] if lo < 64 else desc[big >= lo]
             if len(sel):
                 w = float((sel[:, 3].astype(np.float64) * sel[:, 4].astype(np.float64)).sum())
                 row = {"pairs": int(len(sel)), "limb_products": w}
@@ -431,7 +433,7 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
                     crossover = lo if crossover is None else crossover
                 else:
                     crossover = None
-                buckets[f"{lo}-{2 * lo - 1 if lo < 128 else 128}"] = row
+                buckets[f"{lo}-{2 * lo - 1 if lo < 64 else 128}"] = row
             lo *= 2
         c4["buckets_by_longer_operand_limbs"] = buckets
         c4["mfma_faster_from_bucket"] = crossover
