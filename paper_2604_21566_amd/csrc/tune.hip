@@ -182,36 +182,67 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
     Tuning &t = ctx->tune;
     std::string log;
 
-    // 1) add/sub tile shapes: independent tiles (64-limb pairs) and chained tiles
-    //    (one operand pair spanning the whole array)
+    // 1) add/sub tile shapes: independent tiles (64-limb pairs) and chained tiles (one
+    //    operand pair spanning the whole array).  Chained shapes are scored on random
+    //    operands and on the all-propagate worst case (all-ones + 1: the carry crosses
+    //    every tile), by the sum of times relative to each input's best shape.
     const int shapes[][2] = {{1, 1}, {1, 2}, {2, 1}, {4, 1}, {8, 1}, {8, 2}, {2, 8}, {4, 4}, {4, 8}, {8, 4}};
-    for (int mode = 0; mode < 2; ++mode) {
+    constexpr int NS = sizeof shapes / sizeof shapes[0];
+    {
         float best = 1e30f;
         int bw = 1, br = 1;
         for (auto &sh : shapes) {
-            if (mode == 0) {
-                t.batch_waves = sh[0];
-                t.batch_rows = sh[1];
-            } else {
-                t.chain_waves = sh[0];
-                t.chain_rows = sh[1];
-            }
-            const u64 n = mode == 0 ? 64 : NBIG;
-            const float ms =
-                time_ms([&] { launch_flat_scan(ctx, false, r, a, b, n, NBIG / n, nullptr, nullptr); });
+            t.batch_waves = sh[0];
+            t.batch_rows = sh[1];
+            const float ms = time_ms([&] { launch_flat_scan(ctx, false, r, a, b, 64, NBIG / 64, nullptr, nullptr); });
             if (ms < best) {
                 best = ms;
                 bw = sh[0];
                 br = sh[1];
             }
         }
-        if (mode == 0) {
-            t.batch_waves = bw;
-            t.batch_rows = br;
-        } else {
-            t.chain_waves = bw;
-            t.chain_rows = br;
+        t.batch_waves = bw;
+        t.batch_rows = br;
+    }
+    {
+        u64 *wa = nullptr, *wb = nullptr;
+        if (hipMalloc(&wa, NBIG * 8) != hipSuccess || hipMalloc(&wb, NBIG * 8) != hipSuccess) {
+            (void)hipFree(wa);
+            (void)hipFree(wb);
+            (void)hipFree(a);
+            (void)hipFree(b);
+            (void)hipFree(r);
+            (void)hipSetDevice(prev);
+            return BN_ENOMEM;
         }
+        (void)launch_fill_u64(wa, NBIG, ~0ull, nullptr);
+        (void)launch_fill_u64(wb, NBIG, 0ull, nullptr);
+        (void)launch_fill_u64(wb, 1, 1ull, nullptr);
+        float tms[2][NS] = {};
+        for (int in = 0; in < 2; ++in)
+            for (int k = 0; k < NS; ++k) {
+                t.chain_waves = shapes[k][0];
+                t.chain_rows = shapes[k][1];
+                tms[in][k] = time_ms(
+                    [&] { launch_flat_scan(ctx, false, r, in ? wa : a, in ? wb : b, NBIG, 1, nullptr, nullptr); });
+            }
+        (void)hipDeviceSynchronize();
+        (void)hipFree(wa);
+        (void)hipFree(wb);
+        float best[2] = {1e30f, 1e30f};
+        for (int in = 0; in < 2; ++in)
+            for (int k = 0; k < NS; ++k) best[in] = std::min(best[in], tms[in][k]);
+        int bk = 0;
+        float bscore = 1e30f;
+        for (int k = 0; k < NS; ++k) {
+            const float score = tms[0][k] / best[0] + tms[1][k] / best[1];
+            if (score < bscore) {
+                bscore = score;
+                bk = k;
+            }
+        }
+        t.chain_waves = shapes[bk][0];
+        t.chain_rows = shapes[bk][1];
     }
 
     // 2) mad vs MFMA crossovers: square products, equal total work per size; products
@@ -239,7 +270,7 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
 
     // 3) staging window of the large MFMA kernel: by size (0) or one fixed window, on
     // 64 products of 16384 limbs and 576 of 4096 limbs (the bottom of two Karatsuba
-    // levels on C5), candidates interleaved over three rounds; the winner has the lowest
+    // levels on C5), candidates interleaved over five rounds; the winner has the lowest
     // sum of times relative to the best time of each shape, and a fixed window replaces
     // the size rule only when it is better by more than 1% (the noise of this sweep)
     {
@@ -247,14 +278,19 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         constexpr int NC = sizeof cand / sizeof cand[0];
         const u64 shape[2][2] = {{16384, 64}, {4096, 576}};
         float tms[2][NC] = {};
-        constexpr int ROUNDS = 3;
+        // (the first timing after a change of shape ran a few percent slow: an untimed
+        // launch goes first, and the candidates' order rotates from round to round)
+        constexpr int ROUNDS = NC;
         for (int round = 0; round < ROUNDS; ++round)
-            for (int sh = 0; sh < 2; ++sh)
-                for (int c = 0; c < NC; ++c) {
+            for (int sh = 0; sh < 2; ++sh) {
+                const u64 n = shape[sh][0], np = shape[sh][1];
+                (void)launch_mul_batch(ctx, r, a, b, n, n, np, BN_MUL_MFMA, nullptr);
+                for (int k = 0; k < NC; ++k) {
+                    const int c = (k + round) % NC;
                     t.mfma_chunk = cand[c];
-                    const u64 n = shape[sh][0], np = shape[sh][1];
-                    tms[sh][c] += time_ms([&] { launch_mul_batch(ctx, r, a, b, n, n, np, BN_MUL_MFMA, nullptr); }, 5);
+                    tms[sh][c] += time_ms([&] { launch_mul_batch(ctx, r, a, b, n, n, np, BN_MUL_MFMA, nullptr); }, 3);
                 }
+            }
         float best[2] = {1e30f, 1e30f};
         for (int sh = 0; sh < 2; ++sh)
             for (int c = 0; c < NC; ++c) best[sh] = std::min(best[sh], tms[sh][c]);
