@@ -473,6 +473,7 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
             kar[f"levels{levels}_limb_products_per_s"] = 64.0 * n5 * n5 / (ms * 1e-3)
         best = min((1, 2, 3), key=lambda l: kar[f"levels{l}_ms"])
         kar["best_levels"] = best
+        kar["auto_levels"] = bn.bn_karatsuba_auto_levels(n5, bn.bn_get_param(ctx, "mul.karatsuba_limbs"))
         kar["best_over_schoolbook_mfma"] = c5["mfma_ms"] / kar[f"levels{best}_ms"]
         c5["karatsuba_mfma"] = kar
         res["c5"] = c5

@@ -175,13 +175,22 @@ bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
  * into 3N of m/2 limbs; the bottom level is one bn_mul_n_batch-style launch, the
  * splits and combines are batched add/sub passes.  Pair p: a + p*n, b + p*n, product
  * at r + 2*p*n (exactly 2n limbs).  levels = 0 is bn_mul_n_batch; n must be a
- * multiple of 2^levels and levels <= BN_KARATSUBA_MAX_LEVELS (else BN_EINVAL).  r may
+ * multiple of 2^levels and levels <= BN_KARATSUBA_MAX_LEVELS (else BN_EINVAL).
+ * levels = BN_KARATSUBA_AUTO picks bn_karatsuba_auto_levels(n, "mul.karatsuba_limbs"),
+ * the libraries' size threshold for the recursion (App. A) applied per level.  r may
  * overlap a or b (in place, as for bn_mul).  The context keeps a workspace of about
  * 100 n npairs (3/2)^levels bytes across calls (grown with a device synchronisation;
  * BN_ECAPTURE while a stream capture is active and it would have to grow). */
 #define BN_KARATSUBA_MAX_LEVELS 8
+#define BN_KARATSUBA_AUTO (-1)
 bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
                                    size_t npairs, int levels, int form, bn_stream stream);
+
+/* Karatsuba levels that BN_KARATSUBA_AUTO uses for n-limb operands: one more level
+ * while the halves would keep at least min_half_limbs limbs, n stays divisible by 2 per
+ * level and the count stays within BN_KARATSUBA_MAX_LEVELS (0 when n < 2 min_half_limbs).
+ * Pure host function (no device, no context). */
+int bn_karatsuba_auto_levels(size_t n, size_t min_half_limbs);
 
 /* ------------------------------------------------- ragged batches + plans ---- */
 
@@ -252,6 +261,8 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *                                      share a CU), or 0 (default): by size, 256 for unsplit
  *                                      launches whose shorter operand has >= 10240 limbs,
  *                                      224 otherwise
+ *   "mul.karatsuba_limbs"              BN_KARATSUBA_AUTO splits while the halves keep at
+ *                                      least this many limbs (default 4096, >= 1)
  *   "mul.mfma_rows"                    Toeplitz rows per column block of the large MFMA
  *                                      kernel, in groups of 64: 1 or 2 (default 2: the same
  *                                      LDS reads feed twice the MFMAs)

@@ -32,6 +32,8 @@ BN_ECAPTURE = -7
 BN_MUL_AUTO = 0
 BN_MUL_MAD = 1
 BN_MUL_MFMA = 2
+BN_KARATSUBA_AUTO = -1
+BN_KARATSUBA_MAX_LEVELS = 8
 
 FORMS = {"auto": BN_MUL_AUTO, "mad": BN_MUL_MAD, "mfma": BN_MUL_MFMA}
 
@@ -77,6 +79,7 @@ _PROTOS = {
     "bn_mul": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _i, _vp]),
     "bn_mul_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _sz, _i, _vp]),
     "bn_mul_karatsuba_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _i, _i, _vp]),
+    "bn_karatsuba_auto_levels": (_i, [_sz, _sz]),
     "bn_plan_mul_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, _i, ctypes.POINTER(_vp)]),
     "bn_plan_add_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, ctypes.POINTER(_vp)]),
     "bn_plan_destroy": (_i, [_vp]),
@@ -310,6 +313,11 @@ def bn_mul_karatsuba_n_batch(ctx, r, a, b, n: int, npairs: int, levels: int, for
     _ck(lib().bn_mul_karatsuba_n_batch(ctx, _ptr(r, "r", 2 * n * npairs), _ptr(a, "a", n * npairs),
                                        _ptr(b, "b", n * npairs), n, npairs, int(levels),
                                        _form(form), _stream(stream)), "bn_mul_karatsuba_n_batch")
+
+
+def bn_karatsuba_auto_levels(n: int, min_half_limbs: int) -> int:
+    """Levels BN_KARATSUBA_AUTO uses for n-limb operands (host only)."""
+    return lib().bn_karatsuba_auto_levels(n, min_half_limbs)
 
 
 # ------------------------------------------------------------------ ragged ----

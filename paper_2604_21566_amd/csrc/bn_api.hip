@@ -331,10 +331,22 @@ bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
                       [&](u64 *out) { return launch_mul_batch(ctx, out, a, b, na, nb, npairs, form, S(stream)); });
 }
 
+int bn_karatsuba_auto_levels(size_t n, size_t min_half_limbs) {
+    if (min_half_limbs == 0) min_half_limbs = 1;
+    int levels = 0;
+    size_t m = n;
+    while (levels < BN_KARATSUBA_MAX_LEVELS && m % 2 == 0 && m / 2 >= min_half_limbs) {
+        m /= 2;
+        ++levels;
+    }
+    return levels;
+}
+
 bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
                                    size_t npairs, int levels, int form, bn_stream stream) {
     bn_status st = mul_args(ctx, r, a, b, n, n, npairs, form);
     if (st != BN_OK) return st;
+    if (levels == BN_KARATSUBA_AUTO) levels = bn_karatsuba_auto_levels(n, (size_t)ctx->tune.karatsuba_limbs);
     if (levels < 0 || levels > BN_KARATSUBA_MAX_LEVELS) return BN_EINVAL;
     if (n && (n % ((size_t)1 << levels))) return BN_EINVAL;
     DeviceGuard g(ctx->device);
@@ -445,7 +457,8 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 // ------------------------------------------------------------------ params ----
 static const char *kParamNames =
     "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,"
-    "mul.crossover_limbs,mul.small_crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,lookback.spin_limit,debug.flags";
+    "mul.crossover_limbs,mul.small_crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,mul.karatsuba_limbs,"
+    "lookback.spin_limit,debug.flags";
 
 const char *bn_param_names(void) { return kParamNames; }
 
@@ -477,6 +490,9 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
     } else if (k == "mul.mfma_chunk") {
         if (v != 0 && (v < 16 || v > 256 || (v & 1))) return BN_EINVAL;  // even (steps run in pairs); staging registers
         t.mfma_chunk = (int)v;
+    } else if (k == "mul.karatsuba_limbs") {
+        if (v < 1) return BN_EINVAL;
+        t.karatsuba_limbs = v;
     } else if (k == "mul.mfma_rows") {
         if (v != 1 && v != 2) return BN_EINVAL;
         t.mfma_rows = (int)v;
@@ -505,6 +521,7 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "mul.mad_xchunk") *v = t.mad_xchunk;
     else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;
     else if (k == "mul.mfma_rows") *v = t.mfma_rows;
+    else if (k == "mul.karatsuba_limbs") *v = t.karatsuba_limbs;
     else if (k == "lookback.spin_limit") *v = t.spin_limit;
     else if (k == "debug.flags") *v = t.debug_flags;
     else return BN_EINVAL;

@@ -55,6 +55,7 @@ struct Tuning {
                                        // workgroups of the large MFMA kernel fit a CU up to 234);
                                        // 0: by size (mfma_window in k_mul.hip)
     int mfma_rows = 2;                 // Toeplitz row groups of 64 per column block (1 or 2)
+    i64 karatsuba_limbs = 4096;        // BN_KARATSUBA_AUTO: smallest half that is split again
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
                                        // bit 1: record look-back distances in ScanCtl::hist

@@ -88,3 +88,16 @@ def test_product_path_fails_loudly_when_library_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(bn, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(bn.BnLibraryMissing):
         bn.lib()
+
+
+def test_karatsuba_auto_levels(bn):
+    """BN_KARATSUBA_AUTO's level rule: split while the halves keep min_half_limbs limbs,
+    n stays even per level, at most BN_KARATSUBA_MAX_LEVELS levels."""
+    f = bn.bn_karatsuba_auto_levels
+    assert f(16384, 4096) == 2          # C5: 8192, 4096
+    assert f(16384, 4097) == 1
+    assert f(8191, 1) == 0              # odd: no split
+    assert f(12000, 1000) == 3          # 6000, 3000, 1500 (750 < 1000)
+    assert f(12000, 1) == 5             # 6000, 3000, 1500, 750, 375 (odd)
+    assert f(1 << 20, 1) == bn.BN_KARATSUBA_MAX_LEVELS
+    assert f(0, 4096) == 0 and f(1, 0) == 0 and f(2, 0) == 1

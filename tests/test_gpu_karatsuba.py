@@ -72,6 +72,22 @@ def test_signs_and_carries(bnctx, form, levels):
     _check(bnctx, pa.reshape(-1), pb.reshape(-1), n, pa.shape[0], levels, form)
 
 
+@pytest.mark.parametrize("n,min_half,levels", [(2048, 4096, 0), (4096, 2048, 1), (12000, 1000, 3)])
+def test_auto_levels(bnctx, n, min_half, levels):
+    """levels = BN_KARATSUBA_AUTO splits while the halves keep mul.karatsuba_limbs limbs:
+    the same product as the schoolbook oracle, and the level count the rule gives."""
+    assert bn.bn_karatsuba_auto_levels(n, min_half) == levels
+    old = bn.bn_get_param(bnctx, "mul.karatsuba_limbs")
+    bn.bn_set_param(bnctx, "mul.karatsuba_limbs", min_half)
+    try:
+        g = np.random.default_rng(n + levels)
+        a = g.integers(0, MAX, n * 2, dtype=np.uint64, endpoint=True)
+        b = g.integers(0, MAX, n * 2, dtype=np.uint64, endpoint=True)
+        _check(bnctx, a, b, n, 2, bn.BN_KARATSUBA_AUTO, "mfma")
+    finally:
+        bn.bn_set_param(bnctx, "mul.karatsuba_limbs", old)
+
+
 @pytest.mark.parametrize("n", [12288, 12000])
 def test_sign_pieces(bnctx, n):
     """Halves that differ in one limb only, at the ends and the boundaries of the
