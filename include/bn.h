@@ -205,14 +205,16 @@ typedef struct bn_plan bn_plan;
 /* Build a plan for a ragged multiply batch from a HOST copy of the descriptors:
  * validates sizes (1 <= na, nb <= 2^20), sorts the pairs by work (na*nb,
  * largest first), picks mad or MFMA per pair (form, or the tuned crossover for
- * BN_MUL_AUTO), and uploads the work list to device memory it owns.
+ * BN_MUL_AUTO; automatic products of 129-256 limbs take MFMA), and uploads the work
+ * list to device memory it owns.
  * Synchronous (allocates).  Product ranges must not overlap each other or the inputs. */
 bn_status bn_plan_mul_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, int form,
                              bn_plan **plan);
 bn_status bn_plan_destroy(bn_plan *plan);
 
-/* Run a planned ragged multiply: one persistent launch per form (mad, MFMA); wave k
- * of W resident waves takes pairs k, k+W, ... of the work-sorted list.  Pairs with
+/* Run a planned ragged multiply: one persistent launch (both forms in one kernel when
+ * the plan has both); wave k of W resident waves takes pairs k, k+W, ... of the
+ * work-sorted list.  Pairs with
  * na + nb > 256 run through the batched path, one call each.  No allocation
  * (beyond the batched path's workspace, reserved by graph capture), no host sync. */
 bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,

@@ -60,10 +60,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // Both forms in one persistent launch (a batch with mad and MFMA items): the item's
 // form picks the path, wave-uniformly.  One launch instead of two back to back lets
 // the waves that finish their share of one form go on with the other, so the two
-// tails overlap.  Without a bound the two paths' registers add up to four waves per
-// SIMD.  Capped at six waves (80 registers) a few values spill (80 bytes per lane)
-// and C4 runs 3% faster than at five without spills; at seven the spills cost 3.5x.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_mul_ragged_mixed(const RItem *__restrict__ items, u32 nitems,
+// tails overlap.  The mad path takes products of at most 128 limbs (the plan gives
+// automatic items of 129-256 limbs the MFMA form): without the four-step mad path the
+// kernel fits 64 registers and runs at eight waves per SIMD without spills (with it:
+// six waves and 80 bytes per lane spilled; C4 7% slower).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_mul_ragged_mixed(const RItem *__restrict__ items, u32 nitems,
                                                           u64 *__restrict__ r, const u64 *__restrict__ a,
                                                           const u64 *__restrict__ b) {
     __shared__ u64 lds[4 * RAGGED_LDS_U64];
@@ -74,17 +75,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
         const u64 *pa = a + m.a_off;
         const u64 *pb = b + m.b_off;
         u64 *pr = r + m.r_off;
-        if (m.form == BN_MUL_MFMA) {
+        const u32 P = m.na + m.nb;
+        if (m.form == BN_MUL_MFMA || P > 128) {  // (the plan leaves no mad item above 128 limbs here)
             mul_item_mfma_small<2>(pa, m.na, pb, m.nb, pr, lds + w * RAGGED_LDS_U64);
             wave_sync();
+        } else if (P <= 64) {
+            mul_item_mad<1>(pa, m.na, pb, m.nb, pr);
         } else {
-            const u32 P = m.na + m.nb;
-            if (P <= 64)
-                mul_item_mad<1>(pa, m.na, pb, m.nb, pr);
-            else if (P <= 128)
-                mul_item_mad<2>(pa, m.na, pb, m.nb, pr);
-            else
-                mul_item_mad<4>(pa, m.na, pb, m.nb, pr);
+            mul_item_mad<2>(pa, m.na, pb, m.nb, pr);
         }
     }
 }
@@ -178,6 +176,9 @@ bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int 
         }
         RItem it{p.a_off, p.b_off, p.r_off, p.na, p.nb, 0, (u32)i};
         it.form = (u32)mul_pick_form(ctx, p.na, p.nb, form);
+        // automatic one-wave items of 129-256 limbs take the MFMA form: the kernel that
+        // runs both forms in one launch has no mad path for them (see k_mul_ragged_mixed)
+        if (form == BN_MUL_AUTO && (u64)p.na + p.nb > 128 && (u64)p.na + p.nb <= 256) it.form = BN_MUL_MFMA;
         (it.form == BN_MUL_MFMA ? pl->nmfma : pl->nmad)++;
         pl->work += (u64)p.na * p.nb;
         if ((u64)p.na + p.nb <= 256)
