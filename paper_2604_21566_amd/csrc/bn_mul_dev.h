@@ -119,14 +119,17 @@ __device__ void mul_item_mad(const u64 *__restrict__ a, u32 na, const u64 *__res
         lo[q] = 0;
         hi[q] = 0;
     }
-    // 64 digits of a per coalesced load; each step broadcasts one of them (readlane).
-    // Steps past nx multiply by a zero digit, so they only cost time.
-    for (u32 xb = 0; xb < nx; xb += 64) {
-        const u32 areg = (xb + lane < nx) ? a32[xb + lane] : 0u;
-        for (u32 s0 = 0; s0 < 64 && xb + s0 < nx; s0 += 2 * Q) {
+    // The digits of a are the same for every lane: scalar loads, 2 Q per group of steps
+    // (a group past nx reads no memory beyond the operand; its missing digits are 0 and
+    // their steps only cost time).
+    {
+        for (u32 s0 = 0; s0 < nx; s0 += 2 * Q) {
+            u32 ad[2 * Q];
+#pragma unroll
+            for (int s = 0; s < 2 * Q; ++s) ad[s] = s0 + s < nx ? a32[s0 + s] : 0u;
 #pragma unroll
             for (int s = 0; s < 2 * Q; ++s) {
-                const u32 al = lane_value(areg, s0 + s);
+                const u32 al = ad[s];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) mac96(lo[q], hi[q], al, R[(q - s + 2 * Q) % Q]);
                 const int k = (Q - 1 - s + 2 * Q) % Q;
