@@ -207,6 +207,7 @@ typedef struct bn_plan bn_plan;
  * largest first), picks mad or MFMA per pair (form, or the tuned crossover for
  * BN_MUL_AUTO; automatic products of 129-256 limbs take MFMA), and uploads the work
  * list to device memory it owns.
+ * Offsets plus lengths must stay below 2^60 limbs (else BN_ERANGE).
  * Synchronous (allocates).  Product ranges must not overlap each other or the inputs. */
 bn_status bn_plan_mul_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, int form,
                              bn_plan **plan);
@@ -216,7 +217,8 @@ bn_status bn_plan_destroy(bn_plan *plan);
  * the plan has both); wave k of W resident waves takes pairs k, k+W, ... of the
  * work-sorted list.  Pairs with
  * na + nb > 256 run through the batched path, one call each.  No allocation
- * (beyond the batched path's workspace, reserved by graph capture), no host sync. */
+ * (beyond the batched path's workspace, reserved by graph capture), no host sync.
+ * BN_EINVAL for a plan of another kind or one built on a context of another device. */
 bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
                         const uint64_t *b_pool, bn_stream stream);
 

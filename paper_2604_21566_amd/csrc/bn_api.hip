@@ -32,8 +32,9 @@ bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s) {
         buf.ptr = nullptr;
         return BN_ENOMEM;
     }
-    // status words must start below every epoch in use (epoch >= 1)
-    if (hipMemset(buf.ptr, 0, want) != hipSuccess) return BN_EHIP;
+    // status words must start below every epoch in use (epoch >= 1); the clear runs on
+    // the null stream, so wait for it before a kernel on a non-blocking stream reads them
+    if (hipMemset(buf.ptr, 0, want) != hipSuccess || hipDeviceSynchronize() != hipSuccess) return BN_EHIP;
     buf.bytes = want;
     return BN_OK;
 }
@@ -380,7 +381,7 @@ bn_status bn_plan_destroy(bn_plan *plan) {
 
 bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
                         const uint64_t *b_pool, bn_stream stream) {
-    if (!ctx || !plan || plan->op != 0) return BN_EINVAL;
+    if (!ctx || !plan || plan->op != 0 || plan->device != ctx->device) return BN_EINVAL;
     if (plan->npairs && (!r_pool || !a_pool || !b_pool)) return BN_EINVAL;
     if (((uintptr_t)r_pool | (uintptr_t)a_pool | (uintptr_t)b_pool) & 7u) return BN_EINVAL;
     DeviceGuard g(ctx->device);
@@ -389,7 +390,7 @@ bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, cons
 
 bn_status bn_add_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
                         const uint64_t *b_pool, uint64_t *carry_out, bn_stream stream) {
-    if (!ctx || !plan || plan->op != 1) return BN_EINVAL;
+    if (!ctx || !plan || plan->op != 1 || plan->device != ctx->device) return BN_EINVAL;
     if (plan->npairs && (!r_pool || !a_pool || !b_pool)) return BN_EINVAL;
     if (((uintptr_t)r_pool | (uintptr_t)a_pool | (uintptr_t)b_pool | (uintptr_t)carry_out) & 7u) return BN_EINVAL;
     DeviceGuard g(ctx->device);
@@ -401,7 +402,7 @@ static bn_status capture(bn_stream stream, bn_graph **out, const std::function<b
 
 bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
                                       const uint64_t *b_pool, bn_stream stream, bn_graph **graph) {
-    if (!ctx || !plan || !graph || !stream) return BN_EINVAL;
+    if (!ctx || !plan || !graph || !stream || plan->op != 0 || plan->device != ctx->device) return BN_EINVAL;
     DeviceGuard g(ctx->device);
     // large items use the batched pipeline: reserve its workspace before capture
     size_t need = 0, status = 0;

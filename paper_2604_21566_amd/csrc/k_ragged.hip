@@ -147,6 +147,10 @@ u32 persistent_blocks(const bn_ctx *ctx, u32 nitems) {
     return std::max<u32>(1, std::min(want, need));
 }
 
+// a range of n limbs at limb offset off stays below 2^60 limbs (2^63 bytes), so the
+// kernels' byte addresses cannot wrap
+bool span_ok(u64 off, u64 n) { return off <= (1ull << 60) - n; }
+
 bn_status upload_plan(bn_ctx *ctx, bn_plan *pl, std::vector<RItem> &small) {
     pl->nsmall = (u32)small.size();
     if (hipSetDevice(ctx->device) != hipSuccess) return BN_EHIP;
@@ -170,7 +174,8 @@ bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int 
     small.reserve(npairs);
     for (size_t i = 0; i < npairs; ++i) {
         const bn_pair &p = pairs[i];
-        if (p.na == 0 || p.nb == 0 || p.na > (1u << 20) || p.nb > (1u << 20)) {
+        if (p.na == 0 || p.nb == 0 || p.na > (1u << 20) || p.nb > (1u << 20) || !span_ok(p.a_off, p.na) ||
+            !span_ok(p.b_off, p.nb) || !span_ok(p.r_off, (u64)p.na + p.nb)) {
             delete pl;
             return BN_ERANGE;
         }
@@ -211,7 +216,7 @@ bn_status plan_add_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, bn_p
     items.reserve(npairs);
     for (size_t i = 0; i < npairs; ++i) {
         const bn_pair &p = pairs[i];
-        if ((u64)p.na > BN_MAX_LIMBS) {
+        if ((u64)p.na > BN_MAX_LIMBS || !span_ok(p.a_off, p.na) || !span_ok(p.b_off, p.na) || !span_ok(p.r_off, p.na)) {
             delete pl;
             return BN_ERANGE;
         }

@@ -239,6 +239,26 @@ def test_ragged_add(bnctx):
         bn.bn_plan_destroy(plan)
 
 
+def test_ragged_plan_offset_range(bnctx):
+    """Descriptors whose offset plus length would pass 2^60 limbs are refused at plan time."""
+    announce("ragged plan offset range")
+    top = (1 << 60) - 8
+    for bad in ((top, 0, 0, 9, 4), (0, top, 0, 4, 9), (0, 0, top, 4, 5), ((1 << 64) - 1, 0, 0, 1, 1)):
+        desc = np.array([(0, 0, 0, 4, 4), bad], np.uint64)
+        with pytest.raises(bn.BnError) as e:
+            bn.bn_plan_mul_ragged(bnctx, desc)
+        assert e.value.status == bn.BN_ERANGE, bad
+        add = desc.copy()   # one length n for a, b and r
+        add[1, 3] = add[1, 4] = 9 if top in bad else 1
+        with pytest.raises(bn.BnError) as e:
+            bn.bn_plan_add_ragged(bnctx, add)
+        assert e.value.status == bn.BN_ERANGE, bad
+    # the largest offsets that still fit are accepted (nothing is launched)
+    ok = np.array([(top, top, top - 8, 8, 8)], np.uint64)
+    for plan in (bn.bn_plan_mul_ragged(bnctx, ok), bn.bn_plan_add_ragged(bnctx, ok)):
+        bn.bn_plan_destroy(plan)
+
+
 def test_mul_errors(bnctx):
     announce("mul argument errors")
     t = torch.zeros(64, dtype=torch.int64, device="cuda")
