@@ -300,7 +300,9 @@ bn_status bn_autotune(bn_ctx *ctx, const char *out_json);
  * BN_ENOMEM, or BN_EHIP. */
 bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mfma_i8_ops_per_s, double *copy_bytes_per_s);
 
-/* Load parameters written by bn_autotune (flat JSON object of "key": integer). */
+/* Load parameters written by bn_autotune (flat JSON object of "key": integer; keys
+ * without a dot and non-integer values are skipped).  All or nothing: BN_EINVAL for an
+ * unreadable file, a malformed entry or a rejected value, and then no setting changes. */
 bn_status bn_load_tuning(bn_ctx *ctx, const char *json_path);
 
 /* Library version string. */

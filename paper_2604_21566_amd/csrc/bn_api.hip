@@ -529,8 +529,18 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     return BN_OK;
 }
 
+static bn_status load_tuning(bn_ctx *ctx, const char *path);
+
 bn_status bn_load_tuning(bn_ctx *ctx, const char *path) {
     if (!ctx || !path) return BN_EINVAL;
+    // all or nothing: a file with a bad entry leaves the settings as they were
+    const Tuning saved = ctx->tune;
+    const bn_status st = load_tuning(ctx, path);
+    if (st != BN_OK) ctx->tune = saved;
+    return st;
+}
+
+static bn_status load_tuning(bn_ctx *ctx, const char *path) {
     FILE *f = fopen(path, "rb");
     if (!f) return BN_EINVAL;
     std::string s;

@@ -66,3 +66,29 @@ def test_probe_rates_are_plausible(bnctx):
     assert 1e12 < mac < 4.0e13, mac
     assert 5e14 < mfma < 5.5e15, mfma
     assert 1e12 < copy < 8.0e12, copy  # HBM3E: 8 TB/s published
+
+
+def test_load_tuning_all_or_nothing(tmp_path):
+    """A table with a rejected value changes nothing, also the entries before it;
+    a good table applies every entry."""
+    announce("load tuning: all or nothing")
+    ctx = bn.bn_create(0)
+    try:
+        before = {k: bn.bn_get_param(ctx, k) for k in KEYS}
+        bad = tmp_path / "bad.json"
+        bad.write_text(json.dumps({"device": "gfx950", "mul.crossover_limbs": before["mul.crossover_limbs"] + 1,
+                                   "mul.mfma_rows": 3}))   # 1 or 2 only
+        with pytest.raises(bn.BnError) as e:
+            bn.bn_load_tuning(ctx, str(bad))
+        assert e.value.status == bn.BN_EINVAL
+        assert {k: bn.bn_get_param(ctx, k) for k in KEYS} == before
+        with pytest.raises(bn.BnError):
+            bn.bn_load_tuning(ctx, str(tmp_path / "missing.json"))
+        good = tmp_path / "good.json"
+        good.write_text(json.dumps({"device": "gfx950", "mul.crossover_limbs": before["mul.crossover_limbs"] + 1,
+                                    "mul.mfma_rows": 1}))
+        bn.bn_load_tuning(ctx, str(good))
+        assert bn.bn_get_param(ctx, "mul.crossover_limbs") == before["mul.crossover_limbs"] + 1
+        assert bn.bn_get_param(ctx, "mul.mfma_rows") == 1
+    finally:
+        bn.bn_destroy(ctx)
