@@ -232,6 +232,12 @@ bn_status bn_add_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, cons
 
 typedef struct bn_graph bn_graph;
 
+/* A graph addresses its context's workspace and, for ragged calls, the plan's work
+ * list: destroy graphs before their context and plan.  Once a context has captured a
+ * graph, a buffer that later calls outgrow is kept (not freed) until bn_destroy, so
+ * replays stay valid after eager calls of any size; replays and eager calls on one
+ * context share the workspace and must not overlap in time (one stream, or ordered). */
+
 /* Capture one bn_mul_ragged call into an instantiated HIP graph (pointers are baked in).
  * The workspace must already be large enough (it is reserved here, before capture). */
 bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool,

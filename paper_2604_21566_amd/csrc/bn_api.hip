@@ -24,7 +24,11 @@ bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s) {
     want = (want + 65535) & ~(size_t)65535;
     if (buf.ptr) {
         if (hipDeviceSynchronize() != hipSuccess) return BN_EHIP;
-        (void)hipFree(buf.ptr);
+        // a captured graph may still address the old buffer: keep it until bn_destroy
+        if (ctx->captured)
+            ctx->retired.push_back(buf.ptr);
+        else
+            (void)hipFree(buf.ptr);
         buf.ptr = nullptr;
         buf.bytes = 0;
     }
@@ -123,6 +127,7 @@ bn_status bn_destroy(bn_ctx *ctx) {
     if (ctx->kwork.ptr) (void)hipFree(ctx->kwork.ptr);
     if (ctx->mstage.ptr) (void)hipFree(ctx->mstage.ptr);
     if (ctx->ctl) (void)hipFree(ctx->ctl);
+    for (void *p : ctx->retired) (void)hipFree(p);
     delete ctx;
     return BN_OK;
 }
@@ -413,6 +418,7 @@ bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t
     bn_status st;
     if ((st = bn_ensure(ctx, ctx->work, need, nullptr)) != BN_OK) return st;
     if ((st = bn_ensure(ctx, ctx->status, status, nullptr)) != BN_OK) return st;
+    ctx->captured = true;
     return capture(stream, graph, [&]() { return bn_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, stream); });
 }
 
@@ -431,11 +437,13 @@ bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_
             return st;
         if ((st = bn_ensure(ctx, ctx->status, mul_status_bytes(ctx, na, nb, npairs, form), nullptr)) != BN_OK)
             return st;
+        ctx->captured = true;
         return capture(stream, graph,
                        [&]() { return bn_mul_n_batch(ctx, r, a, b, na, nb, npairs, form, stream); });
     }
     if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)na, (u64)na * npairs), nullptr)) != BN_OK)
         return st;
+    ctx->captured = true;
     return capture(stream, graph, [&]() {
         return op == 0 ? bn_add_n_batch(ctx, r, a, b, na, npairs, carry_out, stream)
                        : bn_sub_n_batch(ctx, r, a, b, na, npairs, carry_out, stream);

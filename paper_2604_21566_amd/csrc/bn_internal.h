@@ -77,6 +77,8 @@ struct bn_ctx {
     DevBuf mstage;              // products computed in place: staged here, then copied
     u64 host_epoch = 1ull << 61;  // epochs of chained scans launched outside a capture
     Tuning tune;
+    bool captured = false;        // a graph has baked in buffer addresses of this context
+    std::vector<void *> retired;  // buffers replaced after a capture, freed by bn_destroy
 };
 
 // One pair of a ragged batch as the device sees it.

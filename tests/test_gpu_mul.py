@@ -346,3 +346,54 @@ def test_many_large_pairs(bnctx, form):
     na, nb, npairs = 150, 131, 70000
     g = np.random.default_rng(7)
     _check(bnctx, _rand(g, na * npairs), _rand(g, nb * npairs), na, nb, npairs, form)
+
+
+@pytest.mark.parametrize("form", ["mfma", "mad"])
+def test_graph_survives_workspace_growth(form):
+    """A captured product keeps its buffers when later eager calls outgrow them: on a
+    fresh context, capture a product on the workspace path (plus one computed in place,
+    which goes through the staging buffer), grow the workspace, the status array and
+    the staging buffer twice with much larger eager products, and replay after each."""
+    na, nb, npairs = 700, 600, 3
+    announce("graph after workspace growth", form, f"na={na}", f"nb={nb}", f"npairs={npairs}")
+    fcode = bn.BN_MUL_MFMA if form == "mfma" else bn.BN_MUL_MAD
+    g0 = np.random.default_rng(12)
+    a, b = _rand(g0, na * npairs), _rand(g0, nb * npairs)
+    want = oracle.mul_batch(a, b, na, nb, npairs)
+    R = (na + nb) * npairs
+    ctx = bn.bn_create(0)
+    try:
+        assert bn.bn_workspace_size(ctx, 2, 8192, 8192, 4, fcode) > 2 * bn.bn_workspace_size(ctx, 2, na, nb, npairs, fcode)
+        s = torch.cuda.Stream()
+        ta, tb = D(a), D(b)
+        tr = torch.empty(R, dtype=torch.int64, device="cuda")
+        buf = torch.zeros(R + nb * npairs, dtype=torch.int64, device="cuda")   # r over a, b behind
+        ri, ai, bi = buf[:R], buf[:na * npairs], buf[R:]
+        g = bn.bn_graph_capture_batch(ctx, 2, tr, ta, tb, na, nb, npairs, None, form, stream=s)
+        gi = bn.bn_graph_capture_batch(ctx, 2, ri, ai, bi, na, nb, npairs, None, form, stream=s)
+        try:
+            for big in (8192, 16384):
+                x = D(_rand(g0, big * 4))
+                xr = torch.empty(2 * big * 4, dtype=torch.int64, device="cuda")
+                bn.bn_mul_n_batch(ctx, xr, x, x, big, big, 4, form)                        # grows work, status
+                xs = torch.zeros(2 * big * 4, dtype=torch.int64, device="cuda")
+                xs[:big * 4].copy_(x)
+                bn.bn_mul_n_batch(ctx, xs, xs[:big * 4], x, big, big, 4, form)            # grows the staging
+                torch.cuda.synchronize()
+                tr.fill_(7)
+                buf.zero_()
+                ai.copy_(ta)
+                bi.copy_(tb)
+                torch.cuda.synchronize()
+                bn.bn_graph_launch(g, s)
+                bn.bn_graph_launch(gi, s)
+                s.synchronize()
+                assert (H(tr) == want).all(), f"replay after growth to {big}"
+                assert (H(ri) == want).all(), f"in-place replay after growth to {big}"
+                del x, xr, xs
+        finally:
+            bn.bn_graph_destroy(g)
+            bn.bn_graph_destroy(gi)
+    finally:
+        torch.cuda.synchronize()
+        bn.bn_destroy(ctx)
