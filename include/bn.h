@@ -23,6 +23,9 @@
  * arguments on the host, enqueues kernels and returns without synchronising.
  * Calls on one context must not overlap in time (they share the workspace):
  * issue them on one stream, or use one context per concurrently used stream.
+ * A context is not thread-safe on the host either (its workspace, epoch counter
+ * and settings change without a lock): one thread at a time per context; separate
+ * contexts may be driven from separate threads.
  *
  * Errors: every entry point returns a bn_status.  Argument errors are detected
  * synchronously and nothing is enqueued.  HIP launch errors map to BN_EHIP.
