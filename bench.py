@@ -52,6 +52,23 @@ def measured_traffic(per_launch_bytes_alg: float):
         return None
 
 
+def ci95(ts) -> float:
+    """Half-width of the 95% confidence interval of the mean of the samples ts
+    (Student t with n - 1 degrees of freedom)."""
+    n = len(ts)
+    if n < 2:
+        return float("nan")
+    try:
+        from scipy.stats import t as student_t
+        q = float(student_t.ppf(0.975, n - 1))
+    except ImportError:
+        q = 1.96
+    return q * float(np.std(ts, ddof=1)) / np.sqrt(n)
+
+
+REPS = 20   # timed repetitions of each secondary workload (mean and 95% CI), after warm-ups
+
+
 def gpu_time(fn, reps: int, warmup: int = 1):
     """Mean and per-rep ms of fn() on torch's current stream (HIP events)."""
     import torch
@@ -93,9 +110,8 @@ def main():
     from paper_2604_21566_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    ctx = bn.bn_create(0)
-    if args.tuning:
-        bn.bn_load_tuning(ctx, args.tuning)
+    # compute calls never allocate: every workload's workspace is reserved before it runs
+    ctx = bn.bn_create(0, tuning=args.tuning)
     D = bn.to_device
     if args.only:
         res = extra_workloads(ctx, bn, wl, torch, only=set(args.only.split(",")))
@@ -113,6 +129,8 @@ def main():
     tr = torch.empty(N, dtype=torch.int64, device="cuda")
     tc = torch.empty(npairs, dtype=torch.int64, device="cuda")
     bytes_per_launch = 24.0 * N + 8.0 * npairs
+
+    bn.bn_reserve_for(ctx, bn.BN_OP_ADDSUB, n, 0, npairs)
 
     def add():
         bn.bn_add_n_batch(ctx, tr, ta, tb, n, npairs, tc)
@@ -363,6 +381,7 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         log("c3")
         c3 = {}
         n3 = 1 << 26
+        bn.bn_reserve_for(ctx, bn.BN_OP_ADDSUB, n3, 0, 1)
         tr = torch.empty(n3, dtype=torch.int64, device="cuda")
         tc = torch.empty(1, dtype=torch.int64, device="cuda")
         for op in ("add", "sub"):
@@ -370,9 +389,11 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
                 a, b = wl.c3(op, n=n3, worst=worst)
                 ta, tb = D(a), D(b)
                 f = bn.bn_add if op == "add" else bn.bn_sub
-                ms, _ = gpu_time(lambda: f(ctx, tr, ta, tb, tc), 10, 2)
+                ms, ts = gpu_time(lambda: f(ctx, tr, ta, tb, tc), REPS, 2)
                 key = f"{op}{'_worst' if worst else ''}"
                 c3[key + "_GBps"] = 24.0 * n3 / (ms * 1e-3) / 1e9
+                c3[key + "_ms"] = ms
+                c3[key + "_ci95_ms"] = ci95(ts)
                 # look-back distances of one more (untimed) run
                 bn.bn_lookback_stats(ctx)
                 bn.bn_set_param(ctx, "debug.flags", 2)
@@ -396,17 +417,19 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
             plan = bn.bn_plan_mul_ragged(ctx, desc, form)
             g = bn.bn_graph_capture_mul_ragged(ctx, plan, tr, ta, tb, s)
             with torch.cuda.stream(s):
-                ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 10, 2)
+                ms, ts = gpu_time(lambda: bn.bn_graph_launch(g, s), REPS, 3)
             bn.bn_graph_destroy(g)
             bn.bn_plan_destroy(plan)
             c4[f"{form}_ms"] = ms
+            c4[f"{form}_ci95_ms"] = ci95(ts)
             c4[f"{form}_limb_products_per_s"] = work / (ms * 1e-3)
             c4[f"{form}_pairs_per_s"] = len(desc) / (ms * 1e-3)
         # the same batch launched directly (no graph)
         plan = bn.bn_plan_mul_ragged(ctx, desc, "auto")
-        ms, _ = gpu_time(lambda: bn.bn_mul_ragged(ctx, plan, tr, ta, tb), 10, 2)
+        ms, ts = gpu_time(lambda: bn.bn_mul_ragged(ctx, plan, tr, ta, tb), REPS, 3)
         bn.bn_plan_destroy(plan)
         c4["auto_direct_ms"] = ms
+        c4["auto_direct_ci95_ms"] = ci95(ts)
         # per size bucket (larger operand length in [lo, 2 lo), the last one [64, 128]: the
         # 128-limb operands alone are a few hundred pairs, too few to time), each bucket
         # its own graph
@@ -423,10 +446,11 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
                     plan = bn.bn_plan_mul_ragged(ctx, sel, form)
                     g = bn.bn_graph_capture_mul_ragged(ctx, plan, tr, ta, tb, s)
                     with torch.cuda.stream(s):
-                        ms, _ = gpu_time(lambda: bn.bn_graph_launch(g, s), 10, 2)
+                        ms, ts = gpu_time(lambda: bn.bn_graph_launch(g, s), REPS, 3)
                     bn.bn_graph_destroy(g)
                     bn.bn_plan_destroy(plan)
                     row[f"{form}_us"] = ms * 1e3
+                    row[f"{form}_ci95_us"] = ci95(ts) * 1e3
                     row[f"{form}_limb_products_per_s"] = w / (ms * 1e-3)
                 # the smallest bucket from which MFMA is faster in every larger bucket
                 if row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"]:
@@ -455,8 +479,10 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         tr = torch.empty(64 * 2 * n5, dtype=torch.int64, device="cuda")
         c5 = {"limb_products": 64.0 * n5 * n5}
         for form in ("mad", "mfma"):
-            ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, tr, ta, tb, n5, n5, 64, form), 3, 1)
+            bn.bn_reserve_for(ctx, bn.BN_OP_MUL, n5, n5, 64, form)
+            ms, ts = gpu_time(lambda: bn.bn_mul_n_batch(ctx, tr, ta, tb, n5, n5, 64, form), REPS, 2)
             c5[f"{form}_ms"] = ms
+            c5[f"{form}_ci95_ms"] = ci95(ts)
             c5[f"{form}_limb_products_per_s"] = 64.0 * n5 * n5 / (ms * 1e-3)
             c5[f"{form}_products_per_s"] = 64 / (ms * 1e-3)
         c5["mfma_int8_TOPS"] = 2 * 64.0 * 64.0 * n5 * n5 / (c5["mfma_ms"] * 1e-3) / 1e12
@@ -468,8 +494,10 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         # stated in schoolbook limb products per second for comparison)
         kar = {}
         for levels in (1, 2, 3):
-            ms, _ = gpu_time(lambda: bn.bn_mul_karatsuba_n_batch(ctx, tr, ta, tb, n5, 64, levels, "mfma"), 3, 1)
+            bn.bn_reserve_for(ctx, bn.BN_OP_MUL_KARATSUBA, n5, n5, 64, "mfma", levels)
+            ms, ts = gpu_time(lambda: bn.bn_mul_karatsuba_n_batch(ctx, tr, ta, tb, n5, 64, levels, "mfma"), REPS, 2)
             kar[f"levels{levels}_ms"] = ms
+            kar[f"levels{levels}_ci95_ms"] = ci95(ts)
             kar[f"levels{levels}_limb_products_per_s"] = 64.0 * n5 * n5 / (ms * 1e-3)
         best = min((1, 2, 3), key=lambda l: kar[f"levels{l}_ms"])
         kar["best_levels"] = best
@@ -492,8 +520,11 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
             npairs = int(max(1, min((1 << 32) // (n * n), (1 << 25) // n)))
             row = {}
             for form in ("mad", "mfma"):
-                ms, _ = gpu_time(lambda: bn.bn_mul_n_batch(ctx, out, big, big, n, n, npairs, form), 3, 1)
+                bn.bn_reserve_for(ctx, bn.BN_OP_MUL, n, n, npairs, form)
+                ms, ts = gpu_time(lambda: bn.bn_mul_n_batch(ctx, out, big, big, n, n, npairs, form), REPS, 2)
                 row[form + "_limb_products_per_s"] = npairs * n * n / (ms * 1e-3)
+                row[form + "_ms"] = ms
+                row[form + "_ci95_ms"] = ci95(ts)
             row["pairs"] = npairs
             sweep[str(n)] = row
             faster = row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"]

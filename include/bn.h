@@ -15,8 +15,13 @@
  * Memory: every r/a/b/carry pointer is a DEVICE pointer owned by the caller.
  * Pointers must be 8-byte aligned; 16-byte alignment of r, a and b selects the
  * vector-load fast path.  The library owns a per-context device workspace
- * (look-back status words, column accumulators) that it grows on demand; grow it
- * beforehand with bn_reserve() when calls will be captured into a HIP graph.
+ * (look-back status words, column accumulators, Karatsuba and staging arrays).
+ * Compute calls never allocate and never synchronise the host: size the workspace
+ * beforehand with bn_reserve_for() (host-synchronous; ragged plans and graph captures
+ * reserve their own), and a call whose workspace is short returns BN_ENOSPACE with
+ * nothing enqueued.  Setting "workspace.auto_grow" to 1 lets such a call grow the
+ * workspace itself instead (an allocation and a device synchronisation; refused with
+ * BN_ECAPTURE while the stream is being captured).
  *
  * Streams: `bn_stream` is a hipStream_t (NULL = the legacy default stream).
  * Every compute call is asynchronous and stream-ordered: it validates its
@@ -51,6 +56,7 @@ typedef int bn_status;
 #define BN_EHIP (-5)          /* a HIP runtime call or kernel launch failed */
 #define BN_EUNSUPPORTED (-6)  /* no gfx950 device, or a feature not built */
 #define BN_ECAPTURE (-7)      /* workspace would have to grow while the stream is being captured */
+#define BN_ENOSPACE (-8)      /* the context's workspace is too small for the call (bn_reserve_for) */
 
 typedef struct bn_ctx bn_ctx;
 typedef void *bn_stream; /* hipStream_t */
@@ -61,9 +67,12 @@ typedef void *bn_stream; /* hipStream_t */
 /* ---------------------------------------------------------------- context ---- */
 
 /* Create a context on HIP device `device` (makes it current for the call).
- * Allocates the small control block; the workspace grows lazily.
- * Errors: BN_EINVAL (ctx NULL), BN_EUNSUPPORTED (device is not gfx950), BN_EHIP, BN_ENOMEM. */
-bn_status bn_create(bn_ctx **ctx, int device);
+ * Allocates the small control block; the workspace starts empty (bn_reserve_for).
+ * tuning_json: a file written by bn_autotune to load into the context (as
+ * bn_load_tuning does), or NULL for the built-in defaults.
+ * Errors: BN_EINVAL (ctx NULL, or an unreadable / rejected tuning file), BN_EUNSUPPORTED
+ * (device is not gfx950), BN_EHIP, BN_ENOMEM. */
+bn_status bn_create(bn_ctx **ctx, int device, const char *tuning_json);
 
 /* Synchronises the device and frees everything the context owns.  NULL is a no-op. */
 bn_status bn_destroy(bn_ctx *ctx);
@@ -71,13 +80,34 @@ bn_status bn_destroy(bn_ctx *ctx);
 /* Human-readable text for a status code (static storage). */
 const char *bn_strerror(bn_status s);
 
-/* Grow the workspace to at least `bytes` now (host-synchronous allocation), so that
- * later calls, including captured ones, need no allocation. */
+/* Grow the multiplication column workspace to at least `bytes` now (host-synchronous
+ * allocation).  bn_reserve_for sizes every buffer of a call. */
 bn_status bn_reserve(bn_ctx *ctx, size_t bytes);
 
-/* Workspace bytes a call would need (for bn_reserve).  op: 0 add/sub, 1 mul.
- * For add/sub pass n, npairs (na = n); for mul pass na, nb, npairs, form. */
-size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form);
+/* The calls that take workspace, for bn_reserve_for / bn_workspace_size: */
+#define BN_OP_ADDSUB 0          /* bn_add, bn_sub (npairs = 1), bn_add_n_batch, bn_sub_n_batch: na = n */
+#define BN_OP_ADDSUB_NC 1       /* bn_add_nc_n_batch, bn_sub_nc_n_batch: na = n */
+#define BN_OP_ADDSUB_UNEQUAL 2  /* bn_add_unequal, bn_sub_unequal (npairs = 1): na, nb */
+#define BN_OP_SUB_ABS 3         /* bn_sub_abs_n_batch: na = n */
+#define BN_OP_MUL 4             /* bn_mul (npairs = 1), bn_mul_n_batch: na, nb, form */
+#define BN_OP_MUL_KARATSUBA 5   /* bn_mul_karatsuba_n_batch: na = n, form, levels */
+#define BN_OP_IN_PLACE 0x100    /* or'ed into a multiplication op: the output overlaps an operand
+                                   (the staging buffer) */
+
+/* Grow every workspace buffer now (host-synchronous: allocation and a device
+ * synchronisation) so that a call of this shape runs without allocating -- eagerly or
+ * inside a stream capture.  Needs are not monotone in the sizes (a single large product
+ * splits its contraction and takes more than one of a batch): reserve each shape you
+ * will call, or the largest per bn_workspace_size.
+ * form and levels are used by the multiplication ops only (pass BN_MUL_AUTO, 0
+ * otherwise).  Buffers only grow; once the context has captured a graph, replaced
+ * buffers are kept until bn_destroy.  Errors: BN_EINVAL (NULL ctx, unknown op, form or
+ * levels), BN_ERANGE, BN_ENOMEM, BN_EHIP. */
+bn_status bn_reserve_for(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form, int levels);
+
+/* Workspace bytes (all buffers together) a call of this shape needs; 0 for a NULL
+ * ctx, an unknown op or sizes out of range.  Pure host computation. */
+size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form, int levels);
 
 /* Synchronise `stream`, then read and clear the context's device-side latch.
  * *flags (may be NULL) receives it: bit 0 = since the last check, some add/sub tile
@@ -105,7 +135,12 @@ bn_status bn_lookback_stats(bn_ctx *ctx, bn_stream stream, uint64_t *hist, size_
  * carry_out (device, one uint64) may be NULL.  n = 0 is valid (carry 0).
  * One pass over the operands: limb sums, generate/propagate flags, a wave64
  * ballot prefix scan, an LDS scan across waves and a decoupled look-back across
- * workgroups (Sec. 3.1 phases 1-4 restated as a parallel prefix computation). */
+ * workgroups (Sec. 3.1 phases 1-4 restated as a parallel prefix computation).
+ * Workspace: a launch whose workgroup tiles do not each start a pair (one long pair,
+ * or pairs longer than a tile or not dividing it) keeps one look-back status word per
+ * tile: bn_reserve_for(BN_OP_ADDSUB); BN_ENOSPACE if short.  In place, a tile waiting
+ * for an unpublished predecessor only waits (it never recomputes that tile from the
+ * operands, which may already hold sums). */
 bn_status bn_add(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
                  uint64_t *carry_out, bn_stream stream);
 
@@ -144,7 +179,8 @@ bn_status bn_sub_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na,
 
 /* r_p = |a_p - b_p| and sign[p] = [a_p < b_p] (device, may be NULL): the signed
  * difference the Karatsuba step needs (App. A, Algorithm 4).  b - a goes to the
- * context's workspace, then a - b to r, then a select; r may equal a or b exactly. */
+ * context's workspace (bn_reserve_for(BN_OP_SUB_ABS)), then a - b to r, then a select;
+ * r may equal a or b exactly. */
 bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
                              size_t npairs, uint64_t *sign, bn_stream stream);
 
@@ -157,12 +193,12 @@ bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const 
 /* r[0 .. na+nb) = a * b (Theorem 2), exactly na+nb limbs, leading zeros kept.
  * Column products (all independent), then one deferred carry-normalise pass
  * (Algorithm 2, phases 1-5).  na = 0 or nb = 0 gives r = 0 (na+nb limbs).
+ * Workspace: bn_reserve_for(BN_OP_MUL) for products above one wave's size (na + nb >
+ * 512 limbs on the MFMA form, > 1024 on the mad form); BN_ENOSPACE if short.
  * In place: r may overlap a or b, in whole or in part (e.g. r == a with room for
  * na+nb limbs).  The product then goes to a staging buffer the context owns (na+nb
- * limbs per pair, kept across calls and grown like the workspace: with a device
- * synchronisation, BN_ECAPTURE while a capture is active and it would have to grow)
- * and one device-to-device copy on `stream` moves it into r after every read of a
- * and b. */
+ * limbs per pair, reserved with BN_OP_MUL | BN_OP_IN_PLACE) and one device-to-device
+ * copy on `stream` moves it into r after every read of a and b. */
 bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
                  int form, bn_stream stream);
 
@@ -181,9 +217,8 @@ bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
  * multiple of 2^levels and levels <= BN_KARATSUBA_MAX_LEVELS (else BN_EINVAL).
  * levels = BN_KARATSUBA_AUTO picks bn_karatsuba_auto_levels(n, "mul.karatsuba_limbs"),
  * the libraries' size threshold for the recursion (App. A) applied per level.  r may
- * overlap a or b (in place, as for bn_mul).  The context keeps a workspace of about
- * 100 n npairs (3/2)^levels bytes across calls (grown with a device synchronisation;
- * BN_ECAPTURE while a stream capture is active and it would have to grow). */
+ * overlap a or b (in place, as for bn_mul).  Workspace: about 100 n npairs (3/2)^levels
+ * bytes, reserved with bn_reserve_for(BN_OP_MUL_KARATSUBA); BN_ENOSPACE if short. */
 #define BN_KARATSUBA_MAX_LEVELS 8
 #define BN_KARATSUBA_AUTO (-1)
 bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
@@ -209,7 +244,8 @@ typedef struct bn_plan bn_plan;
  * validates sizes (1 <= na, nb <= 2^20), sorts the pairs by work (na*nb,
  * largest first), picks mad or MFMA per pair (form, or the tuned crossover for
  * BN_MUL_AUTO; automatic products of 129-256 limbs take MFMA), and uploads the work
- * list to device memory it owns.
+ * list to device memory it owns.  Pairs that take the batched path (na + nb > 256) get
+ * the context's workspace reserved here.
  * Offsets plus lengths must stay below 2^60 limbs (else BN_ERANGE).
  * Synchronous (allocates).  Product ranges must not overlap each other or the inputs. */
 bn_status bn_plan_mul_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, int form,
@@ -219,8 +255,8 @@ bn_status bn_plan_destroy(bn_plan *plan);
 /* Run a planned ragged multiply: one persistent launch (both forms in one kernel when
  * the plan has both); wave k of W resident waves takes pairs k, k+W, ... of the
  * work-sorted list.  Pairs with
- * na + nb > 256 run through the batched path, one call each.  No allocation
- * (beyond the batched path's workspace, reserved by graph capture), no host sync.
+ * na + nb > 256 run through the batched path, one call each.  No allocation, no host
+ * sync (the plan reserved the workspace; BN_ENOSPACE if it was given up since).
  * BN_EINVAL for a plan of another kind or one built on a context of another device. */
 bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, const uint64_t *a_pool,
                         const uint64_t *b_pool, bn_stream stream);

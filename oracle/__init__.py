@@ -11,7 +11,11 @@ Sec. 2.1 and Theorem 1.
 Parity status: every function is pinned by ``tests/test_oracle.py`` against
 CPython's arbitrary-precision ``int`` (an independent library routine), closed
 forms, algebraic identities, residues and emulations of the paper's
-Algorithms 1 and 2.  No function is "parity unpinned".
+Algorithms 1 and 2; the ragged forms against per-pair ``int`` sums and products
+over pooled arrays with gaps, unsorted offsets and empty pairs.  Planted mistakes
+(dropped carry, wrong borrow, dropped top carry, stray term, ignored carry-in,
+misread ragged descriptors) are compiled into mutant copies of the C source and
+each fails a pin.  No function is "parity unpinned".
 """
 from __future__ import annotations
 

@@ -28,6 +28,15 @@ BN_ENOMEM = -4
 BN_EHIP = -5
 BN_EUNSUPPORTED = -6
 BN_ECAPTURE = -7
+BN_ENOSPACE = -8
+
+BN_OP_ADDSUB = 0
+BN_OP_ADDSUB_NC = 1
+BN_OP_ADDSUB_UNEQUAL = 2
+BN_OP_SUB_ABS = 3
+BN_OP_MUL = 4
+BN_OP_MUL_KARATSUBA = 5
+BN_OP_IN_PLACE = 0x100
 
 BN_MUL_AUTO = 0
 BN_MUL_MAD = 1
@@ -57,12 +66,13 @@ _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
 _i = ctypes.c_int
 _PROTOS = {
-    "bn_create": (_i, [ctypes.POINTER(_vp), _i]),
+    "bn_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.c_char_p]),
     "bn_destroy": (_i, [_vp]),
     "bn_strerror": (ctypes.c_char_p, [_i]),
     "bn_version": (ctypes.c_char_p, []),
     "bn_reserve": (_i, [_vp, _sz]),
-    "bn_workspace_size": (_sz, [_vp, _i, _sz, _sz, _sz, _i]),
+    "bn_reserve_for": (_i, [_vp, _i, _sz, _sz, _sz, _i, _i]),
+    "bn_workspace_size": (_sz, [_vp, _i, _sz, _sz, _sz, _i, _i]),
     "bn_check": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint32)]),
     "bn_lookback_stats": (_i, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64), _sz]),
     "bn_probe_rates": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -163,9 +173,15 @@ def _stream(stream):
 
 
 # ------------------------------------------------------------------ context ----
-def bn_create(device: int = 0):
+def bn_create(device: int = 0, tuning: str | None = None, auto_grow: bool = False):
+    """A context on `device`; `tuning`: a file written by bn_autotune, or None.
+    auto_grow=True sets "workspace.auto_grow": compute calls then grow a short
+    workspace themselves (allocation + device sync) instead of failing with
+    BN_ENOSPACE."""
     ctx = _vp()
-    _ck(lib().bn_create(ctypes.byref(ctx), device), "bn_create")
+    _ck(lib().bn_create(ctypes.byref(ctx), device, tuning.encode() if tuning else None), "bn_create")
+    if auto_grow:
+        bn_set_param(ctx, "workspace.auto_grow", 1)
     return ctx
 
 
@@ -177,8 +193,14 @@ def bn_reserve(ctx, nbytes: int):
     _ck(lib().bn_reserve(ctx, nbytes), "bn_reserve")
 
 
-def bn_workspace_size(ctx, op: int, na: int, nb: int, npairs: int, form: int = BN_MUL_AUTO) -> int:
-    return lib().bn_workspace_size(ctx, op, na, nb, npairs, form)
+def bn_reserve_for(ctx, op: int, na: int, nb: int = 0, npairs: int = 1, form=BN_MUL_AUTO, levels: int = 0):
+    """Size every workspace buffer for one call shape (host-synchronous)."""
+    _ck(lib().bn_reserve_for(ctx, op, na, nb, npairs, _form(form), levels), "bn_reserve_for")
+
+
+def bn_workspace_size(ctx, op: int, na: int, nb: int = 0, npairs: int = 1, form=BN_MUL_AUTO,
+                      levels: int = 0) -> int:
+    return lib().bn_workspace_size(ctx, op, na, nb, npairs, _form(form), levels)
 
 
 def bn_check(ctx, stream=None) -> int:

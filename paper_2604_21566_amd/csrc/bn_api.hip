@@ -15,11 +15,8 @@ bool flat_scan_shape_ok(int waves, int rows);
 
 bn_status bn_launch_status() { return hipGetLastError() == hipSuccess ? BN_OK : BN_EHIP; }
 
-bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s) {
+bn_status bn_grow(bn_ctx *ctx, DevBuf &buf, size_t bytes) {
     if (buf.bytes >= bytes) return BN_OK;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return BN_EHIP;
-    if (cs != hipStreamCaptureStatusNone) return BN_ECAPTURE;
     size_t want = std::max(bytes, buf.bytes + buf.bytes / 2);
     want = (want + 65535) & ~(size_t)65535;
     if (buf.ptr) {
@@ -43,6 +40,33 @@ bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s) {
     return BN_OK;
 }
 
+bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s) {
+    if (buf.bytes >= bytes) return BN_OK;
+    if (!ctx->tune.auto_grow && !ctx->grow_scope) return BN_ENOSPACE;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return BN_EHIP;
+    if (cs != hipStreamCaptureStatusNone) return BN_ECAPTURE;
+    return bn_grow(ctx, buf, bytes);
+}
+
+bn_status ws_reserve(bn_ctx *ctx, const WsNeed &need) {
+    bn_status st;
+    if ((st = bn_grow(ctx, ctx->status, need.status)) != BN_OK) return st;
+    if ((st = bn_grow(ctx, ctx->work, need.work)) != BN_OK) return st;
+    if ((st = bn_grow(ctx, ctx->kwork, need.kwork)) != BN_OK) return st;
+    return bn_grow(ctx, ctx->mstage, need.mstage);
+}
+
+// Every buffer a call needs, checked (or grown, with auto_grow) before anything is
+// enqueued: a short workspace fails the call with nothing launched.
+static bn_status ws_acquire(bn_ctx *ctx, const WsNeed &need, hipStream_t s) {
+    bn_status st;
+    if ((st = bn_ensure(ctx, ctx->status, need.status, s)) != BN_OK) return st;
+    if ((st = bn_ensure(ctx, ctx->work, need.work, s)) != BN_OK) return st;
+    if ((st = bn_ensure(ctx, ctx->kwork, need.kwork, s)) != BN_OK) return st;
+    return bn_ensure(ctx, ctx->mstage, need.mstage, s);
+}
+
 // ------------------------------------------------------------------ helpers ----
 static bool overlaps(const void *x, size_t xbytes, const void *y, size_t ybytes) {
     const uintptr_t a0 = (uintptr_t)x, a1 = a0 + xbytes, b0 = (uintptr_t)y, b1 = b0 + ybytes;
@@ -59,6 +83,44 @@ static bn_status check_ptr(const void *p, size_t limbs) {
 }
 
 static inline hipStream_t S(bn_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Workspace of one call (BN_OP_* of bn.h; in_place for multiplications whose output
+// overlaps an operand).  The same quantities the launch code checks, taken at their
+// largest over the operand alignments the call may see.
+static WsNeed ws_need_for(const bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form, int levels,
+                          bool in_place) {
+    WsNeed w;
+    switch (op) {
+        case BN_OP_ADDSUB:
+            w.status = flat_scan_status_bytes(ctx, na, (u64)na * npairs);
+            break;
+        case BN_OP_ADDSUB_NC:
+            w.status = flat_scan_ext_status_bytes(na, (u64)na * npairs);
+            break;
+        case BN_OP_ADDSUB_UNEQUAL:
+            w = unequal_need(ctx, na, nb, npairs);
+            break;
+        case BN_OP_SUB_ABS:
+            w.status = flat_scan_status_bytes(ctx, na, (u64)na * npairs);
+            w.kwork = ((u64)na * npairs + npairs) * sizeof(u64);
+            break;
+        case BN_OP_MUL:
+            w.work = mul_workspace_bytes(ctx, na, nb, npairs, form);
+            w.status = mul_status_bytes(ctx, na, nb, npairs, form);
+            if (in_place) w.mstage = (na + nb) * npairs * sizeof(u64);
+            break;
+        case BN_OP_MUL_KARATSUBA:
+            if (levels == BN_KARATSUBA_AUTO) levels = bn_karatsuba_auto_levels(na, (size_t)ctx->tune.karatsuba_limbs);
+            w = karatsuba_need(ctx, na, npairs, levels, form);
+            if (in_place) w.mstage = 2 * na * npairs * sizeof(u64);
+            break;
+        default:
+            break;
+    }
+    return w;
+}
+
+static bool op_valid(int op) { return op >= BN_OP_ADDSUB && op <= BN_OP_MUL_KARATSUBA; }
 
 struct DeviceGuard {
     int prev = -1;
@@ -85,12 +147,15 @@ const char *bn_strerror(bn_status s) {
         case BN_ENOMEM: return "device allocation failed";
         case BN_EHIP: return "HIP runtime error";
         case BN_EUNSUPPORTED: return "unsupported device or feature";
-        case BN_ECAPTURE: return "workspace must grow during stream capture (call bn_reserve first)";
+        case BN_ECAPTURE: return "workspace must grow during stream capture (call bn_reserve_for first)";
+        case BN_ENOSPACE: return "workspace too small for this call (call bn_reserve_for first)";
         default: return "unknown status";
     }
 }
 
-bn_status bn_create(bn_ctx **out, int device) {
+static bn_status load_tuning(bn_ctx *ctx, const char *path);
+
+bn_status bn_create(bn_ctx **out, int device, const char *tuning_json) {
     if (!out) return BN_EINVAL;
     *out = nullptr;
     int ndev = 0;
@@ -114,6 +179,14 @@ bn_status bn_create(bn_ctx **out, int device) {
         delete ctx;
         return BN_EHIP;
     }
+    if (tuning_json) {
+        const bn_status st = load_tuning(ctx, tuning_json);
+        if (st != BN_OK) {
+            (void)hipFree(ctx->ctl);
+            delete ctx;
+            return st;
+        }
+    }
     *out = ctx;
     return BN_OK;
 }
@@ -135,13 +208,28 @@ bn_status bn_destroy(bn_ctx *ctx) {
 bn_status bn_reserve(bn_ctx *ctx, size_t bytes) {
     if (!ctx) return BN_EINVAL;
     DeviceGuard g(ctx->device);
-    return bn_ensure(ctx, ctx->work, bytes, nullptr);
+    return bn_grow(ctx, ctx->work, bytes);
 }
 
-size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form) {
-    if (!ctx) return 0;
-    if (op == 0) return 0;  // add/sub only use the status array, sized by bn_reserve_status internally
-    return mul_workspace_bytes(ctx, na, nb, npairs, form);
+bn_status bn_reserve_for(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form, int levels) {
+    if (!ctx || !op_valid(op & ~BN_OP_IN_PLACE)) return BN_EINVAL;
+    if (form != BN_MUL_AUTO && form != BN_MUL_MAD && form != BN_MUL_MFMA) return BN_EINVAL;
+    if (levels != BN_KARATSUBA_AUTO && (levels < 0 || levels > BN_KARATSUBA_MAX_LEVELS)) return BN_EINVAL;
+    size_t t;
+    if (na > BN_MAX_LIMBS || nb > BN_MAX_LIMBS || mul_overflow(na + nb, npairs, &t) || t > 2 * BN_MAX_LIMBS)
+        return BN_ERANGE;
+    DeviceGuard g(ctx->device);
+    return ws_reserve(ctx, ws_need_for(ctx, op & ~BN_OP_IN_PLACE, na, nb, npairs, form, levels,
+                                       (op & BN_OP_IN_PLACE) != 0));
+}
+
+size_t bn_workspace_size(bn_ctx *ctx, int op, size_t na, size_t nb, size_t npairs, int form, int levels) {
+    if (!ctx || !op_valid(op & ~BN_OP_IN_PLACE)) return 0;
+    size_t t;
+    if (na > BN_MAX_LIMBS || nb > BN_MAX_LIMBS || mul_overflow(na + nb, npairs, &t) || t > 2 * BN_MAX_LIMBS) return 0;
+    const WsNeed w =
+        ws_need_for(ctx, op & ~BN_OP_IN_PLACE, na, nb, npairs, form, levels, (op & BN_OP_IN_PLACE) != 0);
+    return w.status + w.work + w.kwork + w.mstage;
 }
 
 bn_status bn_lookback_stats(bn_ctx *ctx, bn_stream stream, uint64_t *hist, size_t nbins) {
@@ -183,6 +271,8 @@ static bn_status addsub(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, c
                   overlaps(carry, npairs * 8, b, bytes)))
         return BN_EALIAS;
     DeviceGuard g(ctx->device);
+    if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_ADDSUB, n, n, npairs, 0, 0, false), S(stream))) != BN_OK)
+        return st;
     return launch_flat_scan(ctx, sub, r, a, b, n, npairs, carry, S(stream));
 }
 
@@ -208,6 +298,8 @@ static bn_status addsub_nc(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a
         return hipMemcpyAsync(carry, cin, npairs * 8, hipMemcpyDeviceToDevice, S(stream)) == hipSuccess ? BN_OK
                                                                                                 : BN_EHIP;
     }
+    if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_ADDSUB_NC, n, n, npairs, 0, 0, false), S(stream))) != BN_OK)
+        return st;
     return launch_addsub_nc(ctx, sub, r, a, b, n, npairs, cin, carry, S(stream));
 }
 
@@ -256,6 +348,8 @@ static bn_status addsub_unequal(bn_ctx *ctx, bool sub, uint64_t *r, const uint64
         return BN_EALIAS;
     DeviceGuard g(ctx->device);
     if (na == 0) return carry ? launch_fill_u64(carry, 1, 0, S(stream)) : BN_OK;
+    if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_ADDSUB_UNEQUAL, na, nb, 1, 0, 0, false), S(stream))) != BN_OK)
+        return st;
     return launch_addsub_unequal(ctx, sub, r, a, na, b, nb, carry, S(stream));
 }
 
@@ -283,6 +377,8 @@ bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const 
                  overlaps(sign, npairs * 8, b, bytes)))
         return BN_EALIAS;
     DeviceGuard g(ctx->device);
+    if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_SUB_ABS, n, n, npairs, 0, 0, false), S(stream))) != BN_OK)
+        return st;
     return launch_sub_abs(ctx, r, a, b, n, npairs, sign, S(stream));
 }
 
@@ -324,6 +420,9 @@ bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const u
     bn_status st = mul_args(ctx, r, a, b, na, nb, 1, form);
     if (st != BN_OK) return st;
     DeviceGuard g(ctx->device);
+    if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_MUL, na, nb, 1, form, 0, mul_in_place(r, a, b, na, nb, 1)),
+                         S(stream))) != BN_OK)
+        return st;
     return mul_staged(ctx, r, a, b, na, nb, 1, S(stream),
                       [&](u64 *out) { return launch_mul_batch(ctx, out, a, b, na, nb, 1, form, S(stream)); });
 }
@@ -333,6 +432,10 @@ bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
     bn_status st = mul_args(ctx, r, a, b, na, nb, npairs, form);
     if (st != BN_OK) return st;
     DeviceGuard g(ctx->device);
+    if ((st = ws_acquire(ctx,
+                         ws_need_for(ctx, BN_OP_MUL, na, nb, npairs, form, 0, mul_in_place(r, a, b, na, nb, npairs)),
+                         S(stream))) != BN_OK)
+        return st;
     return mul_staged(ctx, r, a, b, na, nb, npairs, S(stream),
                       [&](u64 *out) { return launch_mul_batch(ctx, out, a, b, na, nb, npairs, form, S(stream)); });
 }
@@ -356,6 +459,11 @@ bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, 
     if (levels < 0 || levels > BN_KARATSUBA_MAX_LEVELS) return BN_EINVAL;
     if (n && (n % ((size_t)1 << levels))) return BN_EINVAL;
     DeviceGuard g(ctx->device);
+    if ((st = ws_acquire(ctx,
+                         ws_need_for(ctx, BN_OP_MUL_KARATSUBA, n, n, npairs, form, levels,
+                                     mul_in_place(r, a, b, n, n, npairs)),
+                         S(stream))) != BN_OK)
+        return st;
     return mul_staged(ctx, r, a, b, n, n, npairs, S(stream), [&](u64 *out) {
         return launch_mul_karatsuba(ctx, out, a, b, n, npairs, levels, form, S(stream));
     });
@@ -366,7 +474,14 @@ bn_status bn_plan_mul_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npai
     if (!ctx || !plan || (npairs && !host_pairs)) return BN_EINVAL;
     if (form != BN_MUL_AUTO && form != BN_MUL_MAD && form != BN_MUL_MFMA) return BN_EINVAL;
     DeviceGuard g(ctx->device);
-    return plan_mul_ragged(ctx, host_pairs, npairs, form, plan);
+    bn_status st = plan_mul_ragged(ctx, host_pairs, npairs, form, plan);
+    if (st != BN_OK) return st;
+    // the plan's large items run through the batched path: its workspace, reserved now
+    if ((st = ws_reserve(ctx, (*plan)->ws)) != BN_OK) {
+        bn_plan_destroy(*plan);
+        *plan = nullptr;
+    }
+    return st;
 }
 
 bn_status bn_plan_add_ragged(bn_ctx *ctx, const bn_pair *host_pairs, size_t npairs, bn_plan **plan) {
@@ -390,6 +505,8 @@ bn_status bn_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t *r_pool, cons
     if (plan->npairs && (!r_pool || !a_pool || !b_pool)) return BN_EINVAL;
     if (((uintptr_t)r_pool | (uintptr_t)a_pool | (uintptr_t)b_pool) & 7u) return BN_EINVAL;
     DeviceGuard g(ctx->device);
+    bn_status st = ws_acquire(ctx, plan->ws, S(stream));
+    if (st != BN_OK) return st;
     return launch_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, S(stream));
 }
 
@@ -410,14 +527,8 @@ bn_status bn_graph_capture_mul_ragged(bn_ctx *ctx, const bn_plan *plan, uint64_t
     if (!ctx || !plan || !graph || !stream || plan->op != 0 || plan->device != ctx->device) return BN_EINVAL;
     DeviceGuard g(ctx->device);
     // large items use the batched pipeline: reserve its workspace before capture
-    size_t need = 0, status = 0;
-    for (const RItem &it : plan->large) {
-        need = std::max(need, mul_workspace_bytes(ctx, it.na, it.nb, 1, (int)it.form));
-        status = std::max(status, mul_status_bytes(ctx, it.na, it.nb, 1, (int)it.form));
-    }
     bn_status st;
-    if ((st = bn_ensure(ctx, ctx->work, need, nullptr)) != BN_OK) return st;
-    if ((st = bn_ensure(ctx, ctx->status, status, nullptr)) != BN_OK) return st;
+    if ((st = ws_reserve(ctx, plan->ws)) != BN_OK) return st;
     ctx->captured = true;
     return capture(stream, graph, [&]() { return bn_mul_ragged(ctx, plan, r_pool, a_pool, b_pool, stream); });
 }
@@ -430,19 +541,14 @@ bn_status bn_graph_capture_batch(bn_ctx *ctx, int op, uint64_t *r, const uint64_
     bn_status st;
     if (op == 2) {
         if ((st = mul_args(ctx, r, a, b, na, nb, npairs, form)) != BN_OK) return st;
-        if ((st = bn_ensure(ctx, ctx->work, mul_workspace_bytes(ctx, na, nb, npairs, form), nullptr)) != BN_OK)
-            return st;
-        if (mul_in_place(r, a, b, na, nb, npairs) &&
-            (st = bn_ensure(ctx, ctx->mstage, (na + nb) * npairs * 8, nullptr)) != BN_OK)
-            return st;
-        if ((st = bn_ensure(ctx, ctx->status, mul_status_bytes(ctx, na, nb, npairs, form), nullptr)) != BN_OK)
+        if ((st = ws_reserve(ctx, ws_need_for(ctx, BN_OP_MUL, na, nb, npairs, form, 0,
+                                              mul_in_place(r, a, b, na, nb, npairs)))) != BN_OK)
             return st;
         ctx->captured = true;
         return capture(stream, graph,
                        [&]() { return bn_mul_n_batch(ctx, r, a, b, na, nb, npairs, form, stream); });
     }
-    if ((st = bn_ensure(ctx, ctx->status, flat_scan_status_bytes(ctx, (u64)na, (u64)na * npairs), nullptr)) != BN_OK)
-        return st;
+    if ((st = ws_reserve(ctx, ws_need_for(ctx, BN_OP_ADDSUB, na, na, npairs, 0, 0, false))) != BN_OK) return st;
     ctx->captured = true;
     return capture(stream, graph, [&]() {
         return op == 0 ? bn_add_n_batch(ctx, r, a, b, na, npairs, carry_out, stream)
@@ -467,7 +573,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 static const char *kParamNames =
     "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,"
     "mul.crossover_limbs,mul.small_crossover_limbs,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,mul.karatsuba_limbs,"
-    "lookback.spin_limit,debug.flags";
+    "lookback.spin_limit,debug.flags,workspace.auto_grow";
 
 const char *bn_param_names(void) { return kParamNames; }
 
@@ -511,6 +617,9 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
     } else if (k == "debug.flags") {
         if (v < 0 || v > 3) return BN_EINVAL;
         t.debug_flags = (u32)v;
+    } else if (k == "workspace.auto_grow") {
+        if (v != 0 && v != 1) return BN_EINVAL;
+        t.auto_grow = (int)v;
     } else {
         return BN_EINVAL;
     }
@@ -533,11 +642,10 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "mul.karatsuba_limbs") *v = t.karatsuba_limbs;
     else if (k == "lookback.spin_limit") *v = t.spin_limit;
     else if (k == "debug.flags") *v = t.debug_flags;
+    else if (k == "workspace.auto_grow") *v = t.auto_grow;
     else return BN_EINVAL;
     return BN_OK;
 }
-
-static bn_status load_tuning(bn_ctx *ctx, const char *path);
 
 bn_status bn_load_tuning(bn_ctx *ctx, const char *path) {
     if (!ctx || !path) return BN_EINVAL;

@@ -7,6 +7,7 @@
 
 #include "bn.h"
 
+#include <atomic>
 #include <vector>
 
 typedef uint64_t u64;
@@ -56,15 +57,27 @@ struct Tuning {
                                        // 0: by size (mfma_window in k_mul.hip)
     int mfma_rows = 2;                 // Toeplitz row groups of 64 per column block (1 or 2)
     i64 karatsuba_limbs = 4096;        // BN_KARATSUBA_AUTO: smallest half that is split again
+    int auto_grow = 0;                 // 1: a compute call whose workspace is short grows it
+                                       // (allocation + device synchronisation, never during a
+                                       // capture); 0: it returns BN_ENOSPACE
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
                                        // bit 1: record look-back distances in ScanCtl::hist
 };
 
-// Workspace buffer that grows on demand (never while the stream is being captured).
+// Workspace buffer of a context: sized by the reserve calls (or, with auto_grow, by the
+// compute call that needs more; never while the stream is being captured).
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+};
+
+// Workspace a call needs, per buffer (bytes).
+struct WsNeed {
+    size_t status = 0;  // look-back status words of chained scans
+    size_t work = 0;    // multiplication column sums / folded limbs / converted operands
+    size_t kwork = 0;   // Karatsuba levels; |a - b| scratch
+    size_t mstage = 0;  // products computed in place
 };
 
 struct bn_ctx {
@@ -78,6 +91,7 @@ struct bn_ctx {
     u64 host_epoch = 1ull << 61;  // epochs of chained scans launched outside a capture
     Tuning tune;
     bool captured = false;        // a graph has baked in buffer addresses of this context
+    bool grow_scope = false;      // growth allowed inside the call (the autotuner's own calls)
     std::vector<void *> retired;  // buffers replaced after a capture, freed by bn_destroy
 };
 
@@ -99,6 +113,7 @@ struct bn_plan {
     std::vector<RItem> large;      // mul items too big for one wave: one batched launch each
     u32 nmad = 0, nmfma = 0;       // items per form
     u64 work = 0;                  // sum of na * nb (mul) or n (add)
+    WsNeed ws;                     // workspace of the large items (reserved when the plan is built)
 };
 
 struct bn_graph {
@@ -107,7 +122,12 @@ struct bn_graph {
 };
 
 // ---- internal helpers (bn_api.hip) ----
+// `buf` holds at least `bytes`: BN_OK; else, when growth is allowed (auto_grow or the
+// autotuner) and the stream is not being captured, grow it; else BN_ENOSPACE.
 bn_status bn_ensure(bn_ctx *ctx, DevBuf &buf, size_t bytes, hipStream_t s);
+// Grow `buf` to at least `bytes` now (host-synchronous; the reserve calls).
+bn_status bn_grow(bn_ctx *ctx, DevBuf &buf, size_t bytes);
+bn_status ws_reserve(bn_ctx *ctx, const WsNeed &need);
 bn_status bn_launch_status();
 
 // ---- add/sub (k_addsub.hip) ----
@@ -122,12 +142,25 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
 size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N);
 size_t flat_scan_ext_status_bytes(u64 n, u64 N);  // the same for launch_flat_scan_ext
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s);
+// Where a chained launch keeps its look-back state: NULL for the context's control block
+// and status array (grown by the reserve calls), or a fixed device array.
+struct ScanMem {
+    ScanCtl *ctl = nullptr;
+    u64 *status = nullptr;
+    u64 max_tiles = 0;                       // status words available
+    std::atomic<u64> *host_epoch = nullptr;  // epochs of launches outside a capture
+    u32 dbg_mask = ~0u;                      // debug flags that apply
+};
+bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
+                               const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s,
+                               const ScanMem *fixed);
 
 // ---- add/sub extras (k_addsub_ext.hip) ----
 bn_status launch_addsub_nc(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                            const u64 *cin, u64 *carry, hipStream_t s);
 bn_status launch_addsub_unequal(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,
                                 u64 *carry, hipStream_t s);
+WsNeed unequal_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs);
 bn_status launch_sub_abs(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *sign,
                          hipStream_t s);
 
@@ -143,6 +176,7 @@ bool mul_small_range(u64 P);  // products of P limbs that take mul.small_crossov
 bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, int levels,
                                int form, hipStream_t s);
 size_t karatsuba_workspace_bytes(u64 n, u64 npairs, int levels);
+WsNeed karatsuba_need(const bn_ctx *ctx, u64 n, u64 npairs, int levels, int form);
 
 // ---- ragged (k_ragged.hip) ----
 bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int form, bn_plan **plan);

@@ -155,12 +155,13 @@ __device__ void mul_item_mad(const u64 *__restrict__ a, u32 na, const u64 *__res
 //     T_d[rr][k]   = b[32 (d-1) + rr + 1 + k]          (Toeplitz in rr - k)
 //     A_d[k][W]    = a[32 (W-d) + 31 - k]              (32-digit chunk W-d, reversed)
 // so one v_mfma_i32_32x32x32_i8 per (d, block of 32 W) forms 32x32 column sums.
-// The instruction multiplies signed int8, so digits enter as a' = a - 128 (byte
-// xor 0x80) and padding as signed 0; the exact unsigned column sum is restored in
-// the fold: C = C' + 128 (S_a + S_b) - 16384 cnt, with S_a, S_b the sums of the
-// unsigned digits that meet in the column and cnt the number of digit pairs.
-// |a' b'| <= 2^14, 32 products per step: an int32 accumulator stays exact for up
-// to 4095 steps; work items are cut into chunks of at most 4095 steps.
+// The instruction multiplies signed int8, so both operands enter as balanced signed
+// digits in [-128, 127] (one more digit than the operand has bytes; see
+// wave_balanced_digits): the digits sum to the operand exactly, so every column sum
+// is the true signed column sum of the product and needs no correction.  A digit
+// product lies in [-16256, 16384]; one-wave products (at most 8 * 512 + 1 digit pairs
+// per column) keep exact int32 sums, and the large kernel's int32 bound is stated
+// where its epilogue decodes the sums (k_mul.hip).
 //
 // Operand registers: lane (x = lane & 31, h = lane >> 5) supplies bytes k = 16 h .. 16 h + 15
 // of row x of T_d (A-operand) and of column x of A_d (B-operand).  Both operands

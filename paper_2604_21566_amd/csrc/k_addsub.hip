@@ -94,6 +94,7 @@ struct ScanGeom {
     const u64 *cin;  // EXT_CIN: per-segment carry (borrow) into the segment's first limb (bit 0)
     u64 nseg;        // segments (pairs)
     u64 bval;        // EXT_BCONST: the value of every limb of b
+    u32 no_self_help;  // 1 when r overlaps a or b: a waiting tile never reads another tile's operands
 };
 
 // Kernel variants beyond the plain a +- b: a per-segment carry-in, and b given as one
@@ -149,6 +150,13 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
 // computes that tile's aggregate from the operands itself and walks on.  Tiles
 // below index 0 count as "carry-out 0".  `dist` returns how many tiles back the
 // deciding predecessor was.
+//
+// In place (r overlapping a or b) there is no self-help: the unpublished tile may
+// publish and overwrite its operands with sums between our status read and our
+// operand reads, so the wave only waits.  Every wait still ends: a tile publishes
+// before it waits for anything, and the lowest unfinished tile is resident because
+// workgroups of one XCD are dispatched in index order (the argument every decoupled
+// look-back without self-help rests on).
 template <bool SUB, int EXT>
 __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64 *latch,
                         const u64 *__restrict__ a, const u64 *__restrict__ b, const ScanGeom &G, u64 &dist) {
@@ -178,7 +186,7 @@ __device__ u32 lookback(const u64 *status, u64 t, u64 epoch, u32 spin_limit, u64
         const u32 sf = __shfl(state, first);
         dist = (u64)((i64)t - (base - first));  // base - first >= -1: "tile -1" is a carry-out 0
         if (sf != 0) return sf & 1u;
-        if (++spins <= spin_limit) {
+        if (G.no_self_help || ++spins <= spin_limit) {
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
@@ -307,7 +315,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     // ---- phase 3: carries into the waves assuming carry-in 0 into the tile; publish ----
     // A tile that does not propagate knows its carry-out now (I0/I1); one that
     // propagates publishes A and learns its carry-in by look-back in phase 5.
-    const bool poison = (dbg & 1u) && t == 0;
+    // (never in place: without self-help nobody could get past the silent tile)
+    const bool poison = (dbg & 1u) && t == 0 && !G.no_self_help;
     if (threadIdx.x == 0) {
         u32 c = 0, pt = 1;
 #pragma unroll
@@ -482,6 +491,12 @@ scan_fn pick(int waves, int rows) {
 constexpr int UNALIGNED_BATCH_WAVES = 1, UNALIGNED_BATCH_ROWS = 1;
 constexpr int UNALIGNED_CHAIN_WAVES = 4, UNALIGNED_CHAIN_ROWS = 4;
 
+// [x, x + xn) and [y, y + yn) (limbs) share a limb
+bool ranges_overlap(const u64 *x, u64 xn, const u64 *y, u64 yn) {
+    const uintptr_t x0 = (uintptr_t)x, y0 = (uintptr_t)y;
+    return x && y && xn && yn && x0 < y0 + 8 * yn && y0 < x0 + 8 * xn;
+}
+
 }  // namespace
 
 bool flat_scan_shape_ok(int waves, int rows) { return pick<false, false>(waves, rows) != nullptr; }
@@ -550,8 +565,8 @@ static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
                  : k_flat_scan<SUB, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false, EXT>;
 }
 
-bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
-                               const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s) {
+bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
+                             const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s, const ScanMem *fixed) {
     const u64 N = n * npairs;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
     const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst ? nullptr : b)) & 15u) == 0;
@@ -572,8 +587,12 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     const u64 TL = (u64)waves * rows * 128;
     const u64 ntiles = (N + TL - 1) / TL;
     if (chain) {
-        bn_status st = bn_ensure(ctx, ctx->status, ntiles * sizeof(u64), s);
-        if (st != BN_OK) return st;
+        if (fixed) {
+            if (ntiles > fixed->max_tiles) return BN_ERANGE;
+        } else {
+            bn_status st = bn_ensure(ctx, ctx->status, ntiles * sizeof(u64), s);
+            if (st != BN_OK) return st;
+        }
     }
     if (ntiles > 0x7fffffffull) return BN_ERANGE;
     scan_fn f = nullptr;
@@ -595,20 +614,33 @@ bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         f = sub ? k_flat_scan<true, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false>
                 : k_flat_scan<false, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false>;
     if (!f) return BN_EINVAL;
-    // Chained launches outside a stream capture take a fresh epoch from the host
-    // counter (its range, from 2^61 up, is disjoint from the control block's, which
-    // counts from 1); captured ones read the control block and bump it after.
+    // Chained launches outside a stream capture take a fresh epoch from a host counter
+    // (its range, from 2^61 up, is disjoint from the control block's, which counts up
+    // from its initial value); captured ones read the control block and bump it after.
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (chain && hipStreamIsCapturing(s, &cs) != hipSuccess) return BN_EHIP;
     const bool captured = cs != hipStreamCaptureStatusNone;
-    ScanGeom G{N, n, -1, TL, (chain && !captured) ? ++ctx->host_epoch : 0, cin, npairs, bval};
+    u64 epoch = 0;
+    if (chain && !captured) epoch = fixed ? fixed->host_epoch->fetch_add(1) + 1 : ++ctx->host_epoch;
+    // r overlapping an operand: a waiting tile must not read another tile's operands
+    const bool inplace = ranges_overlap(r, N, a, N) || (!bconst && ranges_overlap(r, N, b, N));
+    ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
+    u32 dbg = ctx->tune.debug_flags & (fixed ? fixed->dbg_mask : ~0u);
+    if (inplace) dbg &= ~1u;
+    ScanCtl *ctl = fixed ? fixed->ctl : ctx->ctl;
+    u64 *status = fixed ? fixed->status : (u64 *)ctx->status.ptr;
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
-                       ctx->ctl, (u64 *)ctx->status.ptr, ctx->tune.spin_limit, ctx->tune.debug_flags);
+                       ctl, status, ctx->tune.spin_limit, dbg);
     bn_status st = bn_launch_status();
     if (st != BN_OK || !chain || !captured) return st;
-    hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, ctx->ctl);
+    hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, ctl);
     return bn_launch_status();
+}
+
+bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
+                               const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s) {
+    return launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, cin, bconst, bval, carry, s, nullptr);
 }
 
 bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *carry,

@@ -34,6 +34,18 @@ bn_status launch_addsub_unequal(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64
     return launch_flat_scan_ext(ctx, sub, r + nb, a + nb, nullptr, na - nb, 1, nb > 0 ? tmp : zero, true, 0, carry, s);
 }
 
+// Status words of the two scans of an unequal-length add/sub (one pair).
+WsNeed unequal_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
+    WsNeed w;
+    if (npairs == 0 || na == 0) return w;
+    if (na == nb) {
+        w.status = flat_scan_status_bytes(ctx, na, na * npairs);
+        return w;
+    }
+    w.status = std::max(flat_scan_status_bytes(ctx, nb, nb * npairs), flat_scan_ext_status_bytes(na - nb, (na - nb) * npairs));
+    return w;
+}
+
 // r = |a - b| per pair, sign[p] = [a_p < b_p].  b - a goes to a scratch array first,
 // so r may be a or b exactly.
 bn_status launch_sub_abs(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *sign,

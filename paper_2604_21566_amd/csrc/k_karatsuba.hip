@@ -183,6 +183,29 @@ size_t karatsuba_workspace_bytes(u64 n, u64 npairs, int levels) {
     return (size_t)karatsuba_plan(n, npairs, levels).total * sizeof(u64);
 }
 
+// Every buffer a run touches: its own arrays, the bottom batch's multiplication
+// workspace, and status words for the largest of its scans (splits: N_l pairs of k
+// limbs; combines: N_l pairs of 4 k; the bottom batch's own scans).
+WsNeed karatsuba_need(const bn_ctx *ctx, u64 n, u64 npairs, int levels, int form) {
+    WsNeed w;
+    if (npairs == 0 || n == 0 || levels < 0) return w;
+    if (levels == 0) {
+        w.work = mul_workspace_bytes(ctx, n, n, npairs, form);
+        w.status = mul_status_bytes(ctx, n, n, npairs, form);
+        return w;
+    }
+    const KPlan p = karatsuba_plan(n, npairs, levels);
+    w.kwork = (size_t)p.total * sizeof(u64);
+    for (int l = 0; l < levels; ++l) {
+        const u64 N = p.lv[l].N, k = p.lv[l].m / 2;
+        w.status = std::max({w.status, flat_scan_status_bytes(ctx, k, N * k), flat_scan_status_bytes(ctx, 4 * k, N * 4 * k)});
+    }
+    const KLevel &Bt = p.lv[levels];
+    w.work = mul_workspace_bytes(ctx, Bt.m, Bt.m, Bt.N, form);
+    w.status = std::max(w.status, mul_status_bytes(ctx, Bt.m, Bt.m, Bt.N, form));
+    return w;
+}
+
 bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, int levels,
                                int form, hipStream_t s) {
     if (npairs == 0 || n == 0) return BN_OK;

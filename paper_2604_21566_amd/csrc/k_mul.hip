@@ -3,11 +3,15 @@
 // Small products (na + nb <= 512 limbs on the MFMA form, <= 1024 on the mad form): one
 // wave per pair does everything -- column products, fold, and the in-wave carry pass
 // -- with no workspace.
-// Large products: a product kernel accumulates column sums into a workspace with
-// atomics (work items = output-column block x slice of the contraction range, so
-// every item has about the same work), a fold kernel turns column sums into
-// per-limb (lo, hi) pairs, and the deferred carry pass is the add kernel itself:
-// r = LO + (HI shifted up one limb).
+// Large products, mad form: work items (output-column block x slice of the
+// contraction range, so every item has about the same work) add their 96-bit column
+// sums into a workspace with 64-bit atomics, and a fold kernel turns the column sums
+// into per-limb (lo, hi) pairs.  MFMA form: the operands are converted to balanced
+// signed digits by one carry scan each; a workgroup owns a band of output columns
+// and runs their whole contraction range (unsplit: exact int32 sums decoded in the
+// epilogue, which writes the per-limb values itself, no atomics) or one slice of it
+// (split: per-slice int32 partials, added by a fold kernel).  Either way the deferred
+// carry pass is the add kernel itself: r = LO + (HI shifted up one limb).
 #include "bn_mul_dev.h"
 
 #include <algorithm>

@@ -186,10 +186,13 @@ bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int 
         if (form == BN_MUL_AUTO && (u64)p.na + p.nb > 128 && (u64)p.na + p.nb <= 256) it.form = BN_MUL_MFMA;
         (it.form == BN_MUL_MFMA ? pl->nmfma : pl->nmad)++;
         pl->work += (u64)p.na * p.nb;
-        if ((u64)p.na + p.nb <= 256)
+        if ((u64)p.na + p.nb <= 256) {
             small.push_back(it);
-        else
+        } else {
             pl->large.push_back(it);
+            pl->ws.work = std::max(pl->ws.work, mul_workspace_bytes(ctx, it.na, it.nb, 1, (int)it.form));
+            pl->ws.status = std::max(pl->ws.status, mul_status_bytes(ctx, it.na, it.nb, 1, (int)it.form));
+        }
     }
     // mad items first, then MFMA items; each group by work, largest first
     std::stable_sort(small.begin(), small.end(), [](const RItem &x, const RItem &y) {

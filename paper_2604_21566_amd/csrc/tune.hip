@@ -161,8 +161,17 @@ extern "C" bn_status bn_probe_rates(bn_ctx *ctx, double *mac96_per_s, double *mf
     return BN_OK;
 }
 
+// The autotuner's own calls may grow the context's workspace (it is synchronous and
+// never captured); the scope ends with the call.
+struct GrowScope {
+    bn_ctx *ctx;
+    explicit GrowScope(bn_ctx *c) : ctx(c) { ctx->grow_scope = true; }
+    ~GrowScope() { ctx->grow_scope = false; }
+};
+
 extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
     if (!ctx) return BN_EINVAL;
+    GrowScope grow(ctx);
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);

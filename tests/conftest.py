@@ -21,15 +21,39 @@ def oracle_mod():
 
 @pytest.fixture(scope="session")
 def bnctx():
-    """A library context on cuda:0 (GPU tests only)."""
+    """A library context on cuda:0 (GPU tests only).  Its compute calls grow the
+    workspace as they need it ("workspace.auto_grow"); tests/test_gpu_workspace.py
+    runs every compute entry point on contexts without it."""
     import torch
     import paper_2604_21566_amd as bn
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    ctx = bn.bn_create(0)
+    ctx = bn.bn_create(0, auto_grow=True)
     yield ctx
     torch.cuda.synchronize()
     bn.bn_destroy(ctx)
+
+
+@pytest.fixture(scope="session")
+def c5_oracle():
+    """The full 64 x 16384-limb product batch (a, b, products) from the oracle, computed
+    once per session, pairs spread over host threads (the ctypes call releases the GIL)."""
+    import concurrent.futures as cf
+    import numpy as np
+    import oracle
+    from paper_2604_21566_amd import workloads as wl
+    n, npairs = 16384, 64
+    a, b = wl.c5()
+    oracle._load()
+    r = np.empty(2 * n * npairs, np.uint64)
+
+    def one(p):
+        r[p * 2 * n:(p + 1) * 2 * n] = oracle.mul(a[p * n:(p + 1) * n], b[p * n:(p + 1) * n])
+
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(one, range(npairs)))
+    return a, b, r
 
 
 def announce(*parts):

@@ -68,7 +68,9 @@ def test_null_context_is_rejected_without_touching_a_device(bn):
     assert L.bn_set_param(None, b"mul.crossover_limbs", 5) == bn.BN_EINVAL
     assert L.bn_lookback_stats(None, None, None, 0) == bn.BN_EINVAL
     assert L.bn_probe_rates(None, None, None, None) == bn.BN_EINVAL
-    assert L.bn_create(None, 0) == bn.BN_EINVAL
+    assert L.bn_create(None, 0, None) == bn.BN_EINVAL
+    assert L.bn_reserve_for(None, bn.BN_OP_MUL, 4, 4, 1, 0, 0) == bn.BN_EINVAL
+    assert L.bn_workspace_size(None, bn.BN_OP_MUL, 4, 4, 1, 0, 0) == 0
     assert L.bn_plan_destroy(None) == bn.BN_OK
     assert L.bn_graph_destroy(None) == bn.BN_OK
     assert L.bn_destroy(None) == bn.BN_OK
@@ -79,7 +81,7 @@ def test_create_without_gfx950_reports_unsupported(bn):
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     ctx = ctypes.c_void_p()
-    assert bn.lib().bn_create(ctypes.byref(ctx), 0) in (bn.BN_EUNSUPPORTED, bn.BN_EINVAL)
+    assert bn.lib().bn_create(ctypes.byref(ctx), 0, None) in (bn.BN_EUNSUPPORTED, bn.BN_EINVAL)
 
 
 def test_product_path_fails_loudly_when_library_missing(tmp_path, monkeypatch):

@@ -310,3 +310,92 @@ def test_lookback_histogram_counts_every_chained_tile(bnctx, op, n, npairs):
     # not recorded with the flag off
     _check(bnctx, op, a, b, n, npairs)
     assert sum(bn.bn_lookback_stats(bnctx)) == 0
+
+
+def _in_place_case(ctx, op, a, b, target):
+    """r == a (target "a") or r == b (target "b") on one pair; returns (r, carry)."""
+    ta, tb = D(a), D(b)
+    c = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    r = ta if target == "a" else tb
+    (bn.bn_add if op == "add" else bn.bn_sub)(ctx, r, ta, tb, c)
+    torch.cuda.synchronize()
+    return H(r), int(H(c)[0])
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("target", ["a", "b"])
+def test_in_place_waits_instead_of_self_help(bnctx, op, target):
+    """In place, a waiting tile must not compute an unpublished predecessor from the
+    operands (that tile may already have overwritten them with sums).  With a spin
+    limit of 0 and the silent-tile-0 debug flag, which force self-help on every wait
+    of an out-of-place call, in-place calls stay exact and the self-help latch stays
+    clear; the same settings out of place still take self-help."""
+    old_spin = bn.bn_get_param(bnctx, "lookback.spin_limit")
+    old_dbg = bn.bn_get_param(bnctx, "debug.flags")
+    try:
+        bn.bn_set_param(bnctx, "lookback.spin_limit", 0)
+        for dbg in (0, 1):
+            bn.bn_set_param(bnctx, "debug.flags", dbg)
+            for worst in (False, True):
+                n = (1 << 18) + 77
+                announce("in place, no self-help", op, f"r={target}", f"n={n}", f"debug={dbg}", f"worst={worst}")
+                a, b = wl.c3(op, n=n, worst=worst)
+                bn.bn_check(bnctx)
+                r, c = _in_place_case(bnctx, op, a, b, target)
+                want, wc = (oracle.add if op == "add" else oracle.sub)(a, b)
+                assert (r == want).all(), f"first bad limb {np.argmax(r != want)}"
+                assert c == wc
+                assert bn.bn_check(bnctx) == 0, "in place must never take self-help"
+        # out of place with the same settings: self-help runs (the latch is set)
+        a, b = wl.c3(op, n=(1 << 18) + 77, worst=True)
+        _check(bnctx, op, a, b, a.size, 1)
+        assert bn.bn_check(bnctx) & 1
+    finally:
+        bn.bn_set_param(bnctx, "debug.flags", old_dbg)
+        bn.bn_set_param(bnctx, "lookback.spin_limit", old_spin)
+
+
+def test_in_place_extras_at_spin_limit_zero(bnctx):
+    """The in-place forms of the add/sub extras (carry-in batch, unequal lengths with
+    r == a, |a - b| with r == a and r == b) at a spin limit of 0."""
+    old = bn.bn_get_param(bnctx, "lookback.spin_limit")
+    g = np.random.default_rng(44)
+    try:
+        bn.bn_set_param(bnctx, "lookback.spin_limit", 0)
+        n, npairs = 100003, 3
+        announce("in-place extras", f"n={n}", f"npairs={npairs}")
+        a = np.full(n * npairs, 2 ** 64 - 1, np.uint64)
+        a[g.integers(0, n * npairs, 5)] = g.integers(0, 2 ** 63, 5, dtype=np.uint64)
+        b = np.zeros(n * npairs, np.uint64)
+        cin = np.array([1, 0, 1], np.uint64)
+        ta, tb, tci = D(a), D(b), D(cin)
+        tco = torch.empty(npairs, dtype=torch.int64, device="cuda")
+        bn.bn_add_nc_n_batch(bnctx, ta, ta, tb, n, npairs, tci, tco)
+        torch.cuda.synchronize()
+        want, wc = oracle.add_nc_batch(a, b, n, cin)
+        assert (H(ta) == want).all() and (H(tco) == wc).all()
+        na, nb = 300007, 200003
+        a = g.integers(0, 2 ** 64 - 1, na, dtype=np.uint64, endpoint=True)
+        a[nb:] = 2 ** 64 - 1
+        b = np.full(nb, 2 ** 64 - 1, np.uint64)
+        ta, tb = D(a), D(b)
+        tc = torch.empty(1, dtype=torch.int64, device="cuda")
+        bn.bn_add_unequal(bnctx, ta, ta, na, tb, nb, tc)
+        torch.cuda.synchronize()
+        bext = np.concatenate([b, np.zeros(na - nb, np.uint64)])
+        want, wc = oracle.add(a, bext)
+        assert (H(ta) == want).all() and int(H(tc)[0]) == wc
+        for target in ("a", "b"):
+            a, b = wl.c3("sub", n=(1 << 18) + 77, worst=True)
+            if target == "b":
+                a, b = b, a   # a < b: the result is b - a
+            ta, tb = D(a), D(b)
+            ts = torch.empty(1, dtype=torch.int64, device="cuda")
+            r = ta if target == "a" else tb
+            bn.bn_sub_abs_n_batch(bnctx, r, ta, tb, a.size, 1, ts)
+            torch.cuda.synchronize()
+            neg = int(oracle.sub(a, b)[1])
+            want = oracle.sub(b, a)[0] if neg else oracle.sub(a, b)[0]
+            assert (H(r) == want).all() and int(H(ts)[0]) == neg, target
+    finally:
+        bn.bn_set_param(bnctx, "lookback.spin_limit", old)

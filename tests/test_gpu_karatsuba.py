@@ -117,15 +117,15 @@ def test_sign_pieces(bnctx, n):
 
 
 @pytest.mark.parametrize("levels", [1, 2])
-def test_c5_full(bnctx, levels):
-    """64 pairs x 16384 limbs (incl. all-ones x all-ones and zero x zero): sampled pairs
-    against the oracle, every pair by residues."""
+def test_c5_full(bnctx, c5_oracle, levels):
+    """64 pairs x 16384 limbs (incl. all-ones x all-ones and zero x zero): every limb of
+    every product against the oracle; residues as an extra check."""
     n, npairs = 16384, 64
-    a, b = wl.c5()
+    a, b, want = c5_oracle
+    announce("C5 full, Karatsuba", f"levels={levels}")
     r = _kmul(bnctx, a, b, n, npairs, levels, "mfma")
-    for p in (0, 1, 2, 63):
-        rr = oracle.mul(a[p * n:(p + 1) * n], b[p * n:(p + 1) * n])
-        assert (r[p * 2 * n:(p + 1) * 2 * n] == rr).all(), f"pair {p}"
+    bad = np.flatnonzero(r != want)
+    assert bad.size == 0, f"{bad.size} limbs differ, first at pair {bad[0] // (2 * n)} limb {bad[0] % (2 * n)}"
     for p in range(npairs):
         A = to_int(a[p * n:(p + 1) * n])
         B = to_int(b[p * n:(p + 1) * n])

@@ -22,7 +22,7 @@ MAX = 2 ** 64 - 1
 def ctx1():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    c = bn.bn_create(0)
+    c = bn.bn_create(0, auto_grow=True)
     bn.bn_set_param(c, "mul.mfma_rows", 1)
     yield c
     torch.cuda.synchronize()

@@ -119,14 +119,15 @@ def _residues_ok(a, b, r, n, npairs):
 
 
 @pytest.mark.parametrize("form", ["mad", "mfma"])
-def test_c5_full(bnctx, form):
-    """64 pairs x 16384 limbs: sampled pairs against the oracle, every pair by residues."""
+def test_c5_full(bnctx, c5_oracle, form):
+    """64 pairs x 16384 limbs (incl. all-ones x all-ones and zero x zero): every limb of
+    every product against the oracle; residues as an extra check."""
     n, npairs = 16384, 64
-    a, b = wl.c5()
+    a, b, want = c5_oracle
+    announce("C5 full", form)
     r = _mul_batch(bnctx, a, b, n, n, npairs, form)
-    for p in (0, 1, 2, 63):
-        rr = oracle.mul(a[p * n:(p + 1) * n], b[p * n:(p + 1) * n])
-        assert (r[p * 2 * n:(p + 1) * 2 * n] == rr).all(), f"pair {p}"
+    bad = np.flatnonzero(r != want)
+    assert bad.size == 0, f"{bad.size} limbs differ, first at pair {bad[0] // (2 * n)} limb {bad[0] % (2 * n)}"
     assert _residues_ok(a, b, r, n, npairs) == -1
 
 
@@ -315,7 +316,7 @@ def test_int32_wrap_decode(bnctx, n):
     wrap).  Pairs 0 and 1 (worst x worst, worst x random) against the oracle, every
     pair by residues."""
     npairs = 64
-    ws = bn.bn_workspace_size(bnctx, 1, n, n, npairs, bn.BN_MUL_MFMA)
+    ws = bn.bn_workspace_size(bnctx, bn.BN_OP_MUL, n, n, npairs, bn.BN_MUL_MFMA)
     # converted operands, their top digits, lo and shifted hi; a split would add at
     # least two slices of int32 column sums (2 * npairs * 8 * 2n * 4 bytes)
     assert ws < 8 * npairs * (n + n + 2 + 2 * 2 * n) + (1 << 20), ws
@@ -363,7 +364,7 @@ def test_graph_survives_workspace_growth(form):
     R = (na + nb) * npairs
     ctx = bn.bn_create(0)
     try:
-        assert bn.bn_workspace_size(ctx, 2, 8192, 8192, 4, fcode) > 2 * bn.bn_workspace_size(ctx, 2, na, nb, npairs, fcode)
+        assert bn.bn_workspace_size(ctx, bn.BN_OP_MUL, 8192, 8192, 4, fcode) > 2 * bn.bn_workspace_size(ctx, bn.BN_OP_MUL, na, nb, npairs, fcode)
         s = torch.cuda.Stream()
         ta, tb = D(a), D(b)
         tr = torch.empty(R, dtype=torch.int64, device="cuda")
@@ -373,12 +374,14 @@ def test_graph_survives_workspace_growth(form):
         gi = bn.bn_graph_capture_batch(ctx, 2, ri, ai, bi, na, nb, npairs, None, form, stream=s)
         try:
             for big in (8192, 16384):
+                # grow the workspace, the status array and the staging buffer
+                bn.bn_reserve_for(ctx, bn.BN_OP_MUL | bn.BN_OP_IN_PLACE, big, big, 4, fcode)
                 x = D(_rand(g0, big * 4))
                 xr = torch.empty(2 * big * 4, dtype=torch.int64, device="cuda")
-                bn.bn_mul_n_batch(ctx, xr, x, x, big, big, 4, form)                        # grows work, status
+                bn.bn_mul_n_batch(ctx, xr, x, x, big, big, 4, form)
                 xs = torch.zeros(2 * big * 4, dtype=torch.int64, device="cuda")
                 xs[:big * 4].copy_(x)
-                bn.bn_mul_n_batch(ctx, xs, xs[:big * 4], x, big, big, 4, form)            # grows the staging
+                bn.bn_mul_n_batch(ctx, xs, xs[:big * 4], x, big, big, 4, form)            # in place
                 torch.cuda.synchronize()
                 tr.fill_(7)
                 buf.zero_()

@@ -29,11 +29,15 @@ def test_autotune_roundtrip(tmp_path):
     table = json.load(open(path))
     for k in KEYS:
         assert table[k] == tuned[k]
-    ctx = bn.bn_create(0)
+    ctx = bn.bn_create(0, tuning=path)   # the table loaded at creation
     try:
-        bn.bn_load_tuning(ctx, path)
         assert {k: bn.bn_get_param(ctx, k) for k in KEYS} == tuned
         # exact results with the tuned table: batched add, one long add, AUTO multiply
+        # (a context without auto_grow: every call's workspace reserved first)
+        bn.bn_reserve_for(ctx, bn.BN_OP_ADDSUB, 64, 0, 3000)
+        bn.bn_reserve_for(ctx, bn.BN_OP_ADDSUB, 1 << 17, 0, 1)
+        for n in (16, 300, 2000):
+            bn.bn_reserve_for(ctx, bn.BN_OP_MUL, n, n, 2, "auto")
         a, b = wl.c2("add", npairs=3000)
         ta, tb = bn.to_device(a), bn.to_device(b)
         tr = torch.empty_like(ta)
@@ -70,7 +74,7 @@ def test_probe_rates_are_plausible(bnctx):
 
 def test_load_tuning_all_or_nothing(tmp_path):
     """A table with a rejected value changes nothing, also the entries before it;
-    a good table applies every entry."""
+    a good table applies every entry.  bn_create refuses a bad table."""
     announce("load tuning: all or nothing")
     ctx = bn.bn_create(0)
     try:
@@ -92,3 +96,7 @@ def test_load_tuning_all_or_nothing(tmp_path):
         assert bn.bn_get_param(ctx, "mul.mfma_rows") == 1
     finally:
         bn.bn_destroy(ctx)
+    for path in (bad, tmp_path / "missing.json"):
+        with pytest.raises(bn.BnError) as e:
+            bn.bn_create(0, tuning=str(path))
+        assert e.value.status == bn.BN_EINVAL

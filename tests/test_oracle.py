@@ -369,3 +369,128 @@ def test_carry_lemmas_k8_golden():
     assert carry.size == gold["total_pairs"]
     wrapped = s % X
     assert ((wrapped < a) == carry).all() and ((wrapped < b) == carry).all()
+
+
+# ----------------------------------------------------------------------------------------
+# ragged addition against CPython int (Theorem 1 per pair; descriptor layout read as stated)
+# ----------------------------------------------------------------------------------------
+def test_add_ragged_vs_int(oracle_mod):
+    """Pairs of uneven length in pooled arrays with gaps between them, offsets not in
+    pair order, n = 0 items, all-ones + 1 pairs (carry out of the top limb) and a
+    zero - one style borrow chain.  The descriptor's nb field is ignored for addition:
+    it is set to a different value here so that reading n from the wrong field fails."""
+    g = np.random.default_rng(2604)
+    lens = [5, 0, 1, 33, 2, 0, 17, 64, 3, 9]
+    ones_pairs = {2, 6}          # a = all ones, b = 1: every limb propagates, carry 1
+    npairs = len(lens)
+    # pools with gaps and a permuted placement of the pairs
+    order = g.permutation(npairs)
+    a_pool = _rand(g, 600)
+    b_pool = _rand(g, 600)
+    desc, A, B = [None] * npairs, [None] * npairs, [None] * npairs
+    a_off, b_off, r_off = 3, 11, 7
+    for p in order:
+        n = lens[p]
+        if p in ones_pairs:
+            a_pool[a_off:a_off + n] = MASK64
+            b_pool[b_off:b_off + n] = 0
+            if n:
+                b_pool[b_off] = 1
+        A[p] = a_pool[a_off:a_off + n].copy()
+        B[p] = b_pool[b_off:b_off + n].copy()
+        desc[p] = (a_off, b_off, r_off, n, n // 2)   # nb field: ignored; differs from n when n > 0
+        a_off += n + 4
+        b_off += n + 1
+        r_off += n + 2
+    r_size = r_off + 5
+    r, c = oracle_mod.add_ragged(a_pool, b_pool, np.array(desc, np.uint64), r_size)
+    assert c.size == npairs
+    written = np.zeros(r_size, bool)
+    for p in range(npairs):
+        n = lens[p]
+        ro = desc[p][2]
+        S = to_int(A[p]) + to_int(B[p])
+        assert to_int(r[ro:ro + n]) == S % (1 << (64 * n)), p
+        assert int(c[p]) == S >> (64 * n), p
+        written[ro:ro + n] = True
+        if p in ones_pairs and n:
+            assert int(c[p]) == 1 and not r[ro:ro + n].any()
+    # limbs outside every pair's result range are untouched (the oracle zero-fills r)
+    assert not r[~written].any()
+
+
+# ----------------------------------------------------------------------------------------
+# planted mistakes: each mutant of the oracle source must fail at least one pin
+# ----------------------------------------------------------------------------------------
+MUTANTS = {
+    "dropped carry": ("c = (uint64_t)(t >> 64);       /* floor((A_i + B_i + c_i)/X) */", "c = 0;"),
+    "wrong borrow": ("br = ((u128)a[i] < need) ? 1u : 0u;\n    }\n    return br;\n}\n\n/*\n * Multiplication",
+                     "br = ((u128)a[i] < (u128)b[i]) ? 1u : 0u;\n    }\n    return br;\n}\n\n/*\n * Multiplication"),
+    "dropped top carry": ("        r[i + nb] = c;\n", "        (void)c;\n"),
+    "stray term": ("u128 t = (u128)a[i] * (u128)b[j] + (u128)r[i + j] + (u128)c;",
+                   "u128 t = (u128)a[i] * (u128)b[j] + (u128)r[i + j] + (u128)c + (u128)(i == 1 && j == 2);"),
+    "ragged add: n from the nb field": (
+        "uint64_t c = bnref_add_n(r_pool + d[2], a_pool + d[0], b_pool + d[1], (size_t)d[3]);",
+        "uint64_t c = bnref_add_n(r_pool + d[2], a_pool + d[0], b_pool + d[1], (size_t)d[4]);"),
+    "ragged add: b and r offsets swapped": (
+        "uint64_t c = bnref_add_n(r_pool + d[2], a_pool + d[0], b_pool + d[1], (size_t)d[3]);",
+        "uint64_t c = bnref_add_n(r_pool + d[1], a_pool + d[0], b_pool + d[2], (size_t)d[3]);"),
+    "ragged mul: lengths swapped": (
+        "bnref_mul(r_pool + d[2], a_pool + d[0], (size_t)d[3], b_pool + d[1], (size_t)d[4]);",
+        "bnref_mul(r_pool + d[2], a_pool + d[0], (size_t)d[4], b_pool + d[1], (size_t)d[3]);"),
+    "carry-in ignored": ("uint64_t c = cin;", "uint64_t c = 0;"),
+}
+
+
+def _pins(mod):
+    """The pins a mutant is run against (the same functions as above)."""
+    checks = [
+        lambda: test_add_sub_specials_exhaustive(mod, 1),
+        lambda: test_add_sub_random_vs_int(mod, 33),
+        lambda: test_carry_in_variants_vs_int(mod, 5),
+        lambda: test_mul_random_vs_int(mod, 13, 29),
+        lambda: test_batch_and_ragged_vs_int(mod),
+        lambda: test_closed_forms(mod, 5),
+        lambda: test_add_ragged_vs_int(mod),
+    ]
+    failed = 0
+    for chk in checks:
+        try:
+            chk()
+        except AssertionError:
+            failed += 1
+    return failed
+
+
+_CHILD = """
+import sys
+sys.path[:0] = {paths!r}
+import oracle
+import test_oracle as T
+oracle._LIB, oracle._SRC, oracle._lib = {so!r}, {src!r}, None
+oracle._load()
+sys.exit(3 if T._pins(oracle) >= 1 else 0)
+"""
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_fails_a_pin(oracle_mod, tmp_path, name):
+    """The mutant runs in a child process (a mistake that writes past a buffer must
+    not corrupt this one); exit status 3 means at least one pin failed on it."""
+    import subprocess
+    import sys
+    src = open(oracle_mod._SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site of {name!r} not found once"
+    mut = tmp_path / "bn_oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", str(mut), "-o", str(so)])
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = _CHILD.format(paths=[os.path.dirname(here), here], so=str(so), src=str(mut))
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert res.returncode == 3, f"planted mistake {name!r}: exit {res.returncode}\n{res.stderr[-2000:]}"
+
+
+def test_unmutated_oracle_passes_the_mutation_pins(oracle_mod):
+    assert _pins(oracle_mod) == 0
