@@ -529,6 +529,7 @@ size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N) {
         int waves = 1, rows = 1;
         bool chain = false;
         flat_scan_shape(ctx, n, N, v == 1, waves, rows, chain);
+        if (!chain) continue;  // independent tiles publish nothing
         const u64 TL = (u64)waves * rows * 128;
         tiles = std::max<u64>(tiles, (N + TL - 1) / TL);
     }

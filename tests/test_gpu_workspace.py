@@ -114,6 +114,7 @@ def _cases():
                 ta = buf[:na * npairs]
                 tr = buf
                 src = D(a)
+                ta.copy_(src)   # run() reloads a first: a refused call then leaves buf as it was
 
                 def run(ctx):
                     ta.copy_(src)
@@ -255,6 +256,29 @@ def test_auto_grow_refuses_growth_during_capture():
         torch.cuda.synchronize()
         bn.bn_add(ctx, tr, ta, tb)   # eager: grows, then exact
         _check((tr,), (oracle.add(a, b)[0],), "eager add after growth")
+    finally:
+        torch.cuda.synchronize()
+        bn.bn_destroy(ctx)
+
+
+@pytest.mark.parametrize("n,npairs", [(4, 1088), (64, 1 << 12), (1, 5000), (128, 33)])
+def test_independent_tile_batches_need_no_workspace(n, npairs):
+    """Batches whose pair length divides the 128-limb tile run as independent tiles:
+    they publish no status words, so a fresh strict context runs them unreserved."""
+    announce("unreserved independent-tile batch", n, npairs)
+    g = np.random.default_rng(n * 7919 + npairs)
+    a, b = _rand(g, n * npairs), _rand(g, n * npairs)
+    ctx = bn.bn_create(0)
+    try:
+        assert bn.bn_workspace_size(ctx, bn.BN_OP_ADDSUB, n, n, npairs) == 0
+        assert bn.bn_workspace_size(ctx, bn.BN_OP_ADDSUB, 3, 3, npairs) > 0   # 3 does not divide 128: chained
+        for op in ("add", "sub"):
+            ta, tb = D(a), D(b)
+            tr = torch.full((n * npairs,), 7, dtype=torch.int64, device="cuda")
+            tc = torch.full((npairs,), 7, dtype=torch.int64, device="cuda")
+            (bn.bn_add_n_batch if op == "add" else bn.bn_sub_n_batch)(ctx, tr, ta, tb, n, npairs, tc)
+            want, wc = (oracle.add_batch if op == "add" else oracle.sub_batch)(a, b, n)
+            _check((tr, tc), (want, wc), f"unreserved {op} {n}x{npairs}")
     finally:
         torch.cuda.synchronize()
         bn.bn_destroy(ctx)
