@@ -155,6 +155,28 @@ bn_status bn_add_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
 bn_status bn_sub_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b,
                          size_t n, size_t npairs, uint64_t *borrow_out, bn_stream stream);
 
+/* For callers that cannot allocate device memory at call time (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc) and will not reserve a
+ * workspace: bn_add_n_batch (sub = 0) or bn_sub_n_batch (sub = 1) with the look-back
+ * status of chained launches kept in a fixed device array of the library, one per GPU,
+ * instead of the context's workspace.  Arguments, results, in-place rules and errors
+ * are those of bn_add_n_batch / bn_sub_n_batch (npairs = 1 is bn_add / bn_sub); the
+ * context supplies the device and the tuned tile shapes only, and its workspace is
+ * neither used nor grown.  The call allocates nothing and never synchronises.
+ * Limit: the array holds BN_SCRATCH_MAX_TILES status words (about 1 MiB per GPU, held
+ * until the process ends), one per workgroup tile of a chained launch: with the default
+ * shapes, one pair of up to 2^28 limbs (2 GiB per operand) -- batches whose pair length
+ * divides 128 need no status words and have no such limit.  A launch that could need
+ * more (at either operand alignment) returns BN_ERANGE with nothing enqueued.
+ * The array is shared by every call on that GPU, from any context, and keeps the last
+ * call's contents (each chained launch tags its words with an epoch of its own, so no
+ * clearing is needed): calls that overlap in time on one GPU race and must be ordered
+ * (one stream, or events).  BN_EINVAL if sub is not 0 or 1; BN_EUNSUPPORTED if the
+ * context's device has no such array (device index 64 or above). */
+#define BN_SCRATCH_MAX_TILES (1u << 17)
+bn_status bn_addsub_n_batch_noalloc(bn_ctx *ctx, int sub, uint64_t *r, const uint64_t *a, const uint64_t *b,
+                                    size_t n, size_t npairs, uint64_t *carry_out, bn_stream stream);
+
 /* With a carry (borrow) into limb 0 of every pair: the c_in of Algorithm 1's W-limb
  * step (Sec. 3.1), which chains additions of more limbs than one call holds.
  * r_p = (a_p + b_p + cin_p) mod 2^(64n), carry_out[p] = the carry out; sub:

@@ -81,6 +81,7 @@ _PROTOS = {
     "bn_sub": (_i, [_vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "bn_add_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
     "bn_sub_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
+    "bn_addsub_n_batch_noalloc": (_i, [_vp, _i, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
     "bn_add_nc_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp, _vp]),
     "bn_sub_nc_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp, _vp]),
     "bn_add_unequal": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _vp, _vp]),
@@ -278,6 +279,18 @@ def bn_sub_n_batch(ctx, r, a, b, n: int, npairs: int, borrow_out=None, stream=No
     _ck(lib().bn_sub_n_batch(ctx, _ptr(r, "r", N), _ptr(a, "a", N), _ptr(b, "b", N), n, npairs,
                              _ptr(borrow_out, "borrow", npairs),
                              _stream(stream)), "bn_sub_n_batch")
+
+
+BN_SCRATCH_MAX_TILES = 1 << 17
+
+
+def bn_addsub_n_batch_noalloc(ctx, sub: int, r, a, b, n: int, npairs: int, carry_out=None, stream=None):
+    """bn_add_n_batch (sub=0) / bn_sub_n_batch (sub=1) with the look-back state in the
+    library's fixed per-GPU array: no allocation, no workspace."""
+    N = n * npairs
+    _ck(lib().bn_addsub_n_batch_noalloc(ctx, int(sub), _ptr(r, "r", N), _ptr(a, "a", N), _ptr(b, "b", N), n,
+                                        npairs, _ptr(carry_out, "carry", npairs), _stream(stream)),
+        "bn_addsub_n_batch_noalloc")
 
 
 # ------------------------------------------------------------------ multiply ----

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbn.so")
-SOURCES = ["bn_api.hip", "k_addsub.hip", "k_addsub_ext.hip", "k_mul.hip", "k_karatsuba.hip", "k_ragged.hip", "tune.hip"]
+SOURCES = ["bn_api.hip", "k_addsub.hip", "k_addsub_ext.hip", "k_mul.hip", "k_karatsuba.hip", "k_ragged.hip", "tune.hip",
+           "scratch.hip"]
 
 HOST_LIB = os.path.join(HERE, "libbn_host.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

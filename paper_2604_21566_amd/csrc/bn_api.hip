@@ -179,6 +179,11 @@ bn_status bn_create(bn_ctx **out, int device, const char *tuning_json) {
         delete ctx;
         return BN_EHIP;
     }
+    if (scratch_setup(device) != BN_OK) {  // once per device: the no-allocation entry point's array
+        (void)hipFree(ctx->ctl);
+        delete ctx;
+        return BN_EHIP;
+    }
     if (tuning_json) {
         const bn_status st = load_tuning(ctx, tuning_json);
         if (st != BN_OK) {
@@ -257,8 +262,9 @@ bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags) {
 }
 
 // --------------------------------------------------------------- add / sub ----
+// fixed: look-back state in the per-GPU scratch array instead of the context's workspace
 static bn_status addsub(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
-                        size_t npairs, uint64_t *carry, bn_stream stream) {
+                        size_t npairs, uint64_t *carry, bn_stream stream, const ScanMem *fixed = nullptr) {
     if (!ctx) return BN_EINVAL;
     size_t N;
     if (mul_overflow(n, npairs, &N) || N > BN_MAX_LIMBS) return BN_ERANGE;
@@ -271,6 +277,10 @@ static bn_status addsub(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, c
                   overlaps(carry, npairs * 8, b, bytes)))
         return BN_EALIAS;
     DeviceGuard g(ctx->device);
+    if (fixed) {  // the status words of either operand alignment must fit the array
+        if (flat_scan_status_bytes(ctx, n, N) > fixed->max_tiles * sizeof(u64)) return BN_ERANGE;
+        return launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, nullptr, false, 0, carry, S(stream), fixed);
+    }
     if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_ADDSUB, n, n, npairs, 0, 0, false), S(stream))) != BN_OK)
         return st;
     return launch_flat_scan(ctx, sub, r, a, b, n, npairs, carry, S(stream));
@@ -321,6 +331,14 @@ bn_status bn_add_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
 bn_status bn_sub_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,
                          uint64_t *borrow_out, bn_stream stream) {
     return addsub(ctx, true, r, a, b, n, npairs, borrow_out, stream);
+}
+
+bn_status bn_addsub_n_batch_noalloc(bn_ctx *ctx, int sub, uint64_t *r, const uint64_t *a, const uint64_t *b,
+                                     size_t n, size_t npairs, uint64_t *carry_out, bn_stream stream) {
+    if (!ctx || (sub != 0 && sub != 1)) return BN_EINVAL;
+    ScanMem m;
+    if (!scratch_mem(ctx->device, &m)) return BN_EUNSUPPORTED;
+    return addsub(ctx, sub != 0, r, a, b, n, npairs, carry_out, stream, &m);
 }
 
 bn_status bn_add_nc_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, size_t npairs,

@@ -155,6 +155,13 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
                                const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s,
                                const ScanMem *fixed);
 
+// ---- the fixed per-GPU scratch array (scratch.hip) ----
+// Once per device, with that device current (bn_create): take the array's device
+// address and clear it.  Devices past the table are skipped (BN_OK).
+bn_status scratch_setup(int device);
+// The look-back state in that device's array; false if the device was never set up.
+bool scratch_mem(int device, ScanMem *m);
+
 // ---- add/sub extras (k_addsub_ext.hip) ----
 bn_status launch_addsub_nc(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                            const u64 *cin, u64 *carry, hipStream_t s);
