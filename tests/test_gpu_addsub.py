@@ -86,9 +86,17 @@ def test_c2_full(bnctx, op):
 
 
 @pytest.mark.parametrize("op", ["add", "sub"])
-@pytest.mark.parametrize("worst", [False, True])
-def test_c3_full(bnctx, op, worst):
-    a, b = wl.c3(op, worst=worst)
+@pytest.mark.parametrize("kind", ["runs", "worst", "propagate0"])
+def test_c3_full(bnctx, op, kind):
+    """2^26 limbs: random with carry runs, the carry crossing every limb, and every limb
+    propagating with no carry entering anywhere (every tile but the first is an
+    all-propagate tile whose carry-in is 0)."""
+    if kind == "propagate0":
+        n = 1 << 26
+        a = np.full(n, 2 ** 64 - 1 if op == "add" else 5, np.uint64)
+        b = np.zeros(n, np.uint64) if op == "add" else a.copy()
+    else:
+        a, b = wl.c3(op, worst=kind == "worst")
     _check(bnctx, op, a, b, a.size, 1)
 
 
