@@ -87,7 +87,8 @@ bn_status bn_reserve(bn_ctx *ctx, size_t bytes);
 /* The calls that take workspace, for bn_reserve_for / bn_workspace_size: */
 #define BN_OP_ADDSUB 0          /* bn_add, bn_sub (npairs = 1), bn_add_n_batch, bn_sub_n_batch: na = n */
 #define BN_OP_ADDSUB_NC 1       /* bn_add_nc_n_batch, bn_sub_nc_n_batch: na = n */
-#define BN_OP_ADDSUB_UNEQUAL 2  /* bn_add_unequal, bn_sub_unequal (npairs = 1): na, nb */
+#define BN_OP_ADDSUB_UNEQUAL 2  /* bn_add_unequal, bn_sub_unequal (npairs = 1), bn_add_unequal_n_batch,
+                                   bn_sub_unequal_n_batch: na, nb */
 #define BN_OP_SUB_ABS 3         /* bn_sub_abs_n_batch: na = n */
 #define BN_OP_MUL 4             /* bn_mul (npairs = 1), bn_mul_n_batch: na, nb, form */
 #define BN_OP_MUL_KARATSUBA 5   /* bn_mul_karatsuba_n_batch: na = n, form, levels */
@@ -191,13 +192,26 @@ bn_status bn_sub_nc_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const u
 
 /* Unequal lengths (na >= nb, else BN_EINVAL): r[0, na) = a + b with b zero-extended
  * (the shorter operand padded with zero limbs, as in the proof of Theorem 2), carry
- * out in *carry_out; sub: r = (a - b) mod 2^(64 na) and the borrow.  The low nb limbs
- * are one scan, the carry then runs through a's top na - nb limbs (a second scan with
- * b = 0 and the carry as carry-in).  r may equal a exactly (or b when na == nb). */
+ * out in *carry_out; sub: r = (a - b) mod 2^(64 na) and the borrow.  One scan whose b
+ * reads as zero past nb limbs (bn_add_unequal_n_batch with one pair).  r may equal a
+ * exactly (or b when na == nb). */
 bn_status bn_add_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
                          uint64_t *carry_out, bn_stream stream);
 bn_status bn_sub_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
                          uint64_t *borrow_out, bn_stream stream);
+
+/* Unequal lengths, batched: pair p is a + p*na, b + p*nb (na >= nb, else BN_EINVAL) and
+ * r + p*na; r_p = (a_p + b_p) mod 2^(64 na) with b_p zero-extended to na limbs (the
+ * shorter operand padded with zero limbs, as in the proof of Theorem 2) and
+ * carry_out[p] its carry (device, npairs uint64, may be NULL); sub: r_p = (a_p - b_p)
+ * mod 2^(64 na) and the borrow.  One pass of the scan: b's limbs are read by pair
+ * position and count as zero past nb.  r may equal a exactly (or b when na == nb).
+ * Workspace: bn_reserve_for(BN_OP_ADDSUB_UNEQUAL, na, nb, npairs) when pairs cross
+ * workgroup tiles (na not dividing 128); BN_ENOSPACE if short. */
+bn_status bn_add_unequal_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
+                                 size_t nb, size_t npairs, uint64_t *carry_out, bn_stream stream);
+bn_status bn_sub_unequal_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
+                                 size_t nb, size_t npairs, uint64_t *borrow_out, bn_stream stream);
 
 /* r_p = |a_p - b_p| and sign[p] = [a_p < b_p] (device, may be NULL): the signed
  * difference the Karatsuba step needs (App. A, Algorithm 4).  b - a goes to the

@@ -86,6 +86,8 @@ _PROTOS = {
     "bn_sub_nc_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp, _vp]),
     "bn_add_unequal": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _vp, _vp]),
     "bn_sub_unequal": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _vp, _vp]),
+    "bn_add_unequal_n_batch": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _sz, _vp, _vp]),
+    "bn_sub_unequal_n_batch": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _sz, _vp, _vp]),
     "bn_sub_abs_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _vp, _vp]),
     "bn_mul": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _i, _vp]),
     "bn_mul_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _sz, _i, _vp]),
@@ -335,6 +337,19 @@ def bn_sub_unequal(ctx, r, a, na: int, b, nb: int, borrow_out=None, stream=None)
     _ck(lib().bn_sub_unequal(ctx, _ptr(r, "r", na), _ptr(a, "a", na), na, _ptr(b, "b", nb), nb,
                              _ptr(borrow_out, "borrow_out", 1),
                              _stream(stream)), "bn_sub_unequal")
+
+
+def bn_add_unequal_n_batch(ctx, r, a, na: int, b, nb: int, npairs: int, carry_out=None, stream=None):
+    """Pair p: a[p na:(p+1) na] + b[p nb:(p+1) nb] (zero-extended) -> r[p na:(p+1) na]."""
+    _ck(lib().bn_add_unequal_n_batch(ctx, _ptr(r, "r", na * npairs), _ptr(a, "a", na * npairs), na,
+                                     _ptr(b, "b", nb * npairs), nb, npairs, _ptr(carry_out, "carry_out", npairs),
+                                     _stream(stream)), "bn_add_unequal_n_batch")
+
+
+def bn_sub_unequal_n_batch(ctx, r, a, na: int, b, nb: int, npairs: int, borrow_out=None, stream=None):
+    _ck(lib().bn_sub_unequal_n_batch(ctx, _ptr(r, "r", na * npairs), _ptr(a, "a", na * npairs), na,
+                                     _ptr(b, "b", nb * npairs), nb, npairs, _ptr(borrow_out, "borrow_out", npairs),
+                                     _stream(stream)), "bn_sub_unequal_n_batch")
 
 
 def bn_sub_abs_n_batch(ctx, r, a, b, n: int, npairs: int, sign=None, stream=None):

@@ -352,33 +352,47 @@ bn_status bn_sub_nc_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const u
 }
 
 static bn_status addsub_unequal(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
-                                size_t nb, uint64_t *carry, bn_stream stream) {
+                                size_t nb, size_t npairs, uint64_t *carry, bn_stream stream) {
     if (!ctx) return BN_EINVAL;
     if (na < nb) return BN_EINVAL;
-    if (na > BN_MAX_LIMBS) return BN_ERANGE;
+    size_t NA, NB;
+    if (mul_overflow(na, npairs, &NA) || NA > BN_MAX_LIMBS) return BN_ERANGE;
+    NB = nb * npairs;  // nb <= na: cannot overflow
     bn_status st;
-    if ((st = check_ptr(r, na)) || (st = check_ptr(a, na)) || (st = check_ptr(b, nb))) return st;
+    if ((st = check_ptr(r, NA)) || (st = check_ptr(a, NA)) || (st = check_ptr(b, NB))) return st;
     if (carry && ((uintptr_t)carry & 7u)) return BN_EINVAL;
     // r may be a exactly, or b exactly when the lengths are equal
-    if ((r != a && overlaps(r, na * 8, a, na * 8)) || (!(r == b && na == nb) && overlaps(r, na * 8, b, nb * 8)))
+    if ((r != a && overlaps(r, NA * 8, a, NA * 8)) || (!(r == b && na == nb) && overlaps(r, NA * 8, b, NB * 8)))
         return BN_EALIAS;
-    if (carry && (overlaps(carry, 8, r, na * 8) || overlaps(carry, 8, a, na * 8) || overlaps(carry, 8, b, nb * 8)))
+    if (carry && (overlaps(carry, npairs * 8, r, NA * 8) || overlaps(carry, npairs * 8, a, NA * 8) ||
+                  overlaps(carry, npairs * 8, b, NB * 8)))
         return BN_EALIAS;
     DeviceGuard g(ctx->device);
-    if (na == 0) return carry ? launch_fill_u64(carry, 1, 0, S(stream)) : BN_OK;
-    if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_ADDSUB_UNEQUAL, na, nb, 1, 0, 0, false), S(stream))) != BN_OK)
+    if (NA == 0) return carry && npairs ? launch_fill_u64(carry, npairs, 0, S(stream)) : BN_OK;
+    if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_ADDSUB_UNEQUAL, na, nb, npairs, 0, 0, false), S(stream))) !=
+        BN_OK)
         return st;
-    return launch_addsub_unequal(ctx, sub, r, a, na, b, nb, carry, S(stream));
+    return launch_addsub_unequal(ctx, sub, r, a, na, b, nb, npairs, carry, S(stream));
 }
 
 bn_status bn_add_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
                          uint64_t *carry_out, bn_stream stream) {
-    return addsub_unequal(ctx, false, r, a, na, b, nb, carry_out, stream);
+    return addsub_unequal(ctx, false, r, a, na, b, nb, 1, carry_out, stream);
 }
 
 bn_status bn_sub_unequal(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b, size_t nb,
                          uint64_t *borrow_out, bn_stream stream) {
-    return addsub_unequal(ctx, true, r, a, na, b, nb, borrow_out, stream);
+    return addsub_unequal(ctx, true, r, a, na, b, nb, 1, borrow_out, stream);
+}
+
+bn_status bn_add_unequal_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
+                                 size_t nb, size_t npairs, uint64_t *carry_out, bn_stream stream) {
+    return addsub_unequal(ctx, false, r, a, na, b, nb, npairs, carry_out, stream);
+}
+
+bn_status bn_sub_unequal_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
+                                 size_t nb, size_t npairs, uint64_t *borrow_out, bn_stream stream) {
+    return addsub_unequal(ctx, true, r, a, na, b, nb, npairs, borrow_out, stream);
 }
 
 bn_status bn_sub_abs_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,

@@ -29,9 +29,7 @@ constexpr int LOOKBACK_BINS = 32;
 struct ScanCtl {
     u64 epoch;                // look-back epoch of launches recorded into graphs
     u64 err;                  // latched device events (bit 0: a look-back computed a predecessor itself)
-    u64 carry_tmp;            // carry between the two passes of an unequal-length add/sub
-    u64 zero;                 // always 0 (a carry-in of zero)
-    u64 pad[4];
+    u64 pad[6];
     u64 hist[LOOKBACK_BINS];  // look-back distances, recorded when debug flag bit 1 is set
 };
 
@@ -151,9 +149,14 @@ struct ScanMem {
     std::atomic<u64> *host_epoch = nullptr;  // epochs of launches outside a capture
     u32 dbg_mask = ~0u;                      // debug flags that apply
 };
+// nbz >= 0: b holds nbz limbs per pair (its pair stride) and reads as zero past them.
 bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                                const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s,
-                               const ScanMem *fixed);
+                               const ScanMem *fixed, i64 nbz = -1);
+// Unequal lengths, batched: pair p is a + p na, b + p nb (nb <= na), r + p na, and
+// r_p = a_p +- b_p with b_p zero-extended to na limbs; one pass.
+bn_status launch_flat_scan_bzx(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,
+                               u64 npairs, u64 *carry, hipStream_t s);
 
 // ---- the fixed per-GPU scratch array (scratch.hip) ----
 // Once per device, with that device current (bn_create): take the array's device
@@ -166,7 +169,7 @@ bool scratch_mem(int device, ScanMem *m);
 bn_status launch_addsub_nc(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                            const u64 *cin, u64 *carry, hipStream_t s);
 bn_status launch_addsub_unequal(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,
-                                u64 *carry, hipStream_t s);
+                                u64 npairs, u64 *carry, hipStream_t s);
 WsNeed unequal_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs);
 bn_status launch_sub_abs(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *sign,
                          hipStream_t s);

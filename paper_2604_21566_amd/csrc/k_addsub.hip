@@ -95,12 +95,23 @@ struct ScanGeom {
     u64 nseg;        // segments (pairs)
     u64 bval;        // EXT_BCONST: the value of every limb of b
     u32 no_self_help;  // 1 when r overlaps a or b: a waiting tile never reads another tile's operands
+    u64 nbz;           // EXT_BZX: limbs of b per pair (b's pair stride); b reads as 0 past them
 };
 
-// Kernel variants beyond the plain a +- b: a per-segment carry-in, and b given as one
-// limb value repeated (b = 0: the carry-in alone propagates through a; b = 0x80...80:
-// the balanced-digit conversion of a product's operands).
-constexpr int EXT_CIN = 1, EXT_BCONST = 2;
+// Kernel variants beyond the plain a +- b: a per-segment carry-in, b given as one limb
+// value repeated (b = 0: the carry-in alone propagates through a; b = 0x80...80: the
+// balanced-digit conversion of a product's operands), and b shorter than a in every
+// pair (its own pair stride nbz, zero-extended to the segment length: the unequal
+// lengths of the proof of Theorem 2).
+constexpr int EXT_CIN = 1, EXT_BCONST = 2, EXT_BZX = 4;
+
+// Limb of b that meets limb idx = q n + pos of a.
+template <int EXT>
+__device__ __forceinline__ u64 b_limb(const u64 *__restrict__ b, const ScanGeom &G, u64 idx, u64 q, u64 pos) {
+    if constexpr ((EXT & EXT_BCONST) != 0) return G.bval;
+    if constexpr ((EXT & EXT_BZX) != 0) return pos < G.nbz ? b[q * G.nbz + pos] : 0ull;
+    return b[idx];
+}
 
 template <int EXT>
 __device__ __forceinline__ bool seg_cin(const ScanGeom &G, u64 q) {
@@ -124,9 +135,10 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
         divmod_u64(i0, G.n, G.nshift, q, pos);
         bool g0 = false, p0 = false, g1 = false, p1 = false;
         u64 s;
-        const bool bc = (EXT & EXT_BCONST) != 0;
-        if (i0 < hi) limb_gp<SUB>(a[i0], bc ? G.bval : b[i0], s, g0, p0);
-        if (i0 + 1 < hi) limb_gp<SUB>(a[i0 + 1], bc ? G.bval : b[i0 + 1], s, g1, p1);
+        const bool wrap = pos + 1 == G.n;  // limb i0 + 1 starts the next segment
+        if (i0 < hi) limb_gp<SUB>(a[i0], b_limb<EXT>(b, G, i0, q, pos), s, g0, p0);
+        if (i0 + 1 < hi)
+            limb_gp<SUB>(a[i0 + 1], b_limb<EXT>(b, G, i0 + 1, wrap ? q + 1 : q, wrap ? 0 : pos + 1), s, g1, p1);
         // a segment's first limb takes the segment's carry-in, not its neighbour's carry
         g0 = g0 || (pos == 0 && p0 && seg_cin<EXT>(G, q));
         g1 = g1 || (pos + 1 == G.n && i0 + 1 < hi && p1 && seg_cin<EXT>(G, q + 1));
@@ -234,7 +246,33 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     const bool full = VEC && (t + 1) * TL <= N;
     u64 x0[ROWS], x1[ROWS], y0[ROWS], y1[ROWS];
     constexpr bool BC = (EXT & EXT_BCONST) != 0;
-    if (full) {
+    if constexpr ((EXT & EXT_BZX) != 0) {
+        // b limbs by segment position (8-byte loads; consecutive lanes still read
+        // consecutive limbs inside a pair)
+        u64 q, pos;
+        divmod_u64(idx0, n, G.nshift, q, pos);
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const u64 idx = idx0 + (u64)j * 128;
+            if (full) {
+                const u64v2 va = __builtin_nontemporal_load(reinterpret_cast<const u64v2 *>(a + idx));
+                x0[j] = va.x;
+                x1[j] = va.y;
+            } else {
+                x0[j] = idx < N ? a[idx] : 0;
+                x1[j] = idx + 1 < N ? a[idx + 1] : 0;
+            }
+            const bool wrap = pos + 1 == n;
+            y0[j] = idx < N ? b_limb<EXT>(b, G, idx, q, pos) : 0;
+            y1[j] = idx + 1 < N ? b_limb<EXT>(b, G, idx + 1, wrap ? q + 1 : q, wrap ? 0 : pos + 1) : 0;
+            pos += step_mod;
+            q += step_div;
+            if (pos >= n) {
+                pos -= n;
+                q += 1;
+            }
+        }
+    } else if (full) {
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const u64v2 va = __builtin_nontemporal_load(reinterpret_cast<const u64v2 *>(a + idx0 + (u64)j * 128));
@@ -567,11 +605,13 @@ static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
 }
 
 bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
-                             const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s, const ScanMem *fixed) {
+                             const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s, const ScanMem *fixed,
+                             i64 nbz) {
     const u64 N = n * npairs;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
-    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst ? nullptr : b)) & 15u) == 0;
-    const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0);
+    const bool bzx = nbz >= 0;
+    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst || bzx ? nullptr : b)) & 15u) == 0;
+    const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0) | (bzx ? EXT_BZX : 0);
     int waves, rows;
     bool chain;
     if (ext == 0) {
@@ -603,6 +643,8 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         f = sub ? pick_ext<true, EXT_CIN | EXT_BCONST>(vec, chain) : pick_ext<false, EXT_CIN | EXT_BCONST>(vec, chain);
     else if (ext == EXT_BCONST && !sub)
         f = pick_ext<false, EXT_BCONST>(vec, chain, rows);
+    else if (ext == EXT_BZX)
+        f = sub ? pick_ext<true, EXT_BZX>(vec, chain) : pick_ext<false, EXT_BZX>(vec, chain);
     else if (ext != 0)
         return BN_EINVAL;
     else if (vec)
@@ -624,8 +666,9 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     u64 epoch = 0;
     if (chain && !captured) epoch = fixed ? fixed->host_epoch->fetch_add(1) + 1 : ++ctx->host_epoch;
     // r overlapping an operand: a waiting tile must not read another tile's operands
-    const bool inplace = ranges_overlap(r, N, a, N) || (!bconst && ranges_overlap(r, N, b, N));
-    ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u};
+    const bool inplace =
+        ranges_overlap(r, N, a, N) || (!bconst && ranges_overlap(r, N, b, bzx ? (u64)nbz * npairs : N));
+    ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u, bzx ? (u64)nbz : 0};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     u32 dbg = ctx->tune.debug_flags & (fixed ? fixed->dbg_mask : ~0u);
     if (inplace) dbg &= ~1u;
@@ -641,7 +684,12 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
 
 bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                                const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s) {
-    return launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, cin, bconst, bval, carry, s, nullptr);
+    return launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, cin, bconst, bval, carry, s, nullptr, -1);
+}
+
+bn_status launch_flat_scan_bzx(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,
+                               u64 npairs, u64 *carry, hipStream_t s) {
+    return launch_flat_scan_mem(ctx, sub, r, a, b, na, npairs, nullptr, false, 0, carry, s, nullptr, (i64)nb);
 }
 
 bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, u64 *carry,

@@ -1,6 +1,6 @@
 // k_addsub_ext.hip -- add/sub beyond equal-length pairs without carry-in: a carry
 // (borrow) into limb 0, unequal operand lengths, and |a - b| with its sign.  All of
-// them run on the flat scan kernel (its carry-in and b = 0 variants) plus one
+// them run on the flat scan kernel (its carry-in and zero-extended-b variants) plus one
 // streaming select kernel.
 #include "bn_internal.h"
 
@@ -22,27 +22,20 @@ bn_status launch_addsub_nc(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
     return launch_flat_scan_ext(ctx, sub, r, a, b, n, npairs, cin, false, 0, carry, s);
 }
 
-// r[0, na) = a +- b with b zero-extended to na limbs (na >= nb): the low nb limbs
-// as a plain pair, then the carry (borrow) through a's remaining limbs.
+// r_p[0, na) = a_p +- b_p with b_p zero-extended to na limbs (na >= nb), for every
+// pair: equal lengths take the plain scan, otherwise one pass of the scan whose b
+// reads as zero past nb limbs per pair.
 bn_status launch_addsub_unequal(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,
-                                u64 *carry, hipStream_t s) {
-    u64 *tmp = &ctx->ctl->carry_tmp;
-    const u64 *zero = &ctx->ctl->zero;
-    bn_status st;
-    if (na == nb) return launch_flat_scan(ctx, sub, r, a, b, na, 1, carry, s);
-    if (nb > 0 && (st = launch_flat_scan(ctx, sub, r, a, b, nb, 1, tmp, s)) != BN_OK) return st;
-    return launch_flat_scan_ext(ctx, sub, r + nb, a + nb, nullptr, na - nb, 1, nb > 0 ? tmp : zero, true, 0, carry, s);
+                                u64 npairs, u64 *carry, hipStream_t s) {
+    if (na == nb) return launch_flat_scan(ctx, sub, r, a, b, na, npairs, carry, s);
+    return launch_flat_scan_bzx(ctx, sub, r, a, na, b, nb, npairs, carry, s);
 }
 
-// Status words of the two scans of an unequal-length add/sub (one pair).
+// Status words of an unequal-length add/sub batch.
 WsNeed unequal_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs) {
     WsNeed w;
     if (npairs == 0 || na == 0) return w;
-    if (na == nb) {
-        w.status = flat_scan_status_bytes(ctx, na, na * npairs);
-        return w;
-    }
-    w.status = std::max(flat_scan_status_bytes(ctx, nb, nb * npairs), flat_scan_ext_status_bytes(na - nb, (na - nb) * npairs));
+    w.status = na == nb ? flat_scan_status_bytes(ctx, na, na * npairs) : flat_scan_ext_status_bytes(na, na * npairs);
     return w;
 }
 

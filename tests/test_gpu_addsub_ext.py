@@ -129,3 +129,67 @@ def test_errors(bnctx):
     bn.bn_add_nc_n_batch(bnctx, t[:0], t[:0], t[:0], 0, 4, cin, out)
     torch.cuda.synchronize()
     assert H(out).tolist() == [1, 0, 1, 1]
+
+
+def _unequal_operands(g, na, nb, npairs, op):
+    """Pairs of na and nb limbs; every second pair makes its carry (borrow) run from b's
+    top limb through all of a's limbs above it (b all-ones or a zero there)."""
+    a = _rand(g, na * npairs).reshape(npairs, na)
+    b = _rand(g, nb * npairs).reshape(npairs, nb)
+    for p in range(0, npairs, 2):
+        if op == "add":
+            a[p, nb:] = MAX
+            if nb:
+                b[p, :] = MAX
+                a[p, :nb] = 1
+        else:
+            a[p, nb:] = 0
+            if nb:
+                a[p, :nb] = 0
+                b[p, 0] = 1
+    bext = np.zeros((npairs, na), np.uint64)
+    bext[:, :nb] = b
+    return a.reshape(-1), b.reshape(-1), bext.reshape(-1)
+
+
+UNEQUAL = [(4, 1, 1088), (64, 10, 4096), (100, 100, 77), (129, 64, 33), (5000, 37, 7), (100003, 70001, 3),
+           (7, 0, 100), (128, 127, 50), (1, 1, 10), (300, 1, 31), (4096, 4095, 5), (262147, 3, 2)]
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("na,nb,npairs", UNEQUAL)
+def test_unequal_batches(bnctx, op, na, nb, npairs):
+    """Theorem 2's zero-extension: a_p +- b_p with b_p padded to na limbs, bit-exact
+    against the oracle's equal-length batch on the padded operands."""
+    announce("unequal batch", op, f"na={na}", f"nb={nb}", f"npairs={npairs}")
+    g = np.random.default_rng(na * 31 + nb * 7 + npairs)
+    a, b, bext = _unequal_operands(g, na, nb, npairs, op)
+    rr, rc = (oracle.add_batch if op == "add" else oracle.sub_batch)(a, bext, na)
+    f = bn.bn_add_unequal_n_batch if op == "add" else bn.bn_sub_unequal_n_batch
+    for offset in (0, 1):   # 16-byte and 8-byte aligned operands
+        ta = D(np.concatenate([np.zeros(offset, np.uint64), a]))[offset:]
+        tb = D(np.concatenate([np.zeros(offset, np.uint64), b]))[offset:] if nb else \
+            torch.zeros(1, dtype=torch.int64, device="cuda")
+        tr = torch.full((na * npairs + offset,), -1, dtype=torch.int64, device="cuda")[offset:]
+        tc = torch.full((npairs,), -1, dtype=torch.int64, device="cuda")
+        f(bnctx, tr, ta, na, tb, nb, npairs, tc)
+        torch.cuda.synchronize()
+        got = H(tr)
+        assert (got == rr).all(), f"offset {offset}: first bad limb {np.argmax(got != rr)}"
+        assert (H(tc) == rc).all(), f"offset {offset}: first bad carry {np.argmax(H(tc) != rc)}"
+        # in place over a
+        f(bnctx, ta, ta, na, tb, nb, npairs, tc)
+        torch.cuda.synchronize()
+        assert (H(ta) == rr).all() and (H(tc) == rc).all(), f"in place, offset {offset}"
+
+
+def test_unequal_batch_rejects_bad_arguments(bnctx):
+    g = np.random.default_rng(1)
+    a, b = D(_rand(g, 40)), D(_rand(g, 40))
+    r = torch.empty(40, dtype=torch.int64, device="cuda")
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_add_unequal_n_batch(bnctx, r, a, 4, b, 5, 8)     # nb > na
+    assert e.value.status == bn.BN_EINVAL
+    with pytest.raises(bn.BnError) as e:
+        bn.bn_add_unequal_n_batch(bnctx, b, a, 5, b, 4, 8)   # r is b while the lengths differ
+    assert e.value.status == bn.BN_EALIAS

@@ -85,6 +85,25 @@ def _cases():
     for op in ("add", "sub"):
         cases.append((f"bn_{op}_unequal", (bn.BN_OP_ADDSUB_UNEQUAL, 70001, 50021, 1), unequal(op)))
 
+    def unequal_batch(op):
+        na, nb, npairs = 30011, 20011, 4
+        a = _rand(g, na * npairs)
+        b = _rand(g, nb * npairs)
+        bext = np.zeros((npairs, na), np.uint64)
+        bext[:, :nb] = b.reshape(npairs, nb)
+        want, wc = (oracle.add_batch if op == "add" else oracle.sub_batch)(a, bext.reshape(-1), na)
+
+        def make():
+            ta, tb = D(a), D(b)
+            tr = torch.full((na * npairs,), 7, dtype=torch.int64, device="cuda")
+            tc = torch.full((npairs,), 7, dtype=torch.int64, device="cuda")
+            f = bn.bn_add_unequal_n_batch if op == "add" else bn.bn_sub_unequal_n_batch
+            return (lambda ctx: f(ctx, tr, ta, na, tb, nb, npairs, tc)), (tr, tc), (want, wc)
+        return make
+
+    for op in ("add", "sub"):
+        cases.append((f"bn_{op}_unequal_n_batch", (bn.BN_OP_ADDSUB_UNEQUAL, 30011, 20011, 4), unequal_batch(op)))
+
     def sub_abs():
         n, npairs = 3001, 4
         a, b = _rand(g, n * npairs), _rand(g, n * npairs)
