@@ -91,7 +91,8 @@ bn_status bn_reserve(bn_ctx *ctx, size_t bytes);
                                    bn_sub_unequal_n_batch: na, nb */
 #define BN_OP_SUB_ABS 3         /* bn_sub_abs_n_batch: na = n */
 #define BN_OP_MUL 4             /* bn_mul (npairs = 1), bn_mul_n_batch: na, nb, form */
-#define BN_OP_MUL_KARATSUBA 5   /* bn_mul_karatsuba_n_batch: na = n, form, levels */
+#define BN_OP_MUL_KARATSUBA 5   /* bn_mul_karatsuba_batch: na, nb, form, levels (bn_mul_karatsuba_n_batch:
+                                   na = nb = n) */
 #define BN_OP_IN_PLACE 0x100    /* or'ed into a multiplication op: the output overlaps an operand
                                    (the staging buffer) */
 
@@ -242,28 +243,36 @@ bn_status bn_mul(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const u
 bn_status bn_mul_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t na,
                          size_t nb, size_t npairs, int form, bn_stream stream);
 
-/* Uniform batch of square products through `levels` Karatsuba levels above the
- * schoolbook kernels of `form` (the recursion the paper's libraries put above the
- * base case, App. A, Algorithm 4): with k = m/2, A = A_H X^k + A_L, B likewise,
+/* Uniform batch of products through `levels` Karatsuba levels above the schoolbook
+ * kernels of `form` (the recursion the paper's libraries put above the base case,
+ * App. A, Algorithm 4): with k = ceil(m/2), A = A_H X^k + A_L, B likewise,
  * P1 = A_H B_H, P0 = A_L B_L, P2 = sign(A_H-A_L) sign(B_H-B_L) |A_H-A_L| |B_H-B_L|,
  * A B = P1 X^(2k) + (P1 + P0 - P2) X^k + P0.  Each level turns N products of m limbs
- * into 3N of m/2 limbs; the bottom level is one bn_mul_n_batch-style launch, the
- * splits and combines are batched add/sub passes.  Pair p: a + p*n, b + p*n, product
- * at r + 2*p*n (exactly 2n limbs).  levels = 0 is bn_mul_n_batch; n must be a
- * multiple of 2^levels and levels <= BN_KARATSUBA_MAX_LEVELS (else BN_EINVAL).
- * levels = BN_KARATSUBA_AUTO picks bn_karatsuba_auto_levels(n, "mul.karatsuba_limbs"),
- * the libraries' size threshold for the recursion (App. A) applied per level.  r may
- * overlap a or b (in place, as for bn_mul).  Workspace: about 100 n npairs (3/2)^levels
- * bytes, reserved with bn_reserve_for(BN_OP_MUL_KARATSUBA); BN_ENOSPACE if short. */
+ * into 3N of k limbs (for odd m the high halves, k - 1 limbs, are zero-extended to k);
+ * the bottom level is one bn_mul_n_batch-style launch, the splits and combines are
+ * batched add/sub passes.  Pair p: a + p*na, b + p*nb, product at r + p*(na+nb)
+ * (exactly na + nb limbs).  Operands of unequal length are zero-extended to
+ * m = max(na, nb) at the top level (the padding of Theorem 2's proof), so the work is
+ * that of an m x m product: for lengths far apart bn_mul_n_batch does less.  Any sizes;
+ * levels = 0 is bn_mul_n_batch; levels > BN_KARATSUBA_MAX_LEVELS is BN_EINVAL.
+ * levels = BN_KARATSUBA_AUTO picks bn_karatsuba_auto_levels(max(na, nb),
+ * "mul.karatsuba_limbs"), the libraries' size threshold for the recursion (App. A)
+ * applied per level, or 0 when one length is below half the other.  r may overlap a or
+ * b (in place, as for bn_mul).  Workspace: about 100 m npairs (3/2)^levels bytes,
+ * reserved with bn_reserve_for(BN_OP_MUL_KARATSUBA, na, nb, ...); BN_ENOSPACE if
+ * short. */
 #define BN_KARATSUBA_MAX_LEVELS 8
 #define BN_KARATSUBA_AUTO (-1)
+bn_status bn_mul_karatsuba_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
+                                 size_t nb, size_t npairs, int levels, int form, bn_stream stream);
+/* Square products: bn_mul_karatsuba_batch with na = nb = n (product at r + 2*p*n). */
 bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
                                    size_t npairs, int levels, int form, bn_stream stream);
 
 /* Karatsuba levels that BN_KARATSUBA_AUTO uses for n-limb operands: one more level
- * while the halves would keep at least min_half_limbs limbs, n stays divisible by 2 per
- * level and the count stays within BN_KARATSUBA_MAX_LEVELS (0 when n < 2 min_half_limbs).
- * Pure host function (no device, no context). */
+ * while the operand has at least 2 limbs, the halves (ceil(m/2) limbs) would keep at
+ * least min_half_limbs limbs and the count stays within BN_KARATSUBA_MAX_LEVELS
+ * (0 when n < 2 min_half_limbs - 1).  Pure host function (no device, no context). */
 int bn_karatsuba_auto_levels(size_t n, size_t min_half_limbs);
 
 /* ------------------------------------------------- ragged batches + plans ---- */

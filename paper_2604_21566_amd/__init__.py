@@ -92,6 +92,7 @@ _PROTOS = {
     "bn_mul": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _i, _vp]),
     "bn_mul_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _sz, _i, _vp]),
     "bn_mul_karatsuba_n_batch": (_i, [_vp, _vp, _vp, _vp, _sz, _sz, _i, _i, _vp]),
+    "bn_mul_karatsuba_batch": (_i, [_vp, _vp, _vp, _sz, _vp, _sz, _sz, _i, _i, _vp]),
     "bn_karatsuba_auto_levels": (_i, [_sz, _sz]),
     "bn_plan_mul_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, _i, ctypes.POINTER(_vp)]),
     "bn_plan_add_ragged": (_i, [_vp, ctypes.POINTER(bn_pair), _sz, ctypes.POINTER(_vp)]),
@@ -363,6 +364,14 @@ def bn_mul_karatsuba_n_batch(ctx, r, a, b, n: int, npairs: int, levels: int, for
     _ck(lib().bn_mul_karatsuba_n_batch(ctx, _ptr(r, "r", 2 * n * npairs), _ptr(a, "a", n * npairs),
                                        _ptr(b, "b", n * npairs), n, npairs, int(levels),
                                        _form(form), _stream(stream)), "bn_mul_karatsuba_n_batch")
+
+
+def bn_mul_karatsuba_batch(ctx, r, a, na: int, b, nb: int, npairs: int, levels: int, form=BN_MUL_AUTO,
+                           stream=None):
+    """Pair p: a[p na:(p+1) na] x b[p nb:(p+1) nb] -> r[p (na+nb):(p+1) (na+nb)]."""
+    _ck(lib().bn_mul_karatsuba_batch(ctx, _ptr(r, "r", (na + nb) * npairs), _ptr(a, "a", na * npairs), na,
+                                     _ptr(b, "b", nb * npairs), nb, npairs, int(levels), _form(form),
+                                     _stream(stream)), "bn_mul_karatsuba_batch")
 
 
 def bn_karatsuba_auto_levels(n: int, min_half_limbs: int) -> int:

@@ -110,9 +110,9 @@ static WsNeed ws_need_for(const bn_ctx *ctx, int op, size_t na, size_t nb, size_
             if (in_place) w.mstage = (na + nb) * npairs * sizeof(u64);
             break;
         case BN_OP_MUL_KARATSUBA:
-            if (levels == BN_KARATSUBA_AUTO) levels = bn_karatsuba_auto_levels(na, (size_t)ctx->tune.karatsuba_limbs);
-            w = karatsuba_need(ctx, na, npairs, levels, form);
-            if (in_place) w.mstage = 2 * na * npairs * sizeof(u64);
+            if (levels == BN_KARATSUBA_AUTO) levels = karatsuba_auto_levels(ctx, na, nb);
+            w = karatsuba_need(ctx, na, nb, npairs, levels, form);
+            if (in_place) w.mstage = (na + nb) * npairs * sizeof(u64);
             break;
         default:
             break;
@@ -134,6 +134,15 @@ struct DeviceGuard {
 };
 
 // ------------------------------------------------------------------ context ----
+// Levels of BN_KARATSUBA_AUTO for na x nb products: none when one length is below half
+// the other (both are zero-extended to the longer one, which would cost more than the
+// recursion saves).
+int karatsuba_auto_levels(const bn_ctx *ctx, u64 na, u64 nb) {
+    const u64 lo = std::min(na, nb), hi = std::max(na, nb);
+    if (2 * lo < hi) return 0;
+    return bn_karatsuba_auto_levels(hi, (size_t)ctx->tune.karatsuba_limbs);
+}
+
 extern "C" {
 
 const char *bn_version(void) { return BN_VERSION_STRING; }
@@ -476,29 +485,33 @@ int bn_karatsuba_auto_levels(size_t n, size_t min_half_limbs) {
     if (min_half_limbs == 0) min_half_limbs = 1;
     int levels = 0;
     size_t m = n;
-    while (levels < BN_KARATSUBA_MAX_LEVELS && m % 2 == 0 && m / 2 >= min_half_limbs) {
-        m /= 2;
+    while (levels < BN_KARATSUBA_MAX_LEVELS && m >= 2 && (m + 1) / 2 >= min_half_limbs) {
+        m = (m + 1) / 2;
         ++levels;
     }
     return levels;
 }
 
-bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
-                                   size_t npairs, int levels, int form, bn_stream stream) {
-    bn_status st = mul_args(ctx, r, a, b, n, n, npairs, form);
+bn_status bn_mul_karatsuba_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, size_t na, const uint64_t *b,
+                                 size_t nb, size_t npairs, int levels, int form, bn_stream stream) {
+    bn_status st = mul_args(ctx, r, a, b, na, nb, npairs, form);
     if (st != BN_OK) return st;
-    if (levels == BN_KARATSUBA_AUTO) levels = bn_karatsuba_auto_levels(n, (size_t)ctx->tune.karatsuba_limbs);
+    if (levels == BN_KARATSUBA_AUTO) levels = karatsuba_auto_levels(ctx, na, nb);
     if (levels < 0 || levels > BN_KARATSUBA_MAX_LEVELS) return BN_EINVAL;
-    if (n && (n % ((size_t)1 << levels))) return BN_EINVAL;
     DeviceGuard g(ctx->device);
     if ((st = ws_acquire(ctx,
-                         ws_need_for(ctx, BN_OP_MUL_KARATSUBA, n, n, npairs, form, levels,
-                                     mul_in_place(r, a, b, n, n, npairs)),
+                         ws_need_for(ctx, BN_OP_MUL_KARATSUBA, na, nb, npairs, form, levels,
+                                     mul_in_place(r, a, b, na, nb, npairs)),
                          S(stream))) != BN_OK)
         return st;
-    return mul_staged(ctx, r, a, b, n, n, npairs, S(stream), [&](u64 *out) {
-        return launch_mul_karatsuba(ctx, out, a, b, n, npairs, levels, form, S(stream));
+    return mul_staged(ctx, r, a, b, na, nb, npairs, S(stream), [&](u64 *out) {
+        return launch_mul_karatsuba(ctx, out, a, na, b, nb, npairs, levels, form, S(stream));
     });
+}
+
+bn_status bn_mul_karatsuba_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
+                                   size_t npairs, int levels, int form, bn_stream stream) {
+    return bn_mul_karatsuba_batch(ctx, r, a, n, b, n, npairs, levels, form, stream);
 }
 
 // ------------------------------------------------------------------ ragged ----

@@ -183,10 +183,15 @@ int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form);
 bool mul_small_range(u64 P);  // products of P limbs that take mul.small_crossover_limbs
 
 // ---- Karatsuba levels (k_karatsuba.hip) ----
-bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs, int levels,
-                               int form, hipStream_t s);
-size_t karatsuba_workspace_bytes(u64 n, u64 npairs, int levels);
-WsNeed karatsuba_need(const bn_ctx *ctx, u64 n, u64 npairs, int levels, int form);
+// Products of na x nb limbs (pair p: a + p na, b + p nb, r + p (na + nb)) through
+// `levels` Karatsuba levels on operands zero-extended to max(na, nb).
+bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb, u64 npairs,
+                               int levels, int form, hipStream_t s);
+size_t karatsuba_workspace_bytes(u64 na, u64 nb, u64 npairs, int levels);
+WsNeed karatsuba_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int levels, int form);
+// Levels that BN_KARATSUBA_AUTO takes for na x nb products (0 when the lengths differ by
+// more than a factor of two: the zero-extension would cost more than it saves).
+int karatsuba_auto_levels(const bn_ctx *ctx, u64 na, u64 nb);
 
 // ---- ragged (k_ragged.hip) ----
 bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int form, bn_plan **plan);

@@ -93,13 +93,17 @@ def test_product_path_fails_loudly_when_library_missing(tmp_path, monkeypatch):
 
 
 def test_karatsuba_auto_levels(bn):
-    """BN_KARATSUBA_AUTO's level rule: split while the halves keep min_half_limbs limbs,
-    n stays even per level, at most BN_KARATSUBA_MAX_LEVELS levels."""
+    """BN_KARATSUBA_AUTO's level rule: split (halves of ceil(m/2) limbs) while the operand
+    has at least 2 limbs and the halves keep min_half_limbs limbs, at most
+    BN_KARATSUBA_MAX_LEVELS levels."""
     f = bn.bn_karatsuba_auto_levels
     assert f(16384, 4096) == 2          # C5: 8192, 4096
     assert f(16384, 4097) == 1
-    assert f(8191, 1) == 0              # odd: no split
+    assert f(8191, 4096) == 1           # 4096 (odd: the high half is zero-extended)
+    assert f(8191, 4097) == 0
     assert f(12000, 1000) == 3          # 6000, 3000, 1500 (750 < 1000)
-    assert f(12000, 1) == 5             # 6000, 3000, 1500, 750, 375 (odd)
+    assert f(12001, 1000) == 3          # 6001, 3001, 1501 (751 < 1000)
+    assert f(12000, 1) == bn.BN_KARATSUBA_MAX_LEVELS   # 6000 ... 47
+    assert f(3, 2) == 1 and f(3, 3) == 0  # 2, then 1 < 2
     assert f(1 << 20, 1) == bn.BN_KARATSUBA_MAX_LEVELS
     assert f(0, 4096) == 0 and f(1, 0) == 0 and f(2, 0) == 1

@@ -138,11 +138,94 @@ def test_errors(bnctx):
     ta = torch.zeros(96, dtype=torch.int64, device="cuda")
     tr = torch.zeros(192, dtype=torch.int64, device="cuda")
     with pytest.raises(bn.BnError) as e:
-        bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 1, 6)  # 96 is not a multiple of 64
-    assert e.value.status == bn.BN_EINVAL
-    with pytest.raises(bn.BnError) as e:
         bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 1, 9)  # more levels than allowed
     assert e.value.status == bn.BN_EINVAL
     # empty batch and n = 0 are no-ops
     bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 96, 0, 2)
     bn.bn_mul_karatsuba_n_batch(bnctx, tr, ta, ta, 0, 3, 2)
+
+
+def _kmul_general(ctx, a, na, b, nb, npairs, levels, form, in_place=False):
+    announce("karatsuba general", form, f"na={na}", f"nb={nb}", f"npairs={npairs}", f"levels={levels}",
+             f"in_place={in_place}")
+    if in_place:   # r over a, with room for the products
+        buf = torch.zeros(max(na * npairs, (na + nb) * npairs), dtype=torch.int64, device="cuda")
+        buf[:na * npairs].copy_(D(a))
+        bn.bn_mul_karatsuba_batch(ctx, buf[:(na + nb) * npairs], buf[:na * npairs], na, D(b), nb, npairs, levels,
+                                  form)
+        torch.cuda.synchronize()
+        return H(buf[:(na + nb) * npairs])
+    tr = torch.full(((na + nb) * npairs,), -1, dtype=torch.int64, device="cuda")
+    bn.bn_mul_karatsuba_batch(ctx, tr, D(a), na, D(b), nb, npairs, levels, form)
+    torch.cuda.synchronize()
+    return H(tr)
+
+
+GENERAL = [(3, 3, 4, 1), (5, 5, 3, 2), (7, 7, 2, 2), (97, 97, 3, 2), (1001, 1001, 2, 3), (4097, 4097, 2, 2),
+           (100, 60, 5, 2), (60, 100, 5, 1), (1000, 999, 3, 3), (513, 257, 4, 2), (10, 100, 3, 2),
+           (2049, 2048, 2, 3), (12001, 12000, 1, 3), (333, 1, 6, 1), (1, 9, 2, 2)]
+
+
+@pytest.mark.parametrize("form", ["auto", "mad", "mfma"])
+@pytest.mark.parametrize("na,nb,npairs,levels", GENERAL)
+def test_odd_and_unequal_sizes(bnctx, form, na, nb, npairs, levels):
+    """Odd lengths (high halves zero-extended at every level) and unequal lengths (both
+    operands zero-extended to the longer at the top, product of exactly na + nb limbs),
+    bit-exact against the oracle's schoolbook product."""
+    g = np.random.default_rng(na * 7 + nb * 13 + levels)
+    a = g.integers(0, MAX, na * npairs, dtype=np.uint64, endpoint=True)
+    b = g.integers(0, MAX, nb * npairs, dtype=np.uint64, endpoint=True)
+    a[:na] = MAX   # pair 0: all-ones operands (the largest carries in the combines)
+    b[:nb] = MAX
+    want = oracle.mul_batch(a, b, na, nb, npairs)
+    r = _kmul_general(bnctx, a, na, b, nb, npairs, levels, form)
+    bad = np.flatnonzero(r != want)
+    assert bad.size == 0, f"{bad.size} bad limbs, first at {bad[0]}"
+    if form == "mfma":
+        r = _kmul_general(bnctx, a, na, b, nb, npairs, levels, form, in_place=True)
+        assert (r == want).all(), "in place"
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_odd_split_signs(bnctx, levels):
+    """m = 65: the high half (32 limbs) is zero-extended to 33, so it can equal, exceed or
+    fall below the low half only through the low half's top limb; every pairing of those
+    cases on a and b, through one to three levels."""
+    n, k = 65, 33
+    g = np.random.default_rng(levels)
+    rnd = lambda m: g.integers(0, MAX, m, dtype=np.uint64, endpoint=True)
+    ops = []
+    lo = rnd(k)
+    lo[k - 1] = 0
+    ops.append(np.concatenate([lo, lo[:k - 1]]))                 # halves equal
+    lo2 = lo.copy()
+    lo2[k - 1] = 1
+    ops.append(np.concatenate([lo2, lo2[:k - 1]]))               # high below low (top limb)
+    hi = lo[:k - 1].copy()
+    hi[-1] += np.uint64(1)
+    ops.append(np.concatenate([lo, hi]))                         # high above low
+    ops.append(np.full(n, MAX, np.uint64))                       # all ones
+    ops.append(np.zeros(n, np.uint64))
+    A = np.concatenate([x for x in ops for _ in ops])
+    B = np.concatenate([y for _ in ops for y in ops])
+    npairs = len(ops) ** 2
+    want = oracle.mul_batch(A, B, n, n, npairs)
+    for form in ("mad", "mfma"):
+        r = _kmul_general(bnctx, A, n, B, n, npairs, levels, form)
+        assert (r == want).all(), f"{form}: first bad limb {np.argmax(r != want)}"
+
+
+def test_auto_levels_unequal(bnctx):
+    """BN_KARATSUBA_AUTO: lengths within a factor of two recurse on the longer one's level
+    count; lengths further apart take the schoolbook kernels (levels 0)."""
+    old = bn.bn_get_param(bnctx, "mul.karatsuba_limbs")
+    bn.bn_set_param(bnctx, "mul.karatsuba_limbs", 500)
+    try:
+        g = np.random.default_rng(9)
+        for na, nb in ((3000, 2001), (3000, 1400), (1401, 3001)):
+            a = g.integers(0, MAX, na * 2, dtype=np.uint64, endpoint=True)
+            b = g.integers(0, MAX, nb * 2, dtype=np.uint64, endpoint=True)
+            r = _kmul_general(bnctx, a, na, b, nb, 2, bn.BN_KARATSUBA_AUTO, "mfma")
+            assert (r == oracle.mul_batch(a, b, na, nb, 2)).all(), (na, nb)
+    finally:
+        bn.bn_set_param(bnctx, "mul.karatsuba_limbs", old)

@@ -168,6 +168,21 @@ def _cases():
     for levels in (1, 2):
         cases.append((f"bn_mul_karatsuba_n_batch levels={levels}",
                       (bn.BN_OP_MUL_KARATSUBA, 2048, 2048, 3, "mfma", levels), karatsuba(levels)))
+
+    def karatsuba_unequal():
+        na, nb, npairs = 1501, 1100, 3
+        a, b = _rand(g, na * npairs), _rand(g, nb * npairs)
+        want = oracle.mul_batch(a, b, na, nb, npairs)
+
+        def make():
+            ta, tb = D(a), D(b)
+            tr = torch.full(((na + nb) * npairs,), 7, dtype=torch.int64, device="cuda")
+            return (lambda ctx: bn.bn_mul_karatsuba_batch(ctx, tr, ta, na, tb, nb, npairs, 2, "mfma")), (tr,), \
+                (want,)
+        return make
+
+    cases.append(("bn_mul_karatsuba_batch 1501x1100 levels=2",
+                  (bn.BN_OP_MUL_KARATSUBA, 1501, 1100, 3, "mfma", 2), karatsuba_unequal()))
     return cases
 
 
