@@ -94,8 +94,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tuning", default=None, help="tuning JSON written by bn_autotune")
     ap.add_argument("--only", default=None,
-                    help="comma-separated secondary workloads to run alone (copy,c1,c3,c4,c5,crossover); "
-                         "prints their figures only, for profiling runs")
+                    help="comma-separated secondary workloads to run alone (copy, c1, c3, c4, c4auto: the "
+                         "full C4 batch in its automatic plan only, c5: the schoolbook forms, c5k: Karatsuba "
+                         "levels on C5, crossover); prints their figures only, for profiling runs")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 512 MiB device-to-device copy 3 times (the known-size reference "
                          "for scaling HBM byte counters)")
@@ -406,14 +407,15 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         res["c3"] = c3
 
     # ---- c4: 2^16 ragged products, persistent launch captured in a graph
-    if only is None or "c4" in only:
+    if only is None or "c4" in only or "c4auto" in only:
         log("c4")
         a, b, desc, rsz = wl.c4()
         work = float((desc[:, 3].astype(np.float64) * desc[:, 4].astype(np.float64)).sum())
         ta, tb = D(a), D(b)
         tr = torch.empty(rsz, dtype=torch.int64, device="cuda")
         c4 = {"limb_products": work}
-        for form in ("mad", "mfma", "auto"):
+        auto_only = only is not None and "c4" not in only
+        for form in (("auto",) if auto_only else ("mad", "mfma", "auto")):
             plan = bn.bn_plan_mul_ragged(ctx, desc, form)
             g = bn.bn_graph_capture_mul_ragged(ctx, plan, tr, ta, tb, s)
             with torch.cuda.stream(s):
@@ -430,6 +432,9 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         bn.bn_plan_destroy(plan)
         c4["auto_direct_ms"] = ms
         c4["auto_direct_ci95_ms"] = ci95(ts)
+        if auto_only:
+            res["c4"] = c4
+    if only is None or "c4" in only:
         # per size bucket (larger operand length in [lo, 2 lo), the last one [64, 128]: the
         # 128-limb operands alone are a few hundred pairs, too few to time), each bucket
         # its own graph
@@ -464,19 +469,22 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         res["c4"] = c4
 
     # ---- measured ceilings of the two multiplication forms' inner operations
-    mac_rate, mfma_rate, copy_rate = bn.bn_probe_rates(ctx)
-    res["measured_rates"] = {"mac96_per_s": mac_rate, "mfma_i8_ops_per_s": mfma_rate,
-                             "nt_copy_GBps": copy_rate / 1e9,
-                             "mad_form_limb_products_per_s_ceiling": mac_rate / 4,
-                             "mfma_form_limb_products_per_s_ceiling": mfma_rate / 128}
+    if only is None or "c5" in only:
+        mac_rate, mfma_rate, copy_rate = bn.bn_probe_rates(ctx)
+        res["measured_rates"] = {"mac96_per_s": mac_rate, "mfma_i8_ops_per_s": mfma_rate,
+                                 "nt_copy_GBps": copy_rate / 1e9,
+                                 "mad_form_limb_products_per_s_ceiling": mac_rate / 4,
+                                 "mfma_form_limb_products_per_s_ceiling": mfma_rate / 128}
 
     # ---- c5: 64 products of 16384-limb operands
-    if only is None or "c5" in only:
-        log("c5")
-        n5 = 16384
+    n5 = 16384
+    c5 = None
+    if only is None or "c5" in only or "c5k" in only:
         a, b = wl.c5()
         ta, tb = D(a), D(b)
         tr = torch.empty(64 * 2 * n5, dtype=torch.int64, device="cuda")
+    if only is None or "c5" in only:
+        log("c5")
         c5 = {"limb_products": 64.0 * n5 * n5}
         for form in ("mad", "mfma"):
             bn.bn_reserve_for(ctx, bn.BN_OP_MUL, n5, n5, 64, form)
@@ -490,8 +498,11 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         c5["mfma_frac_of_measured_int8"] = c5["mfma_int8_TOPS"] * 1e12 / mfma_rate
         c5["mad_frac_of_measured_mac96"] = c5["mad_limb_products_per_s"] * 4 / mac_rate
         c5["mfma_over_mad"] = c5["mad_ms"] / c5["mfma_ms"]
+        res["c5"] = c5
+    if only is None or "c5k" in only:
         # Karatsuba levels above the MFMA schoolbook kernel (same products; the rate is
         # stated in schoolbook limb products per second for comparison)
+        log("c5 Karatsuba")
         kar = {}
         for levels in (1, 2, 3):
             bn.bn_reserve_for(ctx, bn.BN_OP_MUL_KARATSUBA, n5, n5, 64, "mfma", levels)
@@ -502,9 +513,11 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         best = min((1, 2, 3), key=lambda l: kar[f"levels{l}_ms"])
         kar["best_levels"] = best
         kar["auto_levels"] = bn.bn_karatsuba_auto_levels(n5, bn.bn_get_param(ctx, "mul.karatsuba_limbs"))
-        kar["best_over_schoolbook_mfma"] = c5["mfma_ms"] / kar[f"levels{best}_ms"]
-        c5["karatsuba_mfma"] = kar
-        res["c5"] = c5
+        if c5 is not None:
+            kar["best_over_schoolbook_mfma"] = c5["mfma_ms"] / kar[f"levels{best}_ms"]
+            c5["karatsuba_mfma"] = kar
+        else:
+            res["c5_karatsuba_mfma"] = kar
 
     # ---- crossover sweep: square products
     if only is None or "crossover" in only:

@@ -22,11 +22,18 @@ COPY_BYTES = 512 << 20
 C2_PAIRS, C2_LIMBS = 1 << 20, 64
 
 
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the scan kernel's source file: a counter summary is valid only for the
-    source it was taken on."""
-    with open(os.path.join(CSRC, "k_addsub.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the scan kernel's source file and the headers it includes: a counter
+    summary is valid only for the source it was taken on."""
+    h = hashlib.sha256()
+    for path in (os.path.join(CSRC, "k_addsub.hip"), os.path.join(CSRC, "bn_internal.h"),
+                 os.path.join(INCLUDE, "bn.h")):
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def short(name: str) -> str:
