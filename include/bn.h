@@ -349,6 +349,10 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
  *                                      (na + nb > 1024: the column-workspace kernels)
  *   "mul.small_crossover_limbs"        the same for na + nb <= 1024 (one wave per product)
+ *   "mul.crossover_limbs_p64",          the same for products of at most 64 limbs and of 65-128
+ *   "mul.crossover_limbs_p128"         limbs (the mad form's lanes hold 1 or 2 limbs there, the
+ *                                      MFMA form runs one column block); -1 (default): use
+ *                                      "mul.small_crossover_limbs"
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
  *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large
  *                                      MFMA kernel: even, 16..256 (up to 234, three workgroups

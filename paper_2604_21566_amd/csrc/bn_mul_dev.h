@@ -283,7 +283,7 @@ __device__ __forceinline__ void wave_normalise_row(const u64 (&lo)[4], const u64
 }
 
 // Shapes of the one-wave MFMA product with NB column blocks of 128 output limbs
-// (products of up to 128 NB limbs).
+// (products of up to 128 NB limbs; NB = 1, 2 or 4).
 template <int NB>
 struct SmallMfma {
     static constexpr int LPL = 2 * NB;       // limbs per lane in the digit conversion
@@ -367,20 +367,24 @@ __device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u
     // u = 4h .. 4h+3 of limbs 4 (32 blk + x) + m.  Each lane folds its four columns of
     // every limb (signed, below 2^52 in magnitude), then partners (lane xor 32) swap
     // halves so that lane l ends up owning limbs 256 s + 4 l + m of blocks 2 s + h;
-    // the carry pass then runs over rows of 256 limbs.
+    // the carry pass then runs over rows of 256 limbs.  With one block (NB = 1) both
+    // partners end up with the block's limbs; lanes 32-63 hold them as limbs 128-255,
+    // above every limb of the product (P <= 128): the row's stores skip them and their
+    // carries only move further up.
     constexpr i64 K = (i64)1 << 40;
     u64 carry = 0, prev_hi = 0;
 #pragma unroll
-    for (int sr = 0; sr < NB / 2; ++sr) {
+    for (int sr = 0; sr < (NB + 1) / 2; ++sr) {
         u64 vlo[4], vhi[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             i64 part[2];
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
+                const int blk = 2 * sr + e < NB ? 2 * sr + e : 0;
                 i64 w = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) w += (i64)acc[2 * sr + e][4 * m + i] * ((i64)1 << (8 * i));
+                for (int i = 0; i < 4; ++i) w += (i64)acc[blk][4 * m + i] * ((i64)1 << (8 * i));
                 part[e] = w;
             }
             const i64 own = h ? part[1] : part[0];

@@ -29,13 +29,13 @@ bool mul_one_wave(u64 P, int form) { return P <= (form == BN_MUL_MFMA ? SMALL_MF
 // -------------------------------------------------------------- small kernels ----
 
 // Uniform batch of small products: wave w of block blk handles pair 4*blk + w.  The
-// MFMA form is bounded to eight (two column blocks) or four (four blocks) waves per
-// SIMD: the compiler then keeps the accumulators in ordinary registers (53 / 80 in
+// MFMA form is bounded to eight (one or two column blocks) or four (four blocks) waves
+// per SIMD: the compiler then keeps the accumulators in ordinary registers (53 / 80 in
 // all, no spills) instead of splitting off accumulation registers, one to two more
 // waves than without the bound (192- and 256-limb products 17-20% faster).
 template <int FORM, int L>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(FORM == BN_MUL_MFMA ? (L == 2 ? 8 : 4) : 1, 8))) void k_mul_small(u64 *__restrict__ r, const u64 *__restrict__ a,
+__attribute__((amdgpu_waves_per_eu(FORM == BN_MUL_MFMA ? (L <= 2 ? 8 : 4) : 1, 8))) void k_mul_small(u64 *__restrict__ r, const u64 *__restrict__ a,
                                                    const u64 *__restrict__ b, u32 na, u32 nb, u64 npairs) {
     __shared__ u64 lds[FORM == BN_MUL_MFMA ? 4 * SmallMfma<L>::LDS_U64 : 1];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -590,8 +590,13 @@ static u32 mfma_window(const bn_ctx *ctx, u64 na, u64 nb, u32 nslices) {
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
     if (form != BN_MUL_AUTO) return form;
     // products of at most 1024 limbs (mad: one wave; MFMA: one wave up to 512 limbs)
-    // and larger ones (column-workspace kernels) have a crossover each
-    const i64 x = mul_small_range(na + nb) ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
+    // and larger ones (column-workspace kernels) have a crossover each; one-wave
+    // products of at most 64 and of 65-128 limbs may have their own (the mad form's
+    // lanes then hold 1 or 2 limbs, the MFMA form runs one column block)
+    const u64 P = na + nb;
+    i64 x = mul_small_range(P) ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
+    if (P <= 64 && ctx->tune.mul_crossover_p64 >= 0) x = ctx->tune.mul_crossover_p64;
+    else if (P > 64 && P <= 128 && ctx->tune.mul_crossover_p128 >= 0) x = ctx->tune.mul_crossover_p128;
     return (i64)std::min(na, nb) >= x ? BN_MUL_MFMA : BN_MUL_MAD;
 }
 
@@ -621,7 +626,10 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
     if (mul_one_wave(P, form)) {
         const u64 blocks = (npairs + 3) / 4;
         if (blocks > 0x7fffffffull) return BN_ERANGE;
-        if (form == BN_MUL_MFMA && P <= 256)
+        if (form == BN_MUL_MFMA && P <= 128)
+            hipLaunchKernelGGL((k_mul_small<BN_MUL_MFMA, 1>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
+                               (u32)nb, npairs);
+        else if (form == BN_MUL_MFMA && P <= 256)
             hipLaunchKernelGGL((k_mul_small<BN_MUL_MFMA, 2>), dim3((u32)blocks), dim3(256), 0, s, r, a, b, (u32)na,
                                (u32)nb, npairs);
         else if (form == BN_MUL_MFMA)

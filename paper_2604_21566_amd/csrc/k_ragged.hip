@@ -52,7 +52,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     const u32 W = gridDim.x * 4;
     for (u32 it = blockIdx.x * 4 + w; it < nitems; it += W) {
         const RItem m = items[it];
-        mul_item_mfma_small<2>(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
+        if (m.na + m.nb <= 128)
+            mul_item_mfma_small<1>(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
+        else
+            mul_item_mfma_small<2>(a + m.a_off, m.na, b + m.b_off, m.nb, r + m.r_off, lds + w * RAGGED_LDS_U64);
         wave_sync();
     }
 }
@@ -77,7 +80,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         u64 *pr = r + m.r_off;
         const u32 P = m.na + m.nb;
         if (m.form == BN_MUL_MFMA || P > 128) {  // (the plan leaves no mad item above 128 limbs here)
-            mul_item_mfma_small<2>(pa, m.na, pb, m.nb, pr, lds + w * RAGGED_LDS_U64);
+            if (P <= 128)  // one column block: half the digit conversion and carry pass
+                mul_item_mfma_small<1>(pa, m.na, pb, m.nb, pr, lds + w * RAGGED_LDS_U64);
+            else
+                mul_item_mfma_small<2>(pa, m.na, pb, m.nb, pr, lds + w * RAGGED_LDS_U64);
             wave_sync();
         } else if (P <= 64) {
             mul_item_mad<1>(pa, m.na, pb, m.nb, pr);

@@ -400,3 +400,31 @@ def test_graph_survives_workspace_growth(form):
     finally:
         torch.cuda.synchronize()
         bn.bn_destroy(ctx)
+
+
+@pytest.mark.parametrize("p64,p128", [(1, 1), (1, 1 << 30), (1 << 30, 1), (12, 20)])
+def test_crossover_classes(bnctx, p64, p128):
+    """The automatic form's crossovers for one-wave products of at most 64 and of 65-128
+    limbs, pushed to either extreme (every product of the class on MFMA with its one
+    column block, or on mad): the full 2^16-pair ragged batch and uniform batches of
+    each class stay exact."""
+    announce("crossover classes", p64, p128)
+    old = (bn.bn_get_param(bnctx, "mul.crossover_limbs_p64"), bn.bn_get_param(bnctx, "mul.crossover_limbs_p128"))
+    try:
+        bn.bn_set_param(bnctx, "mul.crossover_limbs_p64", p64)
+        bn.bn_set_param(bnctx, "mul.crossover_limbs_p128", p128)
+        a, b, desc, rsz = _ragged_inputs(1 << 16, seed=4)
+        plan = bn.bn_plan_mul_ragged(bnctx, desc, "auto")
+        try:
+            tr = torch.full((rsz,), -1, dtype=torch.int64, device="cuda")
+            bn.bn_mul_ragged(bnctx, plan, tr, D(a), D(b))
+            torch.cuda.synchronize()
+            assert (H(tr) == oracle.mul_ragged(a, b, desc, rsz)).all()
+        finally:
+            bn.bn_plan_destroy(plan)
+        g = np.random.default_rng(p64 + p128)
+        for na, nb, npairs in ((3, 61, 70), (32, 32, 50), (40, 88, 33), (64, 64, 20), (100, 28, 9)):
+            _check(bnctx, _rand(g, na * npairs), _rand(g, nb * npairs), na, nb, npairs, "auto")
+    finally:
+        bn.bn_set_param(bnctx, "mul.crossover_limbs_p64", old[0])
+        bn.bn_set_param(bnctx, "mul.crossover_limbs_p128", old[1])
