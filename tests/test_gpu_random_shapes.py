@@ -1,0 +1,73 @@
+"""Seeded random shapes for the general-size paths, bit-exact against the oracle:
+Karatsuba levels over odd and unequal lengths, and unequal-length add/sub batches,
+with random alignment and in-place use."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_21566_amd as bn
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+D = bn.to_device
+H = bn.to_host
+MAX = 2 ** 64 - 1
+
+
+def _rand(g, n):
+    x = g.integers(0, MAX, n, dtype=np.uint64, endpoint=True)
+    # runs of all-ones and zeros so that carries cross limbs and tiles
+    for _ in range(max(1, n // 500)):
+        s = int(g.integers(0, max(1, n)))
+        x[s:s + int(g.integers(1, 300))] = MAX if g.integers(0, 2) else 0
+    return x
+
+
+def _log_size(g, lo, hi):
+    return int(np.exp(g.uniform(np.log(lo), np.log(hi + 1))))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_karatsuba_random_shapes(bnctx, seed):
+    g = np.random.default_rng(1000 + seed)
+    hi = _log_size(g, 1, 3000)
+    lo = max(1, min(hi, _log_size(g, max(1, hi // 3), hi)))
+    na, nb = (hi, lo) if g.integers(0, 2) else (lo, hi)
+    npairs = int(g.integers(1, max(2, 6000 // max(na, nb)) + 1))
+    levels = int(g.integers(0, 4))
+    form = ("mad", "mfma", "auto")[seed % 3]
+    a, b = _rand(g, na * npairs), _rand(g, nb * npairs)
+    want = oracle.mul_batch(a, b, na, nb, npairs)
+    announce("random karatsuba", seed, na, nb, npairs, levels, form)
+    tr = torch.full(((na + nb) * npairs,), -1, dtype=torch.int64, device="cuda")
+    bn.bn_mul_karatsuba_batch(bnctx, tr, D(a), na, D(b), nb, npairs, levels, form)
+    torch.cuda.synchronize()
+    got = H(tr)
+    assert (got == want).all(), f"na={na} nb={nb} npairs={npairs} levels={levels} {form}: " \
+                                f"first bad limb {np.argmax(got != want)}"
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_unequal_addsub_random_shapes(bnctx, seed):
+    g = np.random.default_rng(2000 + seed)
+    na = _log_size(g, 1, 300000)
+    nb = int(g.integers(0, na + 1))
+    npairs = int(g.integers(1, max(2, 400000 // na) + 1))
+    op = "add" if seed % 2 == 0 else "sub"
+    offset = int(g.integers(0, 2))
+    in_place = bool(g.integers(0, 2))
+    a, b = _rand(g, na * npairs), _rand(g, nb * npairs)
+    bext = np.zeros((npairs, na), np.uint64)
+    bext[:, :nb] = b.reshape(npairs, nb)
+    want, wc = (oracle.add_batch if op == "add" else oracle.sub_batch)(a, bext.reshape(-1), na)
+    announce("random unequal", seed, op, na, nb, npairs, offset, in_place)
+    ta = D(np.concatenate([np.zeros(offset, np.uint64), a]))[offset:]
+    tb = D(b) if nb else torch.zeros(1, dtype=torch.int64, device="cuda")
+    tr = ta if in_place else torch.full((na * npairs + offset,), -1, dtype=torch.int64, device="cuda")[offset:]
+    tc = torch.full((npairs,), -1, dtype=torch.int64, device="cuda")
+    (bn.bn_add_unequal_n_batch if op == "add" else bn.bn_sub_unequal_n_batch)(bnctx, tr, ta, na, tb, nb, npairs, tc)
+    torch.cuda.synchronize()
+    got = H(tr)
+    assert (got == want).all(), f"{op} na={na} nb={nb} npairs={npairs}: first bad limb {np.argmax(got != want)}"
+    assert (H(tc) == wc).all()
