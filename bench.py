@@ -385,24 +385,32 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
         bn.bn_reserve_for(ctx, bn.BN_OP_ADDSUB, n3, 0, 1)
         tr = torch.empty(n3, dtype=torch.int64, device="cuda")
         tc = torch.empty(1, dtype=torch.int64, device="cuda")
+        defer_default = bn.bn_get_param(ctx, "addsub.defer_tiles")
+        c3["defer_tiles"] = defer_default
         for op in ("add", "sub"):
             for worst in (False, True):
                 a, b = wl.c3(op, n=n3, worst=worst)
                 ta, tb = D(a), D(b)
                 f = bn.bn_add if op == "add" else bn.bn_sub
-                ms, ts = gpu_time(lambda: f(ctx, tr, ta, tb, tc), REPS, 2)
                 key = f"{op}{'_worst' if worst else ''}"
-                c3[key + "_GBps"] = 24.0 * n3 / (ms * 1e-3) / 1e9
-                c3[key + "_ms"] = ms
-                c3[key + "_ci95_ms"] = ci95(ts)
-                # look-back distances of one more (untimed) run
+                # the default (all-propagate tiles deferred to a fill pass at this size)
+                # and the form in which every tile waits for its look-back
+                for form, dt in (("", defer_default), ("_waiting", 0)):
+                    bn.bn_set_param(ctx, "addsub.defer_tiles", dt)
+                    ms, ts = gpu_time(lambda: f(ctx, tr, ta, tb, tc), REPS, 2)
+                    c3[key + form + "_GBps"] = 24.0 * n3 / (ms * 1e-3) / 1e9
+                    c3[key + form + "_ms"] = ms
+                    c3[key + form + "_ci95_ms"] = ci95(ts)
+                # look-back distances of one more (untimed) run of the waiting form
+                # (deferred launches record none)
                 bn.bn_lookback_stats(ctx)
                 bn.bn_set_param(ctx, "debug.flags", 2)
                 f(ctx, tr, ta, tb, tc)
                 h = bn.bn_lookback_stats(ctx)
                 bn.bn_set_param(ctx, "debug.flags", 0)
+                bn.bn_set_param(ctx, "addsub.defer_tiles", defer_default)
                 top = max([k for k, v in enumerate(h) if v] or [0])
-                c3[key + "_lookback_hist_log2"] = h[:top + 1]
+                c3[key + "_waiting_lookback_hist_log2"] = h[:top + 1]
                 del ta, tb
         res["c3"] = c3
 

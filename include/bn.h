@@ -124,7 +124,8 @@ bn_status bn_check(bn_ctx *ctx, bn_stream stream, uint32_t *flags);
  * workgroup tiles whose carry-in was decided by a predecessor 2^k <= d < 2^(k+1)
  * tiles back (d = 1: the nearest one had already published; reaching past the
  * first tile of the operand counts as that tile's distance + 1).  Bins past
- * BN_LOOKBACK_BINS read 0.  Waits for `stream`, then clears the histogram.
+ * BN_LOOKBACK_BINS read 0.  Deferred launches (see bn_add) record nothing.  Waits
+ * for `stream`, then clears the histogram.
  * Returns BN_EINVAL for a NULL ctx, or hist NULL with nbins > 0; BN_EHIP on a
  * stream error. */
 #define BN_LOOKBACK_BINS 32
@@ -138,9 +139,15 @@ bn_status bn_lookback_stats(bn_ctx *ctx, bn_stream stream, uint64_t *hist, size_
  * One pass over the operands: limb sums, generate/propagate flags, a wave64
  * ballot prefix scan, an LDS scan across waves and a decoupled look-back across
  * workgroups (Sec. 3.1 phases 1-4 restated as a parallel prefix computation).
+ * Large launches (at least "addsub.defer_tiles" tiles) add two small kernels and no
+ * tile waits for another tile's look-back: a tile whose every limb propagates stores
+ * nothing and exits (its result is all ones or all zeros, fixed by its carry-in alone),
+ * a tile whose 64-tile look-back window holds only such tiles keeps its sums for
+ * carry-in 0, and after the launch a one-workgroup scan of the status words and a fill
+ * pass write those constants and repairs -- at the same 24 bytes of traffic per limb.
  * Workspace: a launch whose workgroup tiles do not each start a pair (one long pair,
- * or pairs longer than a tile or not dividing it) keeps one look-back status word per
- * tile: bn_reserve_for(BN_OP_ADDSUB); BN_ENOSPACE if short.  In place, a tile waiting
+ * or pairs longer than a tile or not dividing it) keeps one look-back status word and
+ * one fill code byte per tile: bn_reserve_for(BN_OP_ADDSUB); BN_ENOSPACE if short.  In place, a tile waiting
  * for an unpublished predecessor only waits (it never recomputes that tile from the
  * operands, which may already hold sums). */
 bn_status bn_add(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n,
@@ -165,8 +172,9 @@ bn_status bn_sub_n_batch(bn_ctx *ctx, uint64_t *r, const uint64_t *a, const uint
  * are those of bn_add_n_batch / bn_sub_n_batch (npairs = 1 is bn_add / bn_sub); the
  * context supplies the device and the tuned tile shapes only, and its workspace is
  * neither used nor grown.  The call allocates nothing and never synchronises.
- * Limit: the array holds BN_SCRATCH_MAX_TILES status words (about 1 MiB per GPU, held
- * until the process ends), one per workgroup tile of a chained launch: with the default
+ * Limit: the array holds BN_SCRATCH_MAX_TILES status words and as many fill code bytes
+ * (about 1.1 MiB per GPU, held until the process ends), one each per workgroup tile of a
+ * chained launch: with the default
  * shapes, one pair of up to 2^28 limbs (2 GiB per operand) -- batches whose pair length
  * divides 128 need no status words and have no such limit.  A launch that could need
  * more (at either operand alignment) returns BN_ERANGE with nothing enqueued.
@@ -346,6 +354,9 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "addsub.chain_waves", "addsub.chain_rows"   tile shape otherwise (look-back between tiles)
  *                                      waves in {1,2,4,8}, rows of 128 limbs in {1,2,4,8,16},
  *                                      except 8 waves x 16 rows
+ *   "addsub.defer_tiles"               chained launches of at least this many tiles (default
+ *                                      8192, 0 = never) defer the stores of tiles that
+ *                                      propagate through every limb to a fill pass (bn_add)
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
  *                                      (na + nb > 1024: the column-workspace kernels)
  *   "mul.small_crossover_limbs"        the same for na + nb <= 1024 (one wave per product)
@@ -367,7 +378,8 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "lookback.spin_limit"              look-back polls before a tile computes an
  *                                      unpublished predecessor's carry itself
  *   "debug.flags"                      bit 0: tile 0 never publishes its status
- *                                      (test hook for the self-computed look-back);
+ *                                      (test hook for the self-computed look-back; such
+ *                                      launches do not defer);
  *                                      bit 1: record look-back distances
  *                                      (read with bn_lookback_stats)
  * Returns BN_EINVAL for an unknown key or an out-of-range value. */

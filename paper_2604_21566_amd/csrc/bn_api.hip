@@ -287,7 +287,7 @@ static bn_status addsub(bn_ctx *ctx, bool sub, uint64_t *r, const uint64_t *a, c
         return BN_EALIAS;
     DeviceGuard g(ctx->device);
     if (fixed) {  // the status words of either operand alignment must fit the array
-        if (flat_scan_status_bytes(ctx, n, N) > fixed->max_tiles * sizeof(u64)) return BN_ERANGE;
+        if (flat_scan_status_bytes(ctx, n, N) > scan_state_bytes(fixed->max_tiles)) return BN_ERANGE;
         return launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, nullptr, false, 0, carry, S(stream), fixed);
     }
     if ((st = ws_acquire(ctx, ws_need_for(ctx, BN_OP_ADDSUB, n, n, npairs, 0, 0, false), S(stream))) != BN_OK)
@@ -616,7 +616,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 
 // ------------------------------------------------------------------ params ----
 static const char *kParamNames =
-    "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,"
+    "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,addsub.defer_tiles,"
     "mul.crossover_limbs,mul.small_crossover_limbs,mul.crossover_limbs_p64,mul.crossover_limbs_p128,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,mul.karatsuba_limbs,"
     "lookback.spin_limit,debug.flags,workspace.auto_grow";
 
@@ -638,6 +638,9 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
         if (!flat_scan_shape_ok(w, r)) return BN_EINVAL;
         t.chain_waves = w;
         t.chain_rows = r;
+    } else if (k == "addsub.defer_tiles") {
+        if (v < 0) return BN_EINVAL;
+        t.defer_tiles = (u64)v;
     } else if (k == "mul.crossover_limbs") {
         if (v < 1) return BN_EINVAL;
         t.mul_crossover_limbs = v;
@@ -682,6 +685,7 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "addsub.batch_rows") *v = t.batch_rows;
     else if (k == "addsub.chain_waves") *v = t.chain_waves;
     else if (k == "addsub.chain_rows") *v = t.chain_rows;
+    else if (k == "addsub.defer_tiles") *v = (int64_t)t.defer_tiles;
     else if (k == "mul.crossover_limbs") *v = t.mul_crossover_limbs;
     else if (k == "mul.small_crossover_limbs") *v = t.mul_small_crossover_limbs;
     else if (k == "mul.crossover_limbs_p64") *v = t.mul_crossover_p64;

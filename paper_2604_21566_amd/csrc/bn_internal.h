@@ -61,6 +61,8 @@ struct Tuning {
                                        // (allocation + device synchronisation, never during a
                                        // capture); 0: it returns BN_ENOSPACE
     u32 spin_limit = 2048;             // look-back polls before computing a predecessor itself
+    u64 defer_tiles = 8192;            // chained launches of at least this many tiles defer the
+                                       // stores of all-propagate tiles to a fill pass (0: never)
     u32 debug_flags = 0;               // bit 0: tile 0 never publishes (exercises the self-help path)
                                        // bit 1: record look-back distances in ScanCtl::hist
 };
@@ -140,13 +142,14 @@ bn_status launch_flat_scan(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u6
 bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                                const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s);
 size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N);
+size_t scan_state_bytes(u64 tiles);  // status words + fill codes of a chained launch over `tiles` tiles
 size_t flat_scan_ext_status_bytes(u64 n, u64 N);  // the same for launch_flat_scan_ext
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s);
 // Where a chained launch keeps its look-back state: NULL for the context's control block
 // and status array (grown by the reserve calls), or a fixed device array.
 struct ScanMem {
     ScanCtl *ctl = nullptr;
-    u64 *status = nullptr;
+    u64 *status = nullptr;                   // max_tiles status words, then max_tiles fill code bytes
     u64 max_tiles = 0;                       // status words available
     std::atomic<u64> *host_epoch = nullptr;  // epochs of launches outside a capture
     u32 dbg_mask = ~0u;                      // debug flags that apply

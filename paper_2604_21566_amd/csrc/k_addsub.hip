@@ -96,6 +96,8 @@ struct ScanGeom {
     u64 bval;        // EXT_BCONST: the value of every limb of b
     u32 no_self_help;  // 1 when r overlaps a or b: a waiting tile never reads another tile's operands
     u64 nbz;           // EXT_BZX: limbs of b per pair (b's pair stride); b reads as 0 past them
+    u32 defer;         // chained launches: no tile waits for another's look-back (see k_flat_scan, phase 3)
+    uint8_t *codes;    // deferred launches: one byte per tile (1: its carry-in repair is left to the fill pass)
 };
 
 // Kernel variants beyond the plain a +- b: a per-segment carry-in, b given as one limb
@@ -163,6 +165,27 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
 // below index 0 count as "carry-out 0".  `dist` returns how many tiles back the
 // deciding predecessor was.
 //
+// Deferred launches: the carry into tile t from its 64-tile window, or 2 (left to the
+// fill pass) when every tile in the window propagates.  The nearest predecessor that
+// does not propagate publishes its carry-out right after its own loads and never waits
+// for anyone, so a wait for it is short; after `spin_limit` polls (it may not have
+// been dispatched yet) the carry-in is left to the fill pass as well.
+__device__ u32 lookback_defer(const u64 *status, u64 t, u64 epoch, u32 spin_limit) {
+    const int lane = threadIdx.x & 63;
+    const i64 idx = (i64)t - 1 - lane;
+    for (u32 spins = 0;; ++spins) {
+        u64 st = (epoch << 2) | ST_I0;  // below tile 0: carry-out 0
+        if (idx >= 0) st = ld_relaxed(status + idx);
+        const u32 state = ((st >> 2) == epoch) ? (u32)(st & 3) : 0u;
+        const u64 notA = __ballot(state != ST_A);
+        if (notA == 0) return 2u;
+        const u32 sf = __shfl(state, __ffsll((unsigned long long)notA) - 1);
+        if (sf >= ST_I0) return sf & 1u;
+        if (spins >= spin_limit) return 2u;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // In place (r overlapping a or b) there is no self-help: the unpublished tile may
 // publish and overwrite its operands with sums between our status read and our
 // operand reads, so the wave only waits.  Every wait still ends: a tile publishes
@@ -368,13 +391,38 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     }
     __syncthreads();
 
+    // Deferred launches: no tile waits for another tile's look-back.  A tile whose every
+    // limb propagates holds no information but its carry-in -- its result is the
+    // constant the raw limbs turn into (add: all ones with carry-in 0, all zeros with 1;
+    // sub: the reverse) -- so it stores nothing and frees its slot at once; its A status
+    // stays.  (Reading its window once first and storing the constant when that decides
+    // the carry-in was measured slower on every input.)  Every other tile stores its
+    // sums for carry-in 0 and reads its window, waiting only for a predecessor that is
+    // still loading: if every tile in the window propagates, it leaves the repair (the
+    // propagate run at its start) to the fill pass.  After the launch, k_defer_scan
+    // finds the carry-in of every tile left over among the final status words and
+    // k_defer_fill writes the constants and the repairs.
+    if (chain && G.defer && sh_pt) return;
+
     // The tile's real carry-in by look-back (wave 0), its inclusive status published,
     // and the carry into every wave of the tile.
     auto resolve_cin = [&]() {
         if (w == 0) {
             u32 cin = 0;
             const u64 first_pos = __shfl(pos0, 0);
-            if (t > 0 && first_pos != 0) {
+            if (G.defer) {
+                // an undecided carry-in is left to the fill pass (the tile keeps its
+                // carry-in-0 sums, and its flag byte says so)
+                u32 later = 0;
+                if (t > 0 && first_pos != 0) {
+                    cin = lookback_defer(status, t, epoch, spin_limit);
+                    if (cin > 1u) {
+                        cin = 0;
+                        later = 1;
+                    }
+                }
+                if (lane == 0) G.codes[t] = (uint8_t)later;
+            } else if (t > 0 && first_pos != 0) {
                 u64 dist;
                 cin = lookback<SUB, EXT>(status, t, epoch, spin_limit, &ctl->err, a, b, G, dist);
                 if ((dbg & 2u) && lane == 0)
@@ -496,6 +544,160 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     }
 }
 
+// After a deferred launch (every workgroup done): the carry into every tile that left
+// its result to the fill pass -- tiles that propagate through all of their limbs, and
+// tiles whose look-back window did not decide their carry-in.  A tile's carry-in is
+// the carry out of the nearest tile below it that does not propagate (tile 0 starts a
+// segment, so there is one).  Codes written: 0 = nothing to do, 1 + c = fill with
+// carry-in c, 3 = repair with carry-in 1.  One workgroup; blocks of 16384 tiles,
+// thread i taking 16 consecutive tiles; the "last known carry-out" runs across threads
+// by ballots within each wave and across the 16 wave aggregates.
+constexpr int DS_THREADS = 1024, DS_PER = 16;
+__global__ __launch_bounds__(DS_THREADS) void k_defer_scan(const u64 *__restrict__ status, uint8_t *__restrict__ code,
+                                                           u64 ntiles, u64 epoch_arg, const ScanCtl *__restrict__ ctl) {
+    __shared__ u32 sh_def[DS_THREADS / 64], sh_val[DS_THREADS / 64];
+    const u64 epoch = epoch_arg ? epoch_arg : ctl->epoch;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    u32 carry_blocks = 0;  // carry out of the blocks before this one (uniform)
+    for (u64 base = 0; base < ntiles; base += (u64)DS_THREADS * DS_PER) {
+        const u64 t0 = base + (u64)threadIdx.x * DS_PER;
+        const bool whole = t0 + DS_PER <= ntiles;
+        u32 state[DS_PER];
+        u64 flags[DS_PER / 8];  // this thread's flag bytes, packed
+        if (whole) {  // status + t0 is 128-byte aligned, code + t0 8-byte aligned
+#pragma unroll
+            for (int j = 0; j < DS_PER; j += 2) {
+                const u64v2 v = *reinterpret_cast<const u64v2 *>(status + t0 + j);
+                state[j] = (v.x >> 2) == epoch ? (u32)(v.x & 3) : 0u;
+                state[j + 1] = (v.y >> 2) == epoch ? (u32)(v.y & 3) : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < DS_PER / 8; ++k) flags[k] = *reinterpret_cast<const u64 *>(code + t0 + 8 * k);
+        } else {
+#pragma unroll
+            for (int k = 0; k < DS_PER / 8; ++k) flags[k] = 0;
+#pragma unroll
+            for (int j = 0; j < DS_PER; ++j) {
+                const u64 st = t0 + j < ntiles ? status[t0 + j] : 0ull;
+                state[j] = (st >> 2) == epoch ? (u32)(st & 3) : 0u;
+                if (t0 + j < ntiles) flags[j / 8] |= (u64)code[t0 + j] << (8 * (j % 8));
+            }
+        }
+        bool def = false;
+        u32 val = 0;
+#pragma unroll
+        for (int j = 0; j < DS_PER; ++j)
+            if (state[j] >= ST_I0) {
+                def = true;
+                val = state[j] & 1u;
+            }
+        const u64 D = __ballot(def), V = __ballot(def && val);
+        __syncthreads();  // the previous block's readers are done with sh_def / sh_val
+        if (lane == 0) {
+            sh_def[w] = D != 0;
+            sh_val[w] = D ? (u32)((V >> (63 - __clzll((long long)D))) & 1ull) : 0u;
+        }
+        __syncthreads();
+        u32 c = carry_blocks, block_out = carry_blocks;
+#pragma unroll
+        for (int k = 0; k < DS_THREADS / 64; ++k)
+            if (sh_def[k]) {
+                if (k < w) c = sh_val[k];
+                block_out = sh_val[k];
+            }
+        const u64 below = D & ((1ull << lane) - 1ull);
+        if (below) c = (u32)((V >> (63 - __clzll((long long)below))) & 1ull);
+        u64 out[DS_PER / 8] = {};
+#pragma unroll
+        for (int j = 0; j < DS_PER; ++j) {
+            u64 o = 0;
+            if (state[j] == ST_A) {
+                o = 1u + c;
+            } else {
+                if (((flags[j / 8] >> (8 * (j % 8))) & 0xff) != 0 && c) o = 3;
+                if (state[j] >= ST_I0) c = state[j] & 1u;
+            }
+            out[j / 8] |= o << (8 * (j % 8));
+        }
+        if (whole) {
+#pragma unroll
+            for (int k = 0; k < DS_PER / 8; ++k) *reinterpret_cast<u64 *>(code + t0 + 8 * k) = out[k];
+        } else {
+#pragma unroll
+            for (int j = 0; j < DS_PER; ++j)
+                if (t0 + j < ntiles) code[t0 + j] = (uint8_t)(out[j / 8] >> (8 * (j % 8)));
+        }
+        carry_blocks = block_out;
+    }
+}
+
+// The fill pass of a deferred launch, a grid-stride loop over the tiles' codes.
+//   1 + c (c = 0, 1): the tile propagates through every limb; its result is the constant
+//     the raw limbs turn into with carry-in c (add: all ones with 0, zeros with 1; sub:
+//     zeros with 0, all ones with 1).  No segment starts inside such a tile, but its top
+//     limb may end one (the next starts in the next tile, or it is the last limb): that
+//     segment's carry-out is c, passed through every limb.
+//   3: the tile holds its sums for carry-in 0 and its carry-in is 1: the carry runs up
+//     from its first limb through the limbs still holding the propagate value (add: all
+//     ones, sub: 0), which flip, to the first other limb, which moves by one -- or to a
+//     segment start, in which case the segment below it gets carry-out 1.
+// One tile's work (code c) on the whole workgroup.
+template <bool SUB>
+__device__ __forceinline__ void defer_fill_tile(u64 *__restrict__ r, u32 c, u64 lo, u64 hi, u64 n,
+                                                u64 *__restrict__ carry, u32 &sh_stop) {
+    constexpr u64 PV = SUB ? 0ull : ~0ull;  // a propagating limb's value for carry-in 0
+    if (c <= 2) {
+        const u64 v = ((c - 1u) ^ (SUB ? 1u : 0u)) ? 0ull : ~0ull;
+        if (carry && threadIdx.x == 0 && hi % n == 0) carry[hi / n - 1] = c - 1u;
+        if ((((uintptr_t)(r + lo)) & 15u) == 0 && ((hi - lo) & 1u) == 0) {
+            const u64v2 vv = {v, v};
+            for (u64 i = lo + 2 * (u64)threadIdx.x; i < hi; i += 512)
+                __builtin_nontemporal_store(vv, reinterpret_cast<u64v2 *>(r + i));
+        } else {
+            for (u64 i = lo + threadIdx.x; i < hi; i += 256) r[i] = v;
+        }
+        return;
+    }
+    // repair with carry-in 1: where the carry stops (offset from lo), 256 limbs a round
+    if (threadIdx.x == 0) sh_stop = (u32)(hi - lo);
+    __syncthreads();
+    for (u64 base = lo; base < hi; base += 256) {
+        const u64 i = base + threadIdx.x;
+        if (i < hi && ((i > lo && i % n == 0) || r[i] != PV)) atomicMin(&sh_stop, (u32)(i - lo));
+        __syncthreads();
+        // later rounds only lower sh_stop to values past this round, so every thread
+        // takes the same decision here
+        if (sh_stop < (u32)(base + 256 - lo)) break;
+    }
+    const u64 stop = lo + sh_stop;
+    for (u64 i = lo + threadIdx.x; i < stop; i += 256) r[i] = ~PV;
+    if (threadIdx.x == 0) {
+        if (stop < hi && stop % n != 0) r[stop] = SUB ? r[stop] - 1u : r[stop] + 1u;
+        else if (carry && stop % n == 0) carry[stop / n - 1] = 1;
+    }
+    __syncthreads();  // sh_stop is reused by the next tile
+}
+
+// Workgroup b takes tiles b, b + G, b + 2G, ... (G = gridDim.x); the codes of 64 of them
+// are read at once, one per lane (every wave reads the same ones, so the workgroup
+// branches alike), and only the tiles with work are visited.
+template <bool SUB>
+__global__ __launch_bounds__(256) void k_defer_fill(u64 *__restrict__ r, const uint8_t *__restrict__ code, u64 ntiles,
+                                                    u64 TL, u64 N, u64 n, u64 *__restrict__ carry) {
+    __shared__ u32 sh_stop;
+    const int lane = threadIdx.x & 63;
+    for (u64 t0 = blockIdx.x; t0 < ntiles; t0 += 64 * (u64)gridDim.x) {
+        const u64 tk = t0 + (u64)lane * gridDim.x;
+        const u32 ck = tk < ntiles ? code[tk] : 0u;
+        for (u64 m = __ballot(ck != 0); m; m &= m - 1) {
+            const int k = __ffsll((unsigned long long)m) - 1;
+            const u32 c = (u32)__shfl((int)ck, k);
+            const u64 lo = (t0 + (u64)k * gridDim.x) * TL;
+            defer_fill_tile<SUB>(r, c, lo, lo + TL < N ? lo + TL : N, n, carry, sh_stop);
+        }
+    }
+}
+
 // After a chained launch: move to a fresh epoch so that the next launch never
 // mistakes this launch's status words for its own.  Stream order puts it after
 // every workgroup of the scan.
@@ -559,6 +761,10 @@ static void flat_scan_shape(const bn_ctx *ctx, u64 n, u64 N, bool vec, int &wave
     }
 }
 
+// Look-back state of a chained launch over `tiles` tiles: one status word per tile,
+// then one fill code byte per tile (deferred launches).
+size_t scan_state_bytes(u64 tiles) { return (size_t)(tiles + (tiles + 7) / 8) * sizeof(u64); }
+
 // Status words needed by a launch over N limbs in segments of n (the larger count
 // of the aligned and the unaligned shape, so a reservation covers both).
 size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N) {
@@ -571,13 +777,13 @@ size_t flat_scan_status_bytes(const bn_ctx *ctx, u64 n, u64 N) {
         const u64 TL = (u64)waves * rows * 128;
         tiles = std::max<u64>(tiles, (N + TL - 1) / TL);
     }
-    return (size_t)tiles * sizeof(u64);
+    return scan_state_bytes(tiles);
 }
 
 size_t flat_scan_ext_status_bytes(u64 n, u64 N) {
     if (n == 0 || 128 % n == 0) return 0;  // independent tiles: no status words
     const u64 TL = 4 * 128;  // the smallest chained tile
-    return (size_t)((N + TL - 1) / TL) * sizeof(u64);
+    return scan_state_bytes((N + TL - 1) / TL);
 }
 
 bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s) {
@@ -631,7 +837,7 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         if (fixed) {
             if (ntiles > fixed->max_tiles) return BN_ERANGE;
         } else {
-            bn_status st = bn_ensure(ctx, ctx->status, ntiles * sizeof(u64), s);
+            bn_status st = bn_ensure(ctx, ctx->status, scan_state_bytes(ntiles), s);
             if (st != BN_OK) return st;
         }
     }
@@ -668,15 +874,28 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     // r overlapping an operand: a waiting tile must not read another tile's operands
     const bool inplace =
         ranges_overlap(r, N, a, N) || (!bconst && ranges_overlap(r, N, b, bzx ? (u64)nbz * npairs : N));
-    ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u, bzx ? (u64)nbz : 0};
-    if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     u32 dbg = ctx->tune.debug_flags & (fixed ? fixed->dbg_mask : ~0u);
     if (inplace) dbg &= ~1u;
+    // deferred all-propagate tiles from `addsub.defer_tiles` tiles up (the silent-tile-0
+    // debug mode keeps the waiting form: the status scan needs every tile's word)
+    const u64 dt = ctx->tune.defer_tiles;
+    const bool defer = chain && dt > 0 && ntiles >= dt && (dbg & 1u) == 0;
     ScanCtl *ctl = fixed ? fixed->ctl : ctx->ctl;
     u64 *status = fixed ? fixed->status : (u64 *)ctx->status.ptr;
+    uint8_t *codes = chain ? reinterpret_cast<uint8_t *>(status + (fixed ? fixed->max_tiles : ntiles)) : nullptr;
+    ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u, bzx ? (u64)nbz : 0, defer ? 1u : 0u, codes};
+    if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
                        ctl, status, ctx->tune.spin_limit, dbg);
     bn_status st = bn_launch_status();
+    if (st == BN_OK && defer) {
+        hipLaunchKernelGGL(k_defer_scan, dim3(1), dim3(DS_THREADS), 0, s, status, codes, ntiles, epoch, ctl);
+        if ((st = bn_launch_status()) != BN_OK) return st;
+        const u64 fill_blocks = std::min<u64>(ntiles, 8 * (u64)std::max(1, ctx->num_cu));
+        hipLaunchKernelGGL(sub ? k_defer_fill<true> : k_defer_fill<false>, dim3((u32)fill_blocks), dim3(256), 0, s, r,
+                           codes, ntiles, TL, N, n, carry);
+        st = bn_launch_status();
+    }
     if (st != BN_OK || !chain || !captured) return st;
     hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, ctl);
     return bn_launch_status();

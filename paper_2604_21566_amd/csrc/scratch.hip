@@ -11,7 +11,8 @@
 // device address).
 //
 // Layout (bytes): [0, 512) the look-back control block (ScanCtl; epoch starts at 1),
-// [512, 512 + 8 * BN_SCRATCH_MAX_TILES) the status words.  Every call on a device shares
+// [512, 512 + 8 * BN_SCRATCH_MAX_TILES) the status words, then BN_SCRATCH_MAX_TILES
+// bytes of fill codes (launches that defer their all-propagate tiles).  Every call on a device shares
 // them: each chained launch tags its status words with an epoch of its own (a per-device
 // host counter counting up from 2^61 for eager launches, the control block's counter
 // for launches recorded into a graph), so nothing has to be cleared between calls; two
@@ -25,7 +26,7 @@ namespace {
 
 constexpr size_t SCRATCH_CTL_BYTES = 512;
 static_assert(sizeof(ScanCtl) <= SCRATCH_CTL_BYTES, "control block must fit its slot");
-constexpr size_t SCRATCH_WORDS = (SCRATCH_CTL_BYTES + 8 * (size_t)BN_SCRATCH_MAX_TILES) / 8;
+constexpr size_t SCRATCH_WORDS = (SCRATCH_CTL_BYTES + 9 * (size_t)BN_SCRATCH_MAX_TILES) / 8;
 
 static __device__ __align__(256) u64 scratch[SCRATCH_WORDS];
 

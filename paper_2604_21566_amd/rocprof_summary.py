@@ -2,6 +2,10 @@
 
   python -m paper_2604_21566_amd.rocprof_summary <results.db> "<command>" > out.txt
       per-kernel durations from a --kernel-trace --stats run
+  python -m paper_2604_21566_amd.rocprof_summary launches <results.db> "<command>" > out.txt
+      chained add/sub launches in dispatch order, each scan dispatch together with the
+      status scan and fill pass that follow it (deferred launches), grouped into runs
+      of consecutive launches of the same kernel and form
   python -m paper_2604_21566_amd.rocprof_summary pmc <counter_collection.csv> "<command>" > out.txt
       per-kernel mean of every counter of a --pmc run (one row per kernel and counter)
   python -m paper_2604_21566_amd.rocprof_summary traffic <fetch.csv> <write.csv> "<fetch cmd>" "<write cmd>" > out.txt
@@ -55,6 +59,40 @@ def main(db, cmd):
         name, n, tot, avg, mn, mx, vg, ag, lds, gx, wg = r
         print(f"{short(name)[:70]:70s} {n:6d} {tot/1e3:10.1f} {avg/1e3:9.2f} {mn/1e3:9.2f} {mx/1e3:9.2f} "
               f"{100*tot/total:6.2f} {vg:5d} {ag:5d} {lds:6d} {gx:9d} {wg:4d}")
+
+
+def launches(db, cmd):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    groups = []  # [kernel, deferred?, main_us, scan_us, fill_us, start, end]
+    for name, st, en in rows:
+        n = short(name)
+        if "k_flat_scan" in n and n.rstrip(">").split(",")[-2].strip() == "true":
+            groups.append([n, False, (en - st) / 1e3, 0.0, 0.0, st, en])
+        elif groups and ("k_defer_scan" in n or "k_defer_fill" in n):
+            g = groups[-1]
+            g[1] = True
+            g[3 if "scan" in n else 4] += (en - st) / 1e3
+            g[6] = en
+    blocks = []  # consecutive launches of one kernel and form with similar duration
+    for g in groups:
+        b = blocks[-1] if blocks else None
+        if b and b[0] == g[0] and b[1] == g[1] and abs(g[2] - b[2][-1][2]) < 0.25 * b[2][-1][2]:
+            b[2].append(g)
+        else:
+            blocks.append([g[0], g[1], [g]])
+    print(f"# command: {cmd}")
+    print("# chained add/sub launches in dispatch order (rocprofv3 --kernel-trace); a deferred launch")
+    print("# is the scan kernel + k_defer_scan + k_defer_fill; first to last is the first dispatch's")
+    print("# start to the fill's end; microseconds, means over the block")
+    print(f"{'block':>5s} {'kernel':44s} {'form':9s} {'launches':>8s} {'scan_kernel':>11s} {'status_scan':>11s} "
+          f"{'fill':>8s} {'first_to_last':>13s}")
+    for i, (name, deferred, gs) in enumerate(blocks):
+        k = len(gs)
+        m = lambda j: sum(g[j] for g in gs) / k
+        span = sum((g[6] - g[5]) / 1e3 for g in gs) / k
+        print(f"{i:5d} {name[:44]:44s} {'deferred' if deferred else 'waiting':9s} {k:8d} {m(2):11.1f} {m(3):11.1f} "
+              f"{m(4):8.1f} {span:13.1f}")
 
 
 def _counter_rows(path):
@@ -122,6 +160,8 @@ def traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
 if __name__ == "__main__":
     if sys.argv[1] == "traffic":
         traffic(*sys.argv[2:6])
+    elif sys.argv[1] == "launches":
+        launches(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3])
     else:

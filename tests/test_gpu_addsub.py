@@ -292,9 +292,11 @@ def test_self_help_every_tile(bnctx, op):
 @pytest.mark.parametrize("n,npairs", [((1 << 20) + 5, 1), (100003, 7)])
 def test_lookback_histogram_counts_every_chained_tile(bnctx, op, n, npairs):
     """With debug flag bit 1 every tile that looks back records one distance: the
-    histogram total is the number of tiles that do not start a segment."""
+    histogram total is the number of tiles that do not start a segment (launches that
+    wait: all-propagate tiles of deferred launches do not look back)."""
     announce("look-back histogram", op, f"n={n}", f"npairs={npairs}")
     old = bn.bn_get_param(bnctx, "debug.flags")
+    old_defer = bn.bn_get_param(bnctx, "addsub.defer_tiles")
     waves = bn.bn_get_param(bnctx, "addsub.chain_waves")
     rows = bn.bn_get_param(bnctx, "addsub.chain_rows")
     N = n * npairs
@@ -308,11 +310,13 @@ def test_lookback_histogram_counts_every_chained_tile(bnctx, op, n, npairs):
     a, b = wl.c3(op, n=N, worst=True)
     bn.bn_lookback_stats(bnctx)  # clear
     try:
+        bn.bn_set_param(bnctx, "addsub.defer_tiles", 0)
         bn.bn_set_param(bnctx, "debug.flags", 2)
         _check(bnctx, op, a, b, n, npairs)
         h = bn.bn_lookback_stats(bnctx)
     finally:
         bn.bn_set_param(bnctx, "debug.flags", old)
+        bn.bn_set_param(bnctx, "addsub.defer_tiles", old_defer)
     assert sum(h) == expect, (sum(h), expect, h)
     assert all(v == 0 for v in h[max(1, ntiles.bit_length()):]), h
     # not recorded with the flag off
