@@ -154,10 +154,20 @@ struct ScanMem {
     std::atomic<u64> *host_epoch = nullptr;  // epochs of launches outside a capture
     u32 dbg_mask = ~0u;                      // debug flags that apply
 };
+// The child products of a Karatsuba level of N products of out <= 4k limbs, for the
+// scan that forms and adds the level's terms (launch_flat_scan_comb): per product q,
+// P0, P1 and PD at 2k q (2k limbs each), the signs of its two differences in negA[q],
+// negB[q].
+struct ScanComb {
+    const u64 *P0 = nullptr, *P1 = nullptr, *PD = nullptr;
+    const u64 *negA = nullptr, *negB = nullptr;
+    u64 k = 0;
+};
+bn_status launch_flat_scan_comb(bn_ctx *ctx, u64 *r, const ScanComb &comb, u64 out, u64 N, hipStream_t s);
 // nbz >= 0: b holds nbz limbs per pair (its pair stride) and reads as zero past them.
 bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                                const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s,
-                               const ScanMem *fixed, i64 nbz = -1);
+                               const ScanMem *fixed, i64 nbz = -1, const ScanComb *comb = nullptr);
 // Unequal lengths, batched: pair p is a + p na, b + p nb (nb <= na), r + p na, and
 // r_p = a_p +- b_p with b_p zero-extended to na limbs; one pass.
 bn_status launch_flat_scan_bzx(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,

@@ -98,6 +98,7 @@ struct ScanGeom {
     u64 nbz;           // EXT_BZX: limbs of b per pair (b's pair stride); b reads as 0 past them
     u32 defer;         // chained launches: no tile waits for another's look-back (see k_flat_scan, phase 3)
     uint8_t *codes;    // deferred launches: one byte per tile (1: its carry-in repair is left to the fill pass)
+    ScanComb comb;     // EXT_COMB: the terms of a Karatsuba combine
 };
 
 // Kernel variants beyond the plain a +- b: a per-segment carry-in, b given as one limb
@@ -106,6 +107,29 @@ struct ScanGeom {
 // pair (its own pair stride nbz, zero-extended to the segment length: the unequal
 // lengths of the proof of Theorem 2).
 constexpr int EXT_CIN = 1, EXT_BCONST = 2, EXT_BZX = 4;
+// EXT_COMB: the sum is a Karatsuba level's result formed from its three child products
+// (a and b unused): product q (segment of n = out limbs) is
+//     P0 + P1 X^(2k) + (P0 + P1 -+ PD) X^k,
+// with -PD when the two halves' differences had the same sign.  Its limb i term
+//     v_i = [i < 2k] P0_i + [i >= 2k] P1_(i-2k) + [k <= i < 3k] (P0_t + P1_t -+ PD_t),  t = i - k,
+// lies in (-2^64, 2^66) and is taken as v_i + 2^64 - [i > 0] in [0, 2^67) (the offsets
+// add up to X^out, zero modulo X^out, and the product fits out limbs): the scan adds
+// its low word and the high word of the limb below, whose sum has single-bit carries.
+constexpr int EXT_COMB = 8;
+
+// v_i + 2^64 - [i > 0] of product q (EXT_COMB).
+__device__ __forceinline__ unsigned __int128 comb_term(const ScanComb &C, u64 q, u64 i) {
+    typedef unsigned __int128 u128;
+    const u64 k = C.k, base = 2 * k * q;
+    u128 v = (u128)(i < 2 * k ? C.P0[base + i] : C.P1[base + i - 2 * k]) + ((u128)1 << 64) - (i > 0 ? 1u : 0u);
+    if (i >= k && i < 3 * k) {
+        const u64 t = i - k;
+        v += (u128)C.P0[base + t] + C.P1[base + t];
+        const u64 d = C.PD[base + t];
+        v = C.negA[q] == C.negB[q] ? v - d : v + d;
+    }
+    return v;
+}
 
 // Limb of b that meets limb idx = q n + pos of a.
 template <int EXT>
@@ -138,9 +162,24 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
         bool g0 = false, p0 = false, g1 = false, p1 = false;
         u64 s;
         const bool wrap = pos + 1 == G.n;  // limb i0 + 1 starts the next segment
-        if (i0 < hi) limb_gp<SUB>(a[i0], b_limb<EXT>(b, G, i0, q, pos), s, g0, p0);
-        if (i0 + 1 < hi)
-            limb_gp<SUB>(a[i0 + 1], b_limb<EXT>(b, G, i0 + 1, wrap ? q + 1 : q, wrap ? 0 : pos + 1), s, g1, p1);
+        if constexpr ((EXT & EXT_COMB) != 0) {
+            // the terms of both limbs and of the limb below (see comb_term)
+            unsigned __int128 v0 = 0, v1 = 0;
+            u64 yb = 0;
+            if (i0 < hi) {
+                v0 = comb_term(G.comb, q, pos);
+                if (pos > 0) yb = (u64)(comb_term(G.comb, q, pos - 1) >> 64);
+                limb_gp<SUB>((u64)v0, yb, s, g0, p0);
+            }
+            if (i0 + 1 < hi) {
+                v1 = comb_term(G.comb, wrap ? q + 1 : q, wrap ? 0 : pos + 1);
+                limb_gp<SUB>((u64)v1, wrap ? 0ull : (u64)(v0 >> 64), s, g1, p1);
+            }
+        } else {
+            if (i0 < hi) limb_gp<SUB>(a[i0], b_limb<EXT>(b, G, i0, q, pos), s, g0, p0);
+            if (i0 + 1 < hi)
+                limb_gp<SUB>(a[i0 + 1], b_limb<EXT>(b, G, i0 + 1, wrap ? q + 1 : q, wrap ? 0 : pos + 1), s, g1, p1);
+        }
         // a segment's first limb takes the segment's carry-in, not its neighbour's carry
         g0 = g0 || (pos == 0 && p0 && seg_cin<EXT>(G, q));
         g1 = g1 || (pos + 1 == G.n && i0 + 1 < hi && p1 && seg_cin<EXT>(G, q + 1));
@@ -269,7 +308,72 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     const bool full = VEC && (t + 1) * TL <= N;
     u64 x0[ROWS], x1[ROWS], y0[ROWS], y1[ROWS];
     constexpr bool BC = (EXT & EXT_BCONST) != 0;
-    if constexpr ((EXT & EXT_BZX) != 0) {
+    if constexpr ((EXT & EXT_COMB) != 0) {
+        // x = low word of the limb's term, y = high word of the term one limb down (0
+        // at a segment start): from the lane below, lane 63 of the row below, or, for
+        // the wave's first limb, computed here.  Every row's loads go out first
+        // (predicated, no branch between a load and the next), then the arithmetic.
+        const ScanComb &C = G.comb;
+        const u64 k = C.k;
+        u64 q, pos;
+        divmod_u64(idx0, n, G.nshift, q, pos);
+        u32 hprev = 0;  // high word of the term below the wave's first limb
+        if (lane == 0 && pos > 0 && idx0 < N) hprev = (u32)(comb_term(C, q, pos - 1) >> 64);
+        u64 lm[ROWS][2], l0[ROWS][2], l1[ROWS][2], ld[ROWS][2];  // main, P0_t, P1_t, PD_t
+        bool mid[ROWS][2], same[ROWS][2], inb[ROWS][2], st[ROWS][2];
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const u64 idx = idx0 + (u64)j * 128;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const bool wrap = e == 1 && pos + 1 == n;  // limb idx + 1 starts the next segment
+                const u64 qq = wrap ? q + 1 : q, ii = e == 0 ? pos : (wrap ? 0 : pos + 1);
+                const u64 base = 2 * k * qq;
+                const bool in = idx + e < N;
+                const bool md = in && ii >= k && ii < 3 * k;
+                const u64 t = md ? ii - k : 0;
+                const u64 *pm = ii < 2 * k ? C.P0 + base + ii : C.P1 + base + ii - 2 * k;
+                lm[j][e] = in ? *pm : 0ull;
+                l0[j][e] = md ? C.P0[base + t] : 0ull;
+                l1[j][e] = md ? C.P1[base + t] : 0ull;
+                ld[j][e] = md ? C.PD[base + t] : 0ull;
+                same[j][e] = in && C.negA[qq] == C.negB[qq];
+                mid[j][e] = md;
+                inb[j][e] = in;
+                st[j][e] = ii == 0;
+            }
+            pos += step_mod;
+            q += step_div;
+            if (pos >= n) {
+                pos -= n;
+                q += 1;
+            }
+        }
+        u32 h1[ROWS];
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            unsigned __int128 v[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                unsigned __int128 w = (unsigned __int128)lm[j][e] + ((unsigned __int128)1 << 64) - (st[j][e] ? 0u : 1u);
+                if (mid[j][e]) {
+                    w += (unsigned __int128)l0[j][e] + l1[j][e];
+                    w = same[j][e] ? w - ld[j][e] : w + ld[j][e];
+                }
+                v[e] = inb[j][e] ? w : 0;
+            }
+            x0[j] = (u64)v[0];
+            x1[j] = (u64)v[1];
+            y1[j] = st[j][1] ? 0ull : (u64)(v[0] >> 64);
+            h1[j] = (u32)(v[1] >> 64);
+        }
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+            const u32 below = (u32)__shfl_up((int)h1[j], 1);
+            const u32 first = j == 0 ? hprev : (u32)__builtin_amdgcn_readlane((int)h1[j - 1], 63);
+            y0[j] = st[j][0] ? 0ull : (u64)(lane == 0 ? first : below);
+        }
+    } else if constexpr ((EXT & EXT_BZX) != 0) {
         // b limbs by segment position (8-byte loads; consecutive lanes still read
         // consecutive limbs inside a pair)
         u64 q, pos;
@@ -800,6 +904,16 @@ bn_status launch_fill_u64(u64 *p, u64 count, u64 value, hipStream_t s) {
 // and 4 x 1 tiles, so that a small launch still spreads over the device.
 template <bool SUB, int EXT>
 static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
+    if constexpr (EXT == EXT_COMB) {  // at most 4 rows: every row's term loads are held at once
+        if (vec && chain) {
+            if (rows == 1) return k_flat_scan<SUB, 4, 1, true, true, EXT>;
+            if (rows == 2) return k_flat_scan<SUB, 4, 2, true, true, EXT>;
+            return k_flat_scan<SUB, 4, 4, true, true, EXT>;
+        }
+        if (vec) return k_flat_scan<SUB, 1, 1, true, false, EXT>;
+        return chain ? k_flat_scan<SUB, UNALIGNED_CHAIN_WAVES, UNALIGNED_CHAIN_ROWS, false, true, EXT>
+                     : k_flat_scan<SUB, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false, EXT>;
+    }
     if (vec && chain && EXT == EXT_BCONST) {
         if (rows == 1) return k_flat_scan<SUB, 4, 1, true, true, EXT>;
         if (rows == 2) return k_flat_scan<SUB, 4, 2, true, true, EXT>;
@@ -812,12 +926,12 @@ static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
 
 bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                              const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s, const ScanMem *fixed,
-                             i64 nbz) {
+                             i64 nbz, const ScanComb *comb) {
     const u64 N = n * npairs;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
     const bool bzx = nbz >= 0;
     const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst || bzx ? nullptr : b)) & 15u) == 0;
-    const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0) | (bzx ? EXT_BZX : 0);
+    const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0) | (bzx ? EXT_BZX : 0) | (comb ? EXT_COMB : 0);
     int waves, rows;
     bool chain;
     if (ext == 0) {
@@ -825,8 +939,8 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     } else {
         chain = (128 % n) != 0;
         waves = chain ? (vec ? 4 : UNALIGNED_CHAIN_WAVES) : 1;
-        rows = chain ? (vec ? 8 : UNALIGNED_CHAIN_ROWS) : 1;
-        if (ext == EXT_BCONST && chain && vec) {  // at least 8 tiles per CU where rows allow
+        rows = chain ? (vec ? (ext == EXT_COMB ? 4 : 8) : UNALIGNED_CHAIN_ROWS) : 1;
+        if ((ext == EXT_BCONST || ext == EXT_COMB) && chain && vec) {  // at least 8 tiles per CU where rows allow
             const u64 want = 8 * (u64)std::max(1, ctx->num_cu);
             while (rows > 1 && (N + (u64)waves * rows * 128 - 1) / ((u64)waves * rows * 128) < want) rows /= 2;
         }
@@ -851,6 +965,8 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         f = pick_ext<false, EXT_BCONST>(vec, chain, rows);
     else if (ext == EXT_BZX)
         f = sub ? pick_ext<true, EXT_BZX>(vec, chain) : pick_ext<false, EXT_BZX>(vec, chain);
+    else if (ext == EXT_COMB && !sub)
+        f = pick_ext<false, EXT_COMB>(vec, chain, rows);
     else if (ext != 0)
         return BN_EINVAL;
     else if (vec)
@@ -885,6 +1001,7 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     uint8_t *codes = chain ? reinterpret_cast<uint8_t *>(status + (fixed ? fixed->max_tiles : ntiles)) : nullptr;
     ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u, bzx ? (u64)nbz : 0, defer ? 1u : 0u, codes};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
+    if (comb) G.comb = *comb;
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
                        ctl, status, ctx->tune.spin_limit, dbg);
     bn_status st = bn_launch_status();
@@ -904,6 +1021,11 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
 bn_status launch_flat_scan_ext(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                                const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s) {
     return launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, cin, bconst, bval, carry, s, nullptr, -1);
+}
+
+bn_status launch_flat_scan_comb(bn_ctx *ctx, u64 *r, const ScanComb &comb, u64 out, u64 N, hipStream_t s) {
+    return launch_flat_scan_mem(ctx, false, r, nullptr, nullptr, out, N, nullptr, false, 0, nullptr, s, nullptr, -1,
+                                &comb);
 }
 
 bn_status launch_flat_scan_bzx(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,

@@ -15,12 +15,13 @@
 // schoolbook kernels in one launch, and the levels are combined bottom-up.  Batches
 // are stored by kind: children [0, N) are the (A_L, B_L) halves, [N, 2N) the
 // (A_H, B_H) halves and [2N, 3N) the absolute differences, so every add/sub of the
-// split and of the combine is a uniform batch over contiguous arrays.  Both are a
+// split and of the combine is a uniform batch over contiguous arrays.  The split is a
 // streaming pass and one carry scan: the signs of A_H - A_L and B_H - B_L come first
-// (the highest limb where the halves differ, found piece by piece),
-// then every limb of |A_H - A_L| and of P0 + P1 X^2 + (P0 + P1 - P2) X is a signed
-// sum of a few limbs, stored biased as a low word and a small high word, and one
-// flat carry scan adds the two.
+// (the highest limb where the halves differ, found piece by piece), then every limb of
+// |A_H - A_L| is a signed sum of two limbs, stored biased as a low word and a small
+// high word, and one flat carry scan adds the two.  The combine is one carry scan
+// that forms every limb of P0 + P1 X^2 + (P0 + P1 - P2) X from the child products
+// itself (the scan's EXT_COMB variant, same biased terms).
 #include "bn_internal.h"
 
 #include <algorithm>
@@ -46,7 +47,8 @@ __device__ __forceinline__ u64 src_limb(const SplitSrc &s, u64 q, u64 i) {
 // (equal halves, as in all-ones or zero operands, leave nothing to stop early on):
 // one workgroup per piece of SIGN_PIECE limbs of an operand finds the highest limb i
 // where the halves differ and writes key = (i + 1) * 2 + [hi_i < lo_i] (0: no
-// difference); then the largest key of an operand's pieces gives its sign.
+// difference); then the largest key of an operand's pieces gives its sign (reduced by
+// the split kernel itself).
 constexpr u64 SIGN_PIECE = 2048;  // 256 threads x 8 limbs
 
 __global__ __launch_bounds__(256) void k_split_sign_pieces(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 npieces,
@@ -76,27 +78,33 @@ __global__ __launch_bounds__(256) void k_split_sign_pieces(SplitSrc a, SplitSrc 
     if (threadIdx.x == 0) keys[blockIdx.x] = std::max(std::max(sh[0], sh[1]), std::max(sh[2], sh[3]));
 }
 
-__global__ void k_split_sign_reduce(const u64 *__restrict__ keys, u64 N, u64 npieces, u64 *__restrict__ negA,
-                                    u64 *__restrict__ negB) {
-    const u64 seg = blockIdx.x * (u64)blockDim.x + threadIdx.x;
-    if (seg >= 2 * N) return;
-    u64 m = 0;
-    for (u64 p = 0; p < npieces; ++p) m = std::max(m, keys[seg * npieces + p]);
-    if (seg < N) negA[seg] = m & 1;
-    else negB[seg - N] = m & 1;
-}
-
 // For both operands: the children lo and hi (copies, to dst_x and dst_x + N k) and the
 // terms of |hi - lo| = s (hi - lo), s = -1 when neg_x[q]: at limb i the value
 // s (hi_i - lo_i) + 2^64 - [i > 0] lies in [0, 2^65); its low word goes to L_x, its
 // high word (0 or 1) to H_x one limb up.  The offsets add up to X^k (zero modulo X^k),
-// so L_x + H_x is |hi - lo|.
-__global__ void k_split_terms(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 *__restrict__ da, u64 *__restrict__ db,
-                              const u64 *__restrict__ negA, const u64 *__restrict__ negB, u64 *__restrict__ L,
-                              u64 *__restrict__ H) {
-    const u64 total = N * k;
-    for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
-        const u64 q = idx / k, i = idx - q * k;
+// so L_x + H_x is |hi - lo|.  Workgroup (q, c) takes limbs [c C, c C + C) of operand
+// pair q (C = SPLIT_CHUNK); two of its threads first reduce the pair's sign keys (the
+// largest key of its pieces), and chunk 0 stores the signs for the combine.
+constexpr u64 SPLIT_CHUNK = 512;
+__global__ __launch_bounds__(256) void k_split_terms(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 npieces,
+                                                     const u64 *__restrict__ keys, u64 *__restrict__ da,
+                                                     u64 *__restrict__ db, u64 *__restrict__ negA,
+                                                     u64 *__restrict__ negB, u64 *__restrict__ L,
+                                                     u64 *__restrict__ H) {
+    __shared__ u32 sh_neg[2];
+    const u64 nch = (k + SPLIT_CHUNK - 1) / SPLIT_CHUNK;
+    const u64 q = blockIdx.x / nch, c = blockIdx.x - q * nch;
+    if (threadIdx.x < 2) {
+        const u64 *kk = keys + ((threadIdx.x ? N : 0) + q) * npieces;
+        u64 m = 0;
+        for (u64 p = 0; p < npieces; ++p) m = std::max(m, kk[p]);
+        sh_neg[threadIdx.x] = (u32)(m & 1);
+        if (c == 0) (threadIdx.x ? negB : negA)[q] = m & 1;
+    }
+    __syncthreads();
+    const u64 total = N * k, iend = std::min(k, (c + 1) * SPLIT_CHUNK);
+    for (u64 i = c * SPLIT_CHUNK + threadIdx.x; i < iend; i += 256) {
+        const u64 idx = q * k + i;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const SplitSrc &x = side ? b : a;
@@ -104,7 +112,7 @@ __global__ void k_split_terms(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 *__restr
             const u64 lo = src_limb(x, q, i), hi = src_limb(x, q, k + i);
             d[idx] = lo;
             d[total + idx] = hi;
-            const bool neg = (side ? negB : negA)[q] != 0;
+            const bool neg = sh_neg[side] != 0;
             const u128 v = (u128)(neg ? lo : hi) - (neg ? hi : lo) + ((u128)1 << 64) - (i > 0 ? 1u : 0u);
             u64 *l = L + side * total, *h = H + side * total;
             l[idx] = (u64)v;
@@ -114,36 +122,6 @@ __global__ void k_split_terms(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 *__restr
     }
 }
 
-// The terms of a level's result, per product q (`out` limbs, out <= 4k): at limb i,
-//     v_i = [i < 2k] P0_i + [i >= 2k] P1_(i-2k) + [k <= i < 3k] (P0_t + P1_t -+ PD_t),  t = i - k,
-// with -PD when the two differences have the same sign (P2 = +PD) and +PD otherwise.
-// v_i lies in (-2^64, 2^66); stored as v_i + 2^64 - [i > 0] (in [0, 2^67)): the low
-// word to L, the high word to H one limb up (H_0 = 0).  The offsets add up to
-// sum_{i < out} (X - [i > 0]) X^i = X^out, zero modulo X^out, the terms of limbs at or
-// above `out` are multiples of X^out, and the product fits `out` limbs (2m at a level
-// of m-limb operands, na + nb at the top), so L + H modulo X^out (one carry scan,
-// single-bit carries: H <= 4) is the product.
-__global__ void k_combine_terms(u64 *__restrict__ L, u64 *__restrict__ H, const u64 *__restrict__ P0,
-                                const u64 *__restrict__ P1, const u64 *__restrict__ PD, const u64 *__restrict__ negA,
-                                const u64 *__restrict__ negB, u64 N, u64 k, u64 out) {
-    const u64 total = N * out;
-    for (u64 idx = blockIdx.x * (u64)blockDim.x + threadIdx.x; idx < total; idx += (u64)gridDim.x * blockDim.x) {
-        const u64 q = idx / out, i = idx - q * out;
-        const u64 *p0 = P0 + 2 * k * q, *p1 = P1 + 2 * k * q;
-        u128 v = (u128)(i < 2 * k ? p0[i] : p1[i - 2 * k]) + ((u128)1 << 64) - (i > 0 ? 1u : 0u);
-        if (i >= k && i < 3 * k) {
-            const u64 t = i - k;
-            const u64 d = PD[2 * k * q + t];
-            v += (u128)p0[t] + p1[t];
-            v = negA[q] == negB[q] ? v - d : v + d;
-        }
-        L[idx] = (u64)v;
-        if (i + 1 < out) H[idx + 1] = (u64)(v >> 64);
-        if (i == 0) H[idx] = 0;
-    }
-}
-
-u32 stream_blocks(u64 total) { return (u32)std::max<u64>(1, std::min<u64>((total + 255) / 256, 65536)); }
 
 // Workspace layout of a run (u64 offsets).
 struct KLevel {
@@ -155,7 +133,6 @@ struct KLevel {
 struct KPlan {
     std::vector<KLevel> lv;  // 0 .. levels
     u64 d1, d2;              // split terms: low words, shifted high words (a then b, N_l k each)
-    u64 L, H;                // combine terms: low words and shifted high words (N_l out_l each)
     u64 keys;                // split: per-piece sign keys (2 N_l pieces_l, largest level)
     u64 total;               // u64 words
 };
@@ -169,7 +146,7 @@ KPlan karatsuba_plan(u64 na, u64 nb, u64 npairs, int levels) {
         return o;
     };
     p.lv.resize(levels + 1);
-    u64 N = npairs, m = std::max(na, nb), maxNk = 0, maxout = 0, maxkeys = 0;
+    u64 N = npairs, m = std::max(na, nb), maxNk = 0, maxkeys = 0;
     for (int l = 0; l <= levels; ++l) {
         KLevel &L = p.lv[l];
         L.N = N;
@@ -185,7 +162,6 @@ KPlan karatsuba_plan(u64 na, u64 nb, u64 npairs, int levels) {
             L.negA = take(N);
             L.negB = take(N);
             maxNk = std::max(maxNk, N * k);
-            maxout = std::max(maxout, N * L.out);
             maxkeys = std::max(maxkeys, 2 * N * ((k + SIGN_PIECE - 1) / SIGN_PIECE));
         }
         N *= 3;
@@ -193,8 +169,6 @@ KPlan karatsuba_plan(u64 na, u64 nb, u64 npairs, int levels) {
     }
     p.d1 = take(2 * maxNk);  // hi - lo of a, then of b
     p.d2 = take(2 * maxNk);  // lo - hi of a, then of b
-    p.L = take(maxout);
-    p.H = take(maxout);
     p.keys = take(maxkeys);
     p.total = off;
     return p;
@@ -221,7 +195,7 @@ WsNeed karatsuba_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int levels,
     w.kwork = (size_t)p.total * sizeof(u64);
     for (int l = 0; l < levels; ++l) {
         const u64 N = p.lv[l].N, k = (p.lv[l].m + 1) / 2, out = p.lv[l].out;
-        w.status = std::max({w.status, flat_scan_status_bytes(ctx, k, N * k), flat_scan_status_bytes(ctx, out, N * out)});
+        w.status = std::max({w.status, flat_scan_status_bytes(ctx, k, N * k), flat_scan_ext_status_bytes(out, N * out)});
     }
     const KLevel &Bt = p.lv[levels];
     w.work = mul_workspace_bytes(ctx, Bt.m, Bt.m, Bt.N, form);
@@ -250,11 +224,10 @@ bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, u64 na, const 
         hipLaunchKernelGGL(k_split_sign_pieces, dim3((u32)(2 * N * npieces)), dim3(256), 0, s, pa, pb, N, k, npieces,
                            w + p.keys);
         if ((st = bn_launch_status()) != BN_OK) return st;
-        hipLaunchKernelGGL(k_split_sign_reduce, dim3((u32)((2 * N + 255) / 256)), dim3(256), 0, s, w + p.keys, N,
-                           npieces, w + P.negA, w + P.negB);
-        if ((st = bn_launch_status()) != BN_OK) return st;
-        hipLaunchKernelGGL(k_split_terms, dim3(stream_blocks(Nk)), dim3(256), 0, s, pa, pb, N, k, ca, cb, w + P.negA,
-                           w + P.negB, w + p.d1, w + p.d2);
+        const u64 nch = (k + SPLIT_CHUNK - 1) / SPLIT_CHUNK;
+        if (N * nch > 0x7fffffffull) return BN_ERANGE;
+        hipLaunchKernelGGL(k_split_terms, dim3((u32)(N * nch)), dim3(256), 0, s, pa, pb, N, k, npieces, w + p.keys, ca,
+                           cb, w + P.negA, w + P.negB, w + p.d1, w + p.d2);
         if ((st = bn_launch_status()) != BN_OK) return st;
         for (int side = 0; side < 2; ++side)  // |hi - lo| = L + H, the children [2N, 3N)
             if ((st = launch_flat_scan(ctx, false, (side ? cb : ca) + 2 * Nk, w + p.d1 + side * Nk, w + p.d2 + side * Nk,
@@ -270,12 +243,16 @@ bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, u64 na, const 
         const u64 N = P.N, k = C.m, twok = 2 * k;
         const u64 *P0 = w + C.R, *P1 = P0 + N * twok, *PD = P1 + N * twok;
         u64 *out = l == 0 ? r : w + P.R;
-        hipLaunchKernelGGL(k_combine_terms, dim3(stream_blocks(N * P.out)), dim3(256), 0, s, w + p.L, w + p.H, P0, P1,
-                           PD, w + P.negA, w + P.negB, N, k, P.out);
-        if ((st = bn_launch_status()) != BN_OK) return st;
-        // out = P0 + P1 X^2 + (P1 + P0 - P2) X = L + H modulo X^out; the product fits
-        // out limbs, so no carry leaves the top
-        if ((st = launch_flat_scan(ctx, false, out, w + p.L, w + p.H, P.out, N, nullptr, s)) != BN_OK) return st;
+        // out = P0 + P1 X^2 + (P1 + P0 - P2) X, its terms formed inside one carry scan
+        // (modulo X^out: the product fits out limbs, so no carry leaves the top)
+        ScanComb cm;
+        cm.P0 = P0;
+        cm.P1 = P1;
+        cm.PD = PD;
+        cm.negA = w + P.negA;
+        cm.negB = w + P.negB;
+        cm.k = k;
+        if ((st = launch_flat_scan_comb(ctx, out, cm, P.out, N, s)) != BN_OK) return st;
     }
     return BN_OK;
 }
