@@ -762,14 +762,14 @@ __device__ __forceinline__ void defer_fill_tile(u64 *__restrict__ r, u32 c, u64 
         }
         return;
     }
-    // repair with carry-in 1: where the carry stops (offset from lo), 256 limbs a round
+    // repair with carry-in 1: where the carry stops (offset from lo), 256 limbs a pass
     if (threadIdx.x == 0) sh_stop = (u32)(hi - lo);
     __syncthreads();
     for (u64 base = lo; base < hi; base += 256) {
         const u64 i = base + threadIdx.x;
         if (i < hi && ((i > lo && i % n == 0) || r[i] != PV)) atomicMin(&sh_stop, (u32)(i - lo));
         __syncthreads();
-        // later rounds only lower sh_stop to values past this round, so every thread
+        // later passes only lower sh_stop to values past this pass, so every thread
         // takes the same decision here
         if (sh_stop < (u32)(base + 256 - lo)) break;
     }

@@ -240,6 +240,30 @@ def test_products(dctx):
         assert (got == want).all(), f"{na}x{nb} {form}: first bad limb {np.argmax(got != want)}"
 
 
+@pytest.mark.parametrize("offset", [0, 1])
+def test_karatsuba(dctx, offset):
+    """Karatsuba levels: split scans and the combine scan that forms its own terms, in
+    the deferred form, into a 16-byte aligned output and one shifted by a limb (the
+    8-byte kernels).  Operands with long all-ones and zero stretches make the
+    combine's sums propagate across many tiles."""
+    g = np.random.default_rng(31 + offset)
+    for na, nb, npairs, levels, form in ((4096, 4096, 3, 2, "mfma"), (3001, 2500, 2, 1, "mad"),
+                                         (9000, 9000, 1, 3, "auto")):
+        a = g.integers(0, MAX, na * npairs, dtype=np.uint64, endpoint=True)
+        b = g.integers(0, MAX, nb * npairs, dtype=np.uint64, endpoint=True)
+        a[: na // 2] = MAX
+        b[nb // 3: nb // 2] = 0
+        announce("deferred karatsuba", f"na={na}", f"nb={nb}", f"npairs={npairs}", f"levels={levels}", form,
+                 f"offset={offset}")
+        P = (na + nb) * npairs
+        tr = torch.full((P + offset,), 7, dtype=torch.int64, device="cuda")[offset:]
+        bn.bn_mul_karatsuba_batch(dctx, tr, D(a), na, D(b), nb, npairs, levels, form)
+        torch.cuda.synchronize()
+        want = oracle.mul_batch(a, b, na, nb, npairs)
+        got = H(tr)
+        assert (got == want).all(), f"{na}x{nb} L{levels} {form}: first bad limb {np.argmax(got != want)}"
+
+
 def test_param(bnctx):
     old = bn.bn_get_param(bnctx, "addsub.defer_tiles")
     assert old == 8192

@@ -229,3 +229,20 @@ def test_auto_levels_unequal(bnctx):
             assert (r == oracle.mul_batch(a, b, na, nb, 2)).all(), (na, nb)
     finally:
         bn.bn_set_param(bnctx, "mul.karatsuba_limbs", old)
+
+
+@pytest.mark.parametrize("na,nb,npairs,levels", [(4096, 4096, 2, 2), (1001, 777, 3, 1), (97, 97, 5, 3)])
+def test_unaligned_output(bnctx, na, nb, npairs, levels):
+    """An output 8-byte but not 16-byte aligned: the combine scan's 8-byte kernels."""
+    g = np.random.default_rng(na + 3 * levels)
+    a = g.integers(0, MAX, na * npairs, dtype=np.uint64, endpoint=True)
+    b = g.integers(0, MAX, nb * npairs, dtype=np.uint64, endpoint=True)
+    a[:na] = MAX
+    announce("karatsuba unaligned output", f"na={na}", f"nb={nb}", f"npairs={npairs}", f"levels={levels}")
+    P = (na + nb) * npairs
+    tr = torch.full((P + 1,), -1, dtype=torch.int64, device="cuda")[1:]
+    bn.bn_mul_karatsuba_batch(bnctx, tr, D(a), na, D(b), nb, npairs, levels, "mfma")
+    torch.cuda.synchronize()
+    want = oracle.mul_batch(a, b, na, nb, npairs)
+    got = H(tr)
+    assert (got == want).all(), f"first bad limb {np.argmax(got != want)}"
