@@ -99,6 +99,9 @@ struct ScanGeom {
     u32 defer;         // chained launches: no tile waits for another's look-back (see k_flat_scan, phase 3)
     uint8_t *codes;    // deferred launches: one byte per tile (1: its carry-in repair is left to the fill pass)
     ScanComb comb;     // EXT_COMB: the terms of a Karatsuba combine
+    u64 N1;            // two-part launches: limbs of the first part (a whole number of tiles), else 0
+    u64 *r2;           // ... and the second part's arrays (b2 null when b is unused)
+    const u64 *a2, *b2;
 };
 
 // Kernel variants beyond the plain a +- b: a per-segment carry-in, b given as one limb
@@ -299,6 +302,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     constexpr u64 TL = (u64)WAVES * ROWS * 128;
     const u64 N = G.N, n = G.n;
     const u64 idx0 = t * TL + (u64)w * ROWS * 128 + 2 * (u64)lane;
+    // Two-part launches: the tiles past the first part take the second part's arrays
+    // (limb idx of the launch is limb idx - N1 there).  The second part starts a
+    // segment, so no look-back or self-help ever crosses from one part into the other.
+    if (G.N1 != 0 && t * TL >= G.N1) {
+        r = G.r2 - G.N1;
+        a = G.a2 - G.N1;
+        if (G.b2) b = G.b2 - G.N1;
+    }
 
     // ---- phase 1: loads (all rows issued before any use) ----
     // A full tile (the common case) loads without per-row guards so that every
@@ -926,11 +937,24 @@ static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
 
 bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                              const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s, const ScanMem *fixed,
-                             i64 nbz, const ScanComb *comb) {
-    const u64 N = n * npairs;
+                             i64 nbz, const ScanComb *comb, const ScanPart2 *part2) {
+    if (part2 && part2->npairs == 0) part2 = nullptr;
+    if (part2 && (npairs == 0 || n == 0 || cin || nbz >= 0 || comb)) {  // one launch per part
+        bn_status st = launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, cin, bconst, bval, carry, s, fixed, nbz, comb);
+        if (st != BN_OK) return st;
+        return launch_flat_scan_mem(ctx, sub, part2->r, part2->a, part2->b, n, part2->npairs,
+                                    cin ? cin + npairs : nullptr, bconst, bval, carry ? carry + npairs : nullptr, s,
+                                    fixed, nbz, comb);
+    }
+    const u64 N1 = part2 ? n * npairs : 0;
+    const u64 N = n * (npairs + (part2 ? part2->npairs : 0));
+    npairs += part2 ? part2->npairs : 0;
     if (N == 0) return carry ? launch_fill_u64(carry, npairs, 0, s) : BN_OK;
     const bool bzx = nbz >= 0;
-    const bool vec = (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst || bzx ? nullptr : b)) & 15u) == 0;
+    const bool vec =
+        (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst || bzx ? nullptr : b) |
+          (part2 ? ((uintptr_t)part2->r | (uintptr_t)part2->a | (uintptr_t)(bconst ? nullptr : part2->b)) : 0)) &
+         15u) == 0;
     const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0) | (bzx ? EXT_BZX : 0) | (comb ? EXT_COMB : 0);
     int waves, rows;
     bool chain;
@@ -946,6 +970,24 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         }
     }
     const u64 TL = (u64)waves * rows * 128;
+    if (part2) {
+        // one launch only if the first part ends on a tile boundary and every array is
+        // apart from every other (a tile of one part never touches the other's arrays)
+        const u64 N2 = N - N1;
+        const bool apart = !ranges_overlap(r, N1, part2->r, N2) && !ranges_overlap(r, N1, a, N1) &&
+                           !ranges_overlap(r, N1, part2->a, N2) && !ranges_overlap(part2->r, N2, a, N1) &&
+                           !ranges_overlap(part2->r, N2, part2->a, N2) &&
+                           (bconst || (!ranges_overlap(r, N1, b, N1) && !ranges_overlap(r, N1, part2->b, N2) &&
+                                       !ranges_overlap(part2->r, N2, b, N1) &&
+                                       !ranges_overlap(part2->r, N2, part2->b, N2)));
+        if (N1 % TL != 0 || !apart) {
+            const u64 np1 = N1 / n;
+            bn_status st = launch_flat_scan_mem(ctx, sub, r, a, b, n, np1, nullptr, bconst, bval, carry, s, fixed);
+            if (st != BN_OK) return st;
+            return launch_flat_scan_mem(ctx, sub, part2->r, part2->a, part2->b, n, npairs - np1, nullptr, bconst, bval,
+                                        carry ? carry + np1 : nullptr, s, fixed);
+        }
+    }
     const u64 ntiles = (N + TL - 1) / TL;
     if (chain) {
         if (fixed) {
@@ -988,20 +1030,26 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     u64 epoch = 0;
     if (chain && !captured) epoch = fixed ? fixed->host_epoch->fetch_add(1) + 1 : ++ctx->host_epoch;
     // r overlapping an operand: a waiting tile must not read another tile's operands
-    const bool inplace =
-        ranges_overlap(r, N, a, N) || (!bconst && ranges_overlap(r, N, b, bzx ? (u64)nbz * npairs : N));
+    const bool inplace =  // (two-part launches: every array is apart, checked above)
+        !part2 && (ranges_overlap(r, N, a, N) || (!bconst && ranges_overlap(r, N, b, bzx ? (u64)nbz * npairs : N)));
     u32 dbg = ctx->tune.debug_flags & (fixed ? fixed->dbg_mask : ~0u);
     if (inplace) dbg &= ~1u;
     // deferred all-propagate tiles from `addsub.defer_tiles` tiles up (the silent-tile-0
     // debug mode keeps the waiting form: the status scan needs every tile's word)
     const u64 dt = ctx->tune.defer_tiles;
-    const bool defer = chain && dt > 0 && ntiles >= dt && (dbg & 1u) == 0;
+    const bool defer = chain && dt > 0 && ntiles >= dt && (dbg & 1u) == 0 && !part2;
     ScanCtl *ctl = fixed ? fixed->ctl : ctx->ctl;
     u64 *status = fixed ? fixed->status : (u64 *)ctx->status.ptr;
     uint8_t *codes = chain ? reinterpret_cast<uint8_t *>(status + (fixed ? fixed->max_tiles : ntiles)) : nullptr;
     ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u, bzx ? (u64)nbz : 0, defer ? 1u : 0u, codes};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     if (comb) G.comb = *comb;
+    if (part2) {
+        G.N1 = N1;
+        G.r2 = part2->r;
+        G.a2 = part2->a;
+        G.b2 = bconst ? nullptr : part2->b;
+    }
     hipLaunchKernelGGL(f, dim3((u32)ntiles), dim3(waves * 64), 0, s, r, a, b, G, (u64)(128 % n), (u64)(128 / n), carry,
                        ctl, status, ctx->tune.spin_limit, dbg);
     bn_status st = bn_launch_status();

@@ -195,7 +195,8 @@ WsNeed karatsuba_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int levels,
     w.kwork = (size_t)p.total * sizeof(u64);
     for (int l = 0; l < levels; ++l) {
         const u64 N = p.lv[l].N, k = (p.lv[l].m + 1) / 2, out = p.lv[l].out;
-        w.status = std::max({w.status, flat_scan_status_bytes(ctx, k, N * k), flat_scan_ext_status_bytes(out, N * out)});
+        w.status = std::max({w.status, flat_scan_status_bytes(ctx, k, 2 * N * k), flat_scan_status_bytes(ctx, k, N * k),
+                             flat_scan_ext_status_bytes(out, N * out)});
     }
     const KLevel &Bt = p.lv[levels];
     w.work = mul_workspace_bytes(ctx, Bt.m, Bt.m, Bt.N, form);
@@ -229,10 +230,15 @@ bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, u64 na, const 
         hipLaunchKernelGGL(k_split_terms, dim3((u32)(N * nch)), dim3(256), 0, s, pa, pb, N, k, npieces, w + p.keys, ca,
                            cb, w + P.negA, w + P.negB, w + p.d1, w + p.d2);
         if ((st = bn_launch_status()) != BN_OK) return st;
-        for (int side = 0; side < 2; ++side)  // |hi - lo| = L + H, the children [2N, 3N)
-            if ((st = launch_flat_scan(ctx, false, (side ? cb : ca) + 2 * Nk, w + p.d1 + side * Nk, w + p.d2 + side * Nk,
-                                       k, N, nullptr, s)) != BN_OK)
-                return st;
+        // |hi - lo| = L + H, the children [2N, 3N) of both sides: one two-part scan
+        ScanPart2 bside;
+        bside.r = cb + 2 * Nk;
+        bside.a = w + p.d1 + Nk;
+        bside.b = w + p.d2 + Nk;
+        bside.npairs = N;
+        if ((st = launch_flat_scan_mem(ctx, false, ca + 2 * Nk, w + p.d1, w + p.d2, k, N, nullptr, false, 0, nullptr, s,
+                                       nullptr, -1, nullptr, &bside)) != BN_OK)
+            return st;
     }
     // ---- the bottom batch on the schoolbook kernels ----
     const KLevel &Bt = p.lv[levels];

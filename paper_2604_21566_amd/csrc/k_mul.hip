@@ -612,8 +612,9 @@ size_t mul_status_bytes(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int form)
     form = mul_pick_form(ctx, na, nb, form);
     if (mul_one_wave(na + nb, form)) return 0;
     size_t bytes = flat_scan_status_bytes(ctx, na + nb, (na + nb) * npairs);  // the carry pass
-    if (form == BN_MUL_MFMA)  // the operand conversions
-        bytes = std::max({bytes, flat_scan_ext_status_bytes(na, na * npairs), flat_scan_ext_status_bytes(nb, nb * npairs)});
+    if (form == BN_MUL_MFMA)  // the operand conversions (one two-part launch for equal lengths)
+        bytes = std::max({bytes, flat_scan_ext_status_bytes(na, na * npairs), flat_scan_ext_status_bytes(nb, nb * npairs),
+                          na == nb ? flat_scan_ext_status_bytes(na, 2 * na * npairs) : (size_t)0});
     return bytes;
 }
 
@@ -693,12 +694,24 @@ bn_status launch_mul_batch(bn_ctx *ctx, u64 *r, const u64 *a, const u64 *b, u64 
         u64 *ca = reinterpret_cast<u64 *>(ws + L.ca);
         u64 *cb = reinterpret_cast<u64 *>(ws + L.cb);
         u64 *tops = reinterpret_cast<u64 *>(ws + L.tops);
-        // balanced digits: every operand + 0x80...80, the carries out as top digits
-        if ((st = launch_flat_scan_ext(ctx, false, ca, a, nullptr, na, npairs, nullptr, true, XOR80, tops, s)) != BN_OK)
-            return st;
-        if ((st = launch_flat_scan_ext(ctx, false, cb, b, nullptr, nb, npairs, nullptr, true, XOR80, tops + npairs,
-                                       s)) != BN_OK)
-            return st;
+        // balanced digits: every operand + 0x80...80, the carries out as top digits (both
+        // operands in one two-part launch when their lengths agree)
+        if (na == nb) {
+            ScanPart2 bside;
+            bside.r = cb;
+            bside.a = b;
+            bside.npairs = npairs;
+            if ((st = launch_flat_scan_mem(ctx, false, ca, a, nullptr, na, npairs, nullptr, true, XOR80, tops, s,
+                                           nullptr, -1, nullptr, &bside)) != BN_OK)
+                return st;
+        } else {
+            if ((st = launch_flat_scan_ext(ctx, false, ca, a, nullptr, na, npairs, nullptr, true, XOR80, tops, s)) !=
+                BN_OK)
+                return st;
+            if ((st = launch_flat_scan_ext(ctx, false, cb, b, nullptr, nb, npairs, nullptr, true, XOR80, tops + npairs,
+                                           s)) != BN_OK)
+                return st;
+        }
         // (blocks per wave, Toeplitz row groups): both shapes cover 2048 output limbs
         // per workgroup and stage the same LDS window
         const int R = ctx->tune.mfma_rows;
