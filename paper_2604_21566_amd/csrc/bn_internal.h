@@ -164,6 +164,15 @@ struct ScanComb {
     u64 k = 0;
 };
 bn_status launch_flat_scan_comb(bn_ctx *ctx, u64 *r, const ScanComb &comb, u64 out, u64 N, hipStream_t s);
+// Subtraction with the operands swapped per pair: pair q computes b - a instead of
+// a - b when its sign key says so (the largest of keys[q npieces .. q npieces +
+// npieces - 1], bit 0), and the lane holding the pair's first limb stores that sign
+// in neg[q].  Used by a Karatsuba split for |A_H - A_L|.
+struct ScanSwap {
+    const u64 *keys = nullptr;
+    u64 npieces = 0;
+    u64 *neg = nullptr;
+};
 // The second part of a two-part launch: npairs more pairs of the same length whose
 // arrays lie elsewhere (b may be null with bconst); a carry array covers both parts,
 // the first part's pairs first.  One launch when the first part ends on a tile
@@ -177,7 +186,7 @@ struct ScanPart2 {
 bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                                const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s,
                                const ScanMem *fixed, i64 nbz = -1, const ScanComb *comb = nullptr,
-                               const ScanPart2 *part2 = nullptr);
+                               const ScanPart2 *part2 = nullptr, const ScanSwap *swap = nullptr);
 // Unequal lengths, batched: pair p is a + p na, b + p nb (nb <= na), r + p na, and
 // r_p = a_p +- b_p with b_p zero-extended to na limbs; one pass.
 bn_status launch_flat_scan_bzx(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, u64 na, const u64 *b, u64 nb,

@@ -99,6 +99,7 @@ struct ScanGeom {
     u32 defer;         // chained launches: no tile waits for another's look-back (see k_flat_scan, phase 3)
     uint8_t *codes;    // deferred launches: one byte per tile (1: its carry-in repair is left to the fill pass)
     ScanComb comb;     // EXT_COMB: the terms of a Karatsuba combine
+    ScanSwap swap;     // EXT_SWAP: per-pair operand order and its record
     u64 N1;            // two-part launches: limbs of the first part (a whole number of tiles), else 0
     u64 *r2;           // ... and the second part's arrays (b2 null when b is unused)
     const u64 *a2, *b2;
@@ -119,6 +120,15 @@ constexpr int EXT_CIN = 1, EXT_BCONST = 2, EXT_BZX = 4;
 // add up to X^out, zero modulo X^out, and the product fits out limbs): the scan adds
 // its low word and the high word of the limb below, whose sum has single-bit carries.
 constexpr int EXT_COMB = 8;
+// EXT_SWAP (subtraction): pair q computes b - a when its sign says so (ScanSwap).
+constexpr int EXT_SWAP = 16;
+
+// Sign of pair q of an EXT_SWAP launch: bit 0 of the largest of its keys.
+__device__ __forceinline__ bool swap_sign(const ScanSwap &S, u64 q) {
+    u64 m = 0;
+    for (u64 p = 0; p < S.npieces; ++p) m = m > S.keys[q * S.npieces + p] ? m : S.keys[q * S.npieces + p];
+    return (m & 1u) != 0;
+}
 
 // v_i + 2^64 - [i > 0] of product q (EXT_COMB).
 __device__ __forceinline__ unsigned __int128 comb_term(const ScanComb &C, u64 q, u64 i) {
@@ -177,6 +187,15 @@ __device__ void tile_aggregate_from_data(const u64 *__restrict__ a, const u64 *_
             if (i0 + 1 < hi) {
                 v1 = comb_term(G.comb, wrap ? q + 1 : q, wrap ? 0 : pos + 1);
                 limb_gp<SUB>((u64)v1, wrap ? 0ull : (u64)(v0 >> 64), s, g1, p1);
+            }
+        } else if constexpr ((EXT & EXT_SWAP) != 0) {
+            if (i0 < hi) {
+                const bool sw = swap_sign(G.swap, q);
+                limb_gp<SUB>(sw ? b[i0] : a[i0], sw ? a[i0] : b[i0], s, g0, p0);
+            }
+            if (i0 + 1 < hi) {
+                const bool sw = swap_sign(G.swap, wrap ? q + 1 : q);
+                limb_gp<SUB>(sw ? b[i0 + 1] : a[i0 + 1], sw ? a[i0 + 1] : b[i0 + 1], s, g1, p1);
             }
         } else {
             if (i0 < hi) limb_gp<SUB>(a[i0], b_limb<EXT>(b, G, i0, q, pos), s, g0, p0);
@@ -444,10 +463,35 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
     u32 wg = 0, wp = 1;
     {
         u64 pos = pos0, q = q0;
+        u64 sq = ~0ull;  // EXT_SWAP: the pair whose sign sneg holds
+        bool sneg = false;
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const u64 idx = idx0 + (u64)j * 128;
             const bool v0 = idx < N, v1 = idx + 1 < N;
+            if constexpr ((EXT & EXT_SWAP) != 0) {
+                // the pair's operands in the order its sign gives; the lane holding a
+                // pair's first limb records the sign
+                const bool wrap = pos + 1 == n;
+                if (v0 && q != sq) {
+                    sq = q;
+                    sneg = swap_sign(G.swap, q);
+                }
+                const bool n0 = v0 && sneg;
+                const bool n1 = v1 && (wrap ? swap_sign(G.swap, q + 1) : sneg);
+                if (n0) {
+                    const u64 t0 = x0[j];
+                    x0[j] = y0[j];
+                    y0[j] = t0;
+                }
+                if (n1) {
+                    const u64 t1 = x1[j];
+                    x1[j] = y1[j];
+                    y1[j] = t1;
+                }
+                if (v0 && pos == 0) G.swap.neg[q] = n0;
+                if (v1 && wrap) G.swap.neg[q + 1] = n1;
+            }
             u64 s0, s1;
             bool g0, p0, g1, p1;
             limb_gp<SUB>(x0[j], y0[j], s0, g0, p0);
@@ -925,7 +969,7 @@ static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
         return chain ? k_flat_scan<SUB, UNALIGNED_CHAIN_WAVES, UNALIGNED_CHAIN_ROWS, false, true, EXT>
                      : k_flat_scan<SUB, UNALIGNED_BATCH_WAVES, UNALIGNED_BATCH_ROWS, false, false, EXT>;
     }
-    if (vec && chain && EXT == EXT_BCONST) {
+    if (vec && chain && (EXT == EXT_BCONST || EXT == EXT_SWAP)) {
         if (rows == 1) return k_flat_scan<SUB, 4, 1, true, true, EXT>;
         if (rows == 2) return k_flat_scan<SUB, 4, 2, true, true, EXT>;
         if (rows == 4) return k_flat_scan<SUB, 4, 4, true, true, EXT>;
@@ -937,14 +981,25 @@ static scan_fn pick_ext(bool vec, bool chain, int rows = 8) {
 
 bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, const u64 *b, u64 n, u64 npairs,
                              const u64 *cin, bool bconst, u64 bval, u64 *carry, hipStream_t s, const ScanMem *fixed,
-                             i64 nbz, const ScanComb *comb, const ScanPart2 *part2) {
+                             i64 nbz, const ScanComb *comb, const ScanPart2 *part2, const ScanSwap *swap) {
     if (part2 && part2->npairs == 0) part2 = nullptr;
+    // the second part on its own: its pairs' carries, carry-ins and signs follow the first part's
+    auto second_alone = [&](u64 np1) {
+        ScanSwap sw2;
+        if (swap) {
+            sw2 = *swap;
+            sw2.keys += np1 * swap->npieces;
+            sw2.neg += np1;
+        }
+        return launch_flat_scan_mem(ctx, sub, part2->r, part2->a, part2->b, n, part2->npairs, cin ? cin + np1 : nullptr,
+                                    bconst, bval, carry ? carry + np1 : nullptr, s, fixed, nbz, comb, nullptr,
+                                    swap ? &sw2 : nullptr);
+    };
     if (part2 && (npairs == 0 || n == 0 || cin || nbz >= 0 || comb)) {  // one launch per part
-        bn_status st = launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, cin, bconst, bval, carry, s, fixed, nbz, comb);
+        bn_status st =
+            launch_flat_scan_mem(ctx, sub, r, a, b, n, npairs, cin, bconst, bval, carry, s, fixed, nbz, comb, nullptr, swap);
         if (st != BN_OK) return st;
-        return launch_flat_scan_mem(ctx, sub, part2->r, part2->a, part2->b, n, part2->npairs,
-                                    cin ? cin + npairs : nullptr, bconst, bval, carry ? carry + npairs : nullptr, s,
-                                    fixed, nbz, comb);
+        return second_alone(npairs);
     }
     const u64 N1 = part2 ? n * npairs : 0;
     const u64 N = n * (npairs + (part2 ? part2->npairs : 0));
@@ -955,7 +1010,8 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         (((uintptr_t)r | (uintptr_t)a | (uintptr_t)(bconst || bzx ? nullptr : b) |
           (part2 ? ((uintptr_t)part2->r | (uintptr_t)part2->a | (uintptr_t)(bconst ? nullptr : part2->b)) : 0)) &
          15u) == 0;
-    const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0) | (bzx ? EXT_BZX : 0) | (comb ? EXT_COMB : 0);
+    const int ext = (cin ? EXT_CIN : 0) | (bconst ? EXT_BCONST : 0) | (bzx ? EXT_BZX : 0) | (comb ? EXT_COMB : 0) |
+                    (swap ? EXT_SWAP : 0);
     int waves, rows;
     bool chain;
     if (ext == 0) {
@@ -964,7 +1020,7 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         chain = (128 % n) != 0;
         waves = chain ? (vec ? 4 : UNALIGNED_CHAIN_WAVES) : 1;
         rows = chain ? (vec ? (ext == EXT_COMB ? 4 : 8) : UNALIGNED_CHAIN_ROWS) : 1;
-        if ((ext == EXT_BCONST || ext == EXT_COMB) && chain && vec) {  // at least 8 tiles per CU where rows allow
+        if ((ext == EXT_BCONST || ext == EXT_COMB || ext == EXT_SWAP) && chain && vec) {  // >= 8 tiles per CU where rows allow
             const u64 want = 8 * (u64)std::max(1, ctx->num_cu);
             while (rows > 1 && (N + (u64)waves * rows * 128 - 1) / ((u64)waves * rows * 128) < want) rows /= 2;
         }
@@ -982,10 +1038,10 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
                                        !ranges_overlap(part2->r, N2, part2->b, N2)));
         if (N1 % TL != 0 || !apart) {
             const u64 np1 = N1 / n;
-            bn_status st = launch_flat_scan_mem(ctx, sub, r, a, b, n, np1, nullptr, bconst, bval, carry, s, fixed);
+            bn_status st = launch_flat_scan_mem(ctx, sub, r, a, b, n, np1, nullptr, bconst, bval, carry, s, fixed, -1,
+                                                nullptr, nullptr, swap);
             if (st != BN_OK) return st;
-            return launch_flat_scan_mem(ctx, sub, part2->r, part2->a, part2->b, n, npairs - np1, nullptr, bconst, bval,
-                                        carry ? carry + np1 : nullptr, s, fixed);
+            return second_alone(np1);
         }
     }
     const u64 ntiles = (N + TL - 1) / TL;
@@ -1009,6 +1065,8 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
         f = sub ? pick_ext<true, EXT_BZX>(vec, chain) : pick_ext<false, EXT_BZX>(vec, chain);
     else if (ext == EXT_COMB && !sub)
         f = pick_ext<false, EXT_COMB>(vec, chain, rows);
+    else if (ext == EXT_SWAP && sub)
+        f = pick_ext<true, EXT_SWAP>(vec, chain, rows);
     else if (ext != 0)
         return BN_EINVAL;
     else if (vec)
@@ -1044,6 +1102,7 @@ bn_status launch_flat_scan_mem(bn_ctx *ctx, bool sub, u64 *r, const u64 *a, cons
     ScanGeom G{N, n, -1, TL, epoch, cin, npairs, bval, inplace ? 1u : 0u, bzx ? (u64)nbz : 0, defer ? 1u : 0u, codes};
     if ((n & (n - 1)) == 0) G.nshift = __builtin_ctzll(n);
     if (comb) G.comb = *comb;
+    if (swap) G.swap = *swap;
     if (part2) {
         G.N1 = N1;
         G.r2 = part2->r;

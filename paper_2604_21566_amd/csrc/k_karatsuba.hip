@@ -15,11 +15,10 @@
 // schoolbook kernels in one launch, and the levels are combined bottom-up.  Batches
 // are stored by kind: children [0, N) are the (A_L, B_L) halves, [N, 2N) the
 // (A_H, B_H) halves and [2N, 3N) the absolute differences, so every add/sub of the
-// split and of the combine is a uniform batch over contiguous arrays.  The split is a
-// streaming pass and one carry scan: the signs of A_H - A_L and B_H - B_L come first
-// (the highest limb where the halves differ, found piece by piece), then every limb of
-// |A_H - A_L| is a signed sum of two limbs, stored biased as a low word and a small
-// high word, and one flat carry scan adds the two.  The combine is one carry scan
+// split and of the combine is a uniform batch over contiguous arrays.  The split is one
+// pass that copies the halves and finds, piece by piece, the highest limb where they
+// differ, then one subtraction scan (both operands' differences in one launch) that
+// takes lo - hi or hi - lo per pair from those keys.  The combine is one carry scan
 // that forms every limb of P0 + P1 X^2 + (P0 + P1 - P2) X from the child products
 // itself (the scan's EXT_COMB variant, same biased terms).
 #include "bn_internal.h"
@@ -28,8 +27,6 @@
 #include <vector>
 
 namespace {
-
-typedef unsigned __int128 u128;
 
 // Operands of a split: operand q of a side is x + stride q, its limbs past `len` read
 // as zero (len <= stride; at the top level len and stride are the caller's na or nb,
@@ -42,21 +39,23 @@ __device__ __forceinline__ u64 src_limb(const SplitSrc &s, u64 q, u64 i) {
     return i < s.len ? s.x[s.stride * q + i] : 0ull;
 }
 
-// neg_x[q] = [hi < lo] for the halves lo = x[q][0, k), hi = x[q][k, 2k) of the N
-// operands of a and of b, in two steps with a fixed amount of work whatever the data
-// (equal halves, as in all-ones or zero operands, leave nothing to stop early on):
-// one workgroup per piece of SIGN_PIECE limbs of an operand finds the highest limb i
-// where the halves differ and writes key = (i + 1) * 2 + [hi_i < lo_i] (0: no
-// difference); then the largest key of an operand's pieces gives its sign (reduced by
-// the split kernel itself).
+// The children lo = x[q][0, k) and hi = x[q][k, 2k) of the N operands of a and of b
+// (copies, to d_x and d_x + N k), and the signs neg_x[q] = [hi < lo] in two steps with a
+// fixed amount of work whatever the data (equal halves, as in all-ones or zero
+// operands, leave nothing to stop early on): one workgroup per piece of SIGN_PIECE
+// limbs of an operand copies them and writes key = (i + 1) * 2 + [hi_i < lo_i] for the
+// highest limb i where the halves differ (0: no difference); the split scan then takes
+// the largest key of an operand's pieces as its sign.
 constexpr u64 SIGN_PIECE = 2048;  // 256 threads x 8 limbs
 
-__global__ __launch_bounds__(256) void k_split_sign_pieces(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 npieces,
-                                                           u64 *__restrict__ keys) {
+__global__ __launch_bounds__(256) void k_split_halves(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 npieces,
+                                                      u64 *__restrict__ da, u64 *__restrict__ db,
+                                                      u64 *__restrict__ keys) {
     __shared__ u64 sh[4];
     const u64 seg = blockIdx.x / npieces, piece = blockIdx.x - seg * npieces;
     const bool is_b = seg >= N;
     const SplitSrc &x = is_b ? b : a;
+    u64 *d = is_b ? db : da;
     const u64 q = is_b ? seg - N : seg;
     const u64 base = piece * SIGN_PIECE;
     u64 lo[8], hi[8];
@@ -70,6 +69,10 @@ __global__ __launch_bounds__(256) void k_split_sign_pieces(SplitSrc a, SplitSrc 
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const u64 i = base + 256 * u + threadIdx.x;
+        if (i < k) {
+            d[q * k + i] = lo[u];
+            d[N * k + q * k + i] = hi[u];
+        }
         if (hi[u] != lo[u]) key = std::max(key, ((i + 1) << 1) | (hi[u] < lo[u] ? 1u : 0u));
     }
     for (int off = 32; off > 0; off >>= 1) key = std::max(key, (u64)__shfl_xor(key, off));
@@ -78,61 +81,15 @@ __global__ __launch_bounds__(256) void k_split_sign_pieces(SplitSrc a, SplitSrc 
     if (threadIdx.x == 0) keys[blockIdx.x] = std::max(std::max(sh[0], sh[1]), std::max(sh[2], sh[3]));
 }
 
-// For both operands: the children lo and hi (copies, to dst_x and dst_x + N k) and the
-// terms of |hi - lo| = s (hi - lo), s = -1 when neg_x[q]: at limb i the value
-// s (hi_i - lo_i) + 2^64 - [i > 0] lies in [0, 2^65); its low word goes to L_x, its
-// high word (0 or 1) to H_x one limb up.  The offsets add up to X^k (zero modulo X^k),
-// so L_x + H_x is |hi - lo|.  Workgroup (q, c) takes limbs [c C, c C + C) of operand
-// pair q (C = SPLIT_CHUNK); two of its threads first reduce the pair's sign keys (the
-// largest key of its pieces), and chunk 0 stores the signs for the combine.
-constexpr u64 SPLIT_CHUNK = 512;
-__global__ __launch_bounds__(256) void k_split_terms(SplitSrc a, SplitSrc b, u64 N, u64 k, u64 npieces,
-                                                     const u64 *__restrict__ keys, u64 *__restrict__ da,
-                                                     u64 *__restrict__ db, u64 *__restrict__ negA,
-                                                     u64 *__restrict__ negB, u64 *__restrict__ L,
-                                                     u64 *__restrict__ H) {
-    __shared__ u32 sh_neg[2];
-    const u64 nch = (k + SPLIT_CHUNK - 1) / SPLIT_CHUNK;
-    const u64 q = blockIdx.x / nch, c = blockIdx.x - q * nch;
-    if (threadIdx.x < 2) {
-        const u64 *kk = keys + ((threadIdx.x ? N : 0) + q) * npieces;
-        u64 m = 0;
-        for (u64 p = 0; p < npieces; ++p) m = std::max(m, kk[p]);
-        sh_neg[threadIdx.x] = (u32)(m & 1);
-        if (c == 0) (threadIdx.x ? negB : negA)[q] = m & 1;
-    }
-    __syncthreads();
-    const u64 total = N * k, iend = std::min(k, (c + 1) * SPLIT_CHUNK);
-    for (u64 i = c * SPLIT_CHUNK + threadIdx.x; i < iend; i += 256) {
-        const u64 idx = q * k + i;
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const SplitSrc &x = side ? b : a;
-            u64 *d = side ? db : da;
-            const u64 lo = src_limb(x, q, i), hi = src_limb(x, q, k + i);
-            d[idx] = lo;
-            d[total + idx] = hi;
-            const bool neg = sh_neg[side] != 0;
-            const u128 v = (u128)(neg ? lo : hi) - (neg ? hi : lo) + ((u128)1 << 64) - (i > 0 ? 1u : 0u);
-            u64 *l = L + side * total, *h = H + side * total;
-            l[idx] = (u64)v;
-            if (i + 1 < k) h[idx + 1] = (u64)(v >> 64);
-            if (i == 0) h[idx] = 0;
-        }
-    }
-}
-
-
 // Workspace layout of a run (u64 offsets).
 struct KLevel {
     u64 N, m;        // products and operand limbs at this level (m_0 = max(na, nb), m_(l+1) = ceil(m_l / 2))
     u64 out;         // result limbs per product: 2m, na + nb at the top
     u64 A, B, R;     // operands (N x m each) and products (N x 2m) of this level (level >= 1)
-    u64 negA, negB;  // borrows of A_H - A_L and B_H - B_L of this level's split (N each)
+    u64 negA, negB;  // signs of A_H - A_L and B_H - B_L of this level's split (N each, negB = negA + N)
 };
 struct KPlan {
     std::vector<KLevel> lv;  // 0 .. levels
-    u64 d1, d2;              // split terms: low words, shifted high words (a then b, N_l k each)
     u64 keys;                // split: per-piece sign keys (2 N_l pieces_l, largest level)
     u64 total;               // u64 words
 };
@@ -146,7 +103,7 @@ KPlan karatsuba_plan(u64 na, u64 nb, u64 npairs, int levels) {
         return o;
     };
     p.lv.resize(levels + 1);
-    u64 N = npairs, m = std::max(na, nb), maxNk = 0, maxkeys = 0;
+    u64 N = npairs, m = std::max(na, nb), maxkeys = 0;
     for (int l = 0; l <= levels; ++l) {
         KLevel &L = p.lv[l];
         L.N = N;
@@ -159,16 +116,13 @@ KPlan karatsuba_plan(u64 na, u64 nb, u64 npairs, int levels) {
         }
         const u64 k = (m + 1) / 2;
         if (l < levels) {
-            L.negA = take(N);
-            L.negB = take(N);
-            maxNk = std::max(maxNk, N * k);
+            L.negA = take(2 * N);
+            L.negB = L.negA + N;
             maxkeys = std::max(maxkeys, 2 * N * ((k + SIGN_PIECE - 1) / SIGN_PIECE));
         }
         N *= 3;
         m = k;
     }
-    p.d1 = take(2 * maxNk);  // hi - lo of a, then of b
-    p.d2 = take(2 * maxNk);  // lo - hi of a, then of b
     p.keys = take(maxkeys);
     p.total = off;
     return p;
@@ -195,7 +149,7 @@ WsNeed karatsuba_need(const bn_ctx *ctx, u64 na, u64 nb, u64 npairs, int levels,
     w.kwork = (size_t)p.total * sizeof(u64);
     for (int l = 0; l < levels; ++l) {
         const u64 N = p.lv[l].N, k = (p.lv[l].m + 1) / 2, out = p.lv[l].out;
-        w.status = std::max({w.status, flat_scan_status_bytes(ctx, k, 2 * N * k), flat_scan_status_bytes(ctx, k, N * k),
+        w.status = std::max({w.status, flat_scan_ext_status_bytes(k, 2 * N * k), flat_scan_ext_status_bytes(k, N * k),
                              flat_scan_ext_status_bytes(out, N * out)});
     }
     const KLevel &Bt = p.lv[levels];
@@ -222,22 +176,23 @@ bn_status launch_mul_karatsuba(bn_ctx *ctx, u64 *r, const u64 *a, u64 na, const 
         const u64 Nk = N * k;
         const u64 npieces = (k + SIGN_PIECE - 1) / SIGN_PIECE;
         if (2 * N * npieces > 0x7fffffffull) return BN_ERANGE;
-        hipLaunchKernelGGL(k_split_sign_pieces, dim3((u32)(2 * N * npieces)), dim3(256), 0, s, pa, pb, N, k, npieces,
+        hipLaunchKernelGGL(k_split_halves, dim3((u32)(2 * N * npieces)), dim3(256), 0, s, pa, pb, N, k, npieces, ca, cb,
                            w + p.keys);
         if ((st = bn_launch_status()) != BN_OK) return st;
-        const u64 nch = (k + SPLIT_CHUNK - 1) / SPLIT_CHUNK;
-        if (N * nch > 0x7fffffffull) return BN_ERANGE;
-        hipLaunchKernelGGL(k_split_terms, dim3((u32)(N * nch)), dim3(256), 0, s, pa, pb, N, k, npieces, w + p.keys, ca,
-                           cb, w + P.negA, w + P.negB, w + p.d1, w + p.d2);
-        if ((st = bn_launch_status()) != BN_OK) return st;
-        // |hi - lo| = L + H, the children [2N, 3N) of both sides: one two-part scan
+        // |hi - lo| into the children [2N, 3N) of both sides: one two-part subtraction that
+        // takes lo - hi for the pairs whose keys say hi < lo, and records those signs
+        // (negA, then negB) for the combine
         ScanPart2 bside;
         bside.r = cb + 2 * Nk;
-        bside.a = w + p.d1 + Nk;
-        bside.b = w + p.d2 + Nk;
+        bside.a = cb + Nk;
+        bside.b = cb;
         bside.npairs = N;
-        if ((st = launch_flat_scan_mem(ctx, false, ca + 2 * Nk, w + p.d1, w + p.d2, k, N, nullptr, false, 0, nullptr, s,
-                                       nullptr, -1, nullptr, &bside)) != BN_OK)
+        ScanSwap sw;
+        sw.keys = w + p.keys;
+        sw.npieces = npieces;
+        sw.neg = w + P.negA;
+        if ((st = launch_flat_scan_mem(ctx, true, ca + 2 * Nk, ca + Nk, ca, k, N, nullptr, false, 0, nullptr, s, nullptr,
+                                       -1, nullptr, &bside, &sw)) != BN_OK)
             return st;
     }
     // ---- the bottom batch on the schoolbook kernels ----
