@@ -351,9 +351,49 @@ __global__ __launch_bounds__(WAVES * 64) void k_flat_scan(u64 *__restrict__ r, c
         if (lane == 0 && pos > 0 && idx0 < N) hprev = (u32)(comb_term(C, q, pos - 1) >> 64);
         u64 lm[ROWS][2], l0[ROWS][2], l1[ROWS][2], ld[ROWS][2];  // main, P0_t, P1_t, PD_t
         bool mid[ROWS][2], same[ROWS][2], inb[ROWS][2], st[ROWS][2];
+        // Even k, even segments and 16-byte aligned arrays: a lane's two limbs (an even
+        // position and the next) share their segment, their array and their band, so each
+        // array is one 16-byte load.
+        const bool pairs = (k & 1) == 0 && (n & 1) == 0 &&
+                           (((uintptr_t)C.P0 | (uintptr_t)C.P1 | (uintptr_t)C.PD) & 15u) == 0;
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
             const u64 idx = idx0 + (u64)j * 128;
+            if (pairs) {
+                const u64 base = 2 * k * q;
+                const bool in = idx < N;  // N is even: both limbs or neither
+                const bool md = in && pos >= k && pos < 3 * k;
+                const u64 t = md ? pos - k : 0;
+                typedef unsigned long long v2 __attribute__((ext_vector_type(2)));
+                const u64 *pm = pos < 2 * k ? C.P0 + base + pos : C.P1 + base + pos - 2 * k;
+                const v2 vm = in ? *reinterpret_cast<const v2 *>(pm) : v2{0, 0};
+                const v2 v0 = md ? *reinterpret_cast<const v2 *>(C.P0 + base + t) : v2{0, 0};
+                const v2 v1 = md ? *reinterpret_cast<const v2 *>(C.P1 + base + t) : v2{0, 0};
+                const v2 vd = md ? *reinterpret_cast<const v2 *>(C.PD + base + t) : v2{0, 0};
+                const bool sm = in && C.negA[q] == C.negB[q];
+                lm[j][0] = vm.x;
+                lm[j][1] = vm.y;
+                l0[j][0] = v0.x;
+                l0[j][1] = v0.y;
+                l1[j][0] = v1.x;
+                l1[j][1] = v1.y;
+                ld[j][0] = vd.x;
+                ld[j][1] = vd.y;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    same[j][e] = sm;
+                    mid[j][e] = md;
+                    inb[j][e] = in;
+                    st[j][e] = e == 0 && pos == 0;
+                }
+                pos += step_mod;
+                q += step_div;
+                if (pos >= n) {
+                    pos -= n;
+                    q += 1;
+                }
+                continue;
+            }
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const bool wrap = e == 1 && pos + 1 == n;  // limb idx + 1 starts the next segment
