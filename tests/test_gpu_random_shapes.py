@@ -71,3 +71,64 @@ def test_unequal_addsub_random_shapes(bnctx, seed):
     got = H(tr)
     assert (got == want).all(), f"{op} na={na} nb={nb} npairs={npairs}: first bad limb {np.argmax(got != want)}"
     assert (H(tc) == wc).all()
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_addsub_random_forms(bnctx, seed):
+    """Seeded random add/sub batches over the scan's forms: pair lengths from 1 to 3e5
+    limbs, 8-byte or 16-byte alignment, in place or not, the deferred form forced or
+    off, spin limits from 0 up; inputs with long propagate runs."""
+    g = np.random.default_rng(3000 + seed)
+    n = _log_size(g, 1, 300000)
+    npairs = int(g.integers(1, max(2, 1200000 // n) + 1))
+    op = ("add", "sub")[seed % 2]
+    offset = int(g.integers(0, 2))
+    in_place = ("none", "a", "b")[int(g.integers(0, 3))]
+    defer = int(g.choice([0, 1, 64]))
+    spin = int(g.choice([0, 4, 2048]))
+    N = n * npairs
+    a, b = _rand(g, N), _rand(g, N)
+    if op == "sub":  # propagate runs for subtraction are equal limbs
+        m = g.random(N) < 0.3
+        b[m] = a[m]
+    else:
+        m = g.random(N) < 0.3
+        b[m] = ~a[m]
+    want, wc = (oracle.add_batch if op == "add" else oracle.sub_batch)(a, b, n)
+    announce("random add/sub form", seed, op, n, npairs, offset, in_place, defer, spin)
+    old = (bn.bn_get_param(bnctx, "addsub.defer_tiles"), bn.bn_get_param(bnctx, "lookback.spin_limit"))
+    try:
+        bn.bn_set_param(bnctx, "addsub.defer_tiles", defer)
+        bn.bn_set_param(bnctx, "lookback.spin_limit", spin)
+        ta = D(np.concatenate([np.zeros(offset, np.uint64), a]))[offset:]
+        tb = D(np.concatenate([np.zeros(offset, np.uint64), b]))[offset:]
+        tr = {"a": ta, "b": tb}.get(in_place)
+        if tr is None:
+            tr = torch.full((N + offset,), -1, dtype=torch.int64, device="cuda")[offset:]
+        tc = torch.full((npairs,), -1, dtype=torch.int64, device="cuda")
+        (bn.bn_add_n_batch if op == "add" else bn.bn_sub_n_batch)(bnctx, tr, ta, tb, n, npairs, tc)
+        torch.cuda.synchronize()
+        got = H(tr)
+    finally:
+        bn.bn_set_param(bnctx, "addsub.defer_tiles", old[0])
+        bn.bn_set_param(bnctx, "lookback.spin_limit", old[1])
+    assert (got == want).all(), f"{op} n={n} npairs={npairs}: first bad limb {np.argmax(got != want)}"
+    assert (H(tc) == wc).all()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_square_mfma_random(bnctx, seed):
+    """Square MFMA products of random sizes and batch counts: the two operand
+    conversions run as one two-part launch when the first ends on a tile boundary, as
+    two launches otherwise."""
+    g = np.random.default_rng(4000 + seed)
+    n = int(g.choice([520, 777, 1024, 2048, 3001, 4096, 6000]))
+    npairs = int(g.integers(1, 6))
+    a, b = _rand(g, n * npairs), _rand(g, n * npairs)
+    want = oracle.mul_batch(a, b, n, n, npairs)
+    announce("random square mfma", seed, n, npairs)
+    tr = torch.full((2 * n * npairs,), -1, dtype=torch.int64, device="cuda")
+    bn.bn_mul_n_batch(bnctx, tr, D(a), D(b), n, n, npairs, "mfma")
+    torch.cuda.synchronize()
+    got = H(tr)
+    assert (got == want).all(), f"n={n} npairs={npairs}: first bad limb {np.argmax(got != want)}"
