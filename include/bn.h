@@ -397,8 +397,10 @@ bn_status bn_autotune(bn_ctx *ctx, const char *out_json);
 /* Measured device rates, the ceilings the rooflines are also stated against:
  * *mac96_per_s = 32x32-bit multiply-accumulates into a 96-bit sum per second
  * (v_mad_u64_u32 + v_addc_co_u32, the plain form's column step, Alg. 2 phase 2 on
- * 32-bit digits); *mfma_i8_ops_per_s = int8 MFMA operations per second (2 per
- * multiply-add, v_mfma_i32_32x32x32_i8 with independent accumulators); and
+ * random 32-bit digits); *mfma_i8_ops_per_s = int8 MFMA operations per second (2 per
+ * multiply-add, v_mfma_i32_32x32x32_i8 with independent accumulators, on random
+ * operand bytes: the rate depends on the data, and mostly-zero operands run about 25%
+ * faster); and
  * *copy_bytes_per_s = bytes read plus written per second by a 512 MiB device copy
  * with 16-byte non-temporal loads and stores per lane (how the add/sub scan moves
  * its operands), the fastest of 2, 4 or 8 loads in flight per lane.  Each runs over every CU of the context's device.  Synchronises the

@@ -11,35 +11,57 @@
 
 namespace {
 
+// Random 32-bit words for the probes' operands (the rates depend on the data).
+__device__ __forceinline__ int rate_hash(u32 x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return (int)x;
+}
+
 // Rate probes.  k_rate_mac96: eight independent chains per lane of the plain form's
-// instruction pair (v_mad_u64_u32 + v_addc_co_u32, one 32x32 -> 96-bit accumulate).
+// instruction pair (v_mad_u64_u32 + v_addc_co_u32, one 32x32 -> 96-bit accumulate), on
+// random digits as in a product: the wave-uniform digit changes every iteration, the
+// lanes' digits are random.
 __global__ __launch_bounds__(256) void k_rate_mac96(u64 *out, u32 x, u32 y, int iters) {
+    const u32 l = threadIdx.x + 256u * blockIdx.x;
     u64 lo[8];
-    u32 hi[8];
+    u32 hi[8], yk[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         lo[k] = threadIdx.x + k;
         hi[k] = 0;
+        yk[k] = (u32)rate_hash(l * 8 + k + y);
     }
-    for (int i = 0; i < iters; ++i)
+    for (int i = 0; i < iters; ++i) {
+        const u32 xi = x ^ ((u32)i * 0x9e3779b9u);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) mac96(lo[k], hi[k], x, y + k);
+        for (int k = 0; k < 8; ++k) mac96(lo[k], hi[k], xi, yk[k]);
+    }
     u64 sum = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) sum += lo[k] + hi[k];
     out[blockIdx.x * (u64)blockDim.x + threadIdx.x] = sum;
 }
 
-// k_rate_mfma: four independent accumulators per wave of v_mfma_i32_32x32x32_i8.
+// k_rate_mfma: four independent accumulators per wave of v_mfma_i32_32x32x32_i8 on
+// operand bytes that look like a product's digits: hashed (random) bytes, two operand
+// sets alternating so that consecutive MFMAs see different bits.  The rate depends on
+// the data: the same loop on small constant bytes (mostly zero) runs about 25% faster
+// (the part draws less power and holds a higher clock).
 __global__ __launch_bounds__(256) void k_rate_mfma(int *out, int iters) {
-    const int l = (int)threadIdx.x;
-    const v4i p{l, l + 1, l + 2, l + 3}, q{l ^ 5, l ^ 7, l ^ 9, l ^ 11};
+    const u32 l = threadIdx.x + 256u * blockIdx.x;
+    const v4i p{rate_hash(l), rate_hash(l + 77), rate_hash(l + 991), rate_hash(l + 12345)};
+    const v4i q{rate_hash(3 * l + 1), rate_hash(5 * l + 2), rate_hash(7 * l + 3), rate_hash(11 * l + 4)};
+    const v4i p2 = p ^ v4i{0x5a5a5a5a, (int)0xa5a5a5a5, 0x3c3c3c3c, (int)0xc3c3c3c3};
     v16i acc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] = v16i{0};
     for (int i = 0; i < iters; ++i)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(p, q, acc[k], 0, 0, 0);
+        for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8((k & 1) ? p2 : p, q, acc[k], 0, 0, 0);
     u32 sum = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
