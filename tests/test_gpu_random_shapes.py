@@ -28,7 +28,7 @@ def _log_size(g, lo, hi):
     return int(np.exp(g.uniform(np.log(lo), np.log(hi + 1))))
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(24))
 def test_karatsuba_random_shapes(bnctx, seed):
     g = np.random.default_rng(1000 + seed)
     hi = _log_size(g, 1, 3000)
