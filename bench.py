@@ -85,6 +85,26 @@ def gpu_time(fn, reps: int, warmup: int = 1):
     return float(np.mean(ts)), ts
 
 
+def queued_time(torch, fn, k: int, reps: int = 20) -> float:
+    """Median device-side ms per fn() when k calls sit in the stream behind a spin
+    kernel (about 1 ms): the events then time the GPU's work and its dispatch gaps,
+    not the host's enqueue."""
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        torch.cuda._sleep(3_000_000)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / k)
+    return float(np.median(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +395,30 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
                 fn = lambda: f(ctx, tr, ta, tb, 4, 1088, tc)
             ms, _ = gpu_time(fn, 50, 5)
             c1[op + "_direct_us"] = ms * 1e3
+            # device side: the same work queued behind a spin kernel, so that the host's
+            # enqueue time is hidden; 8 back to back per event pair.  Then 8 calls
+            # captured into one graph (the runtime's per-graph launch cost shared by 8).
+            g = bn.bn_graph_capture_batch(ctx, 2, tr, ta, tb, 4, 4, 1088, None, op[4:], s) if op.startswith("mul") \
+                else bn.bn_graph_capture_batch(ctx, 0 if op == "add" else 1, tr, ta, tb, 4, 0, 1088, tc, 0, s)
+            with torch.cuda.stream(s):
+                c1[op + "_device_us"] = queued_time(torch, lambda: bn.bn_graph_launch(g, s), 8) * 1e3
+                c1[op + "_direct_device_us"] = queued_time(torch, fn, 8) * 1e3
+            bn.bn_graph_destroy(g)
+            torch.cuda.synchronize()
+            ref = tr.clone()
+            tr.zero_()
+            g8 = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g8, stream=s, capture_error_mode="thread_local"):
+                for _ in range(8):
+                    fn()
+            with torch.cuda.stream(s):
+                c1[op + "_graph8_us_per_batch"] = queued_time(torch, g8.replay, 1) * 1e3 / 8
+                ms, _ = gpu_time(g8.replay, 50, 5)
+            c1[op + "_graph8_alone_us_per_batch"] = ms * 1e3 / 8
+            torch.cuda.synchronize()
+            if not torch.equal(tr, ref):
+                raise SystemExit(f"c1 {op}: the 8-call graph's output differs from the direct launch's")
+            del g8
         res["c1"] = c1
 
     # ---- c3: one pair of 2^26 limbs (random with runs, and the all-propagate worst case)
