@@ -340,7 +340,9 @@ __device__ __forceinline__ void mul_item_mfma_small(const u64 *__restrict__ a, u
             if (4 + m < (u32)S::BZ) bz[4 + m] = db[k];
             if (m < 4 * nca) aR[4 * nca - 1 - m] = __builtin_bswap64(da[k]);
         }
-        if (lane < 4) bz[lane] = 0ull;
+        // zero pad, from the opaque lane index (lane >> 6 is 0): a literal zero here was
+        // kept in registers across the caller's item loop and spilled
+        if (lane < 4) bz[lane] = (u64)((u32)lane >> 6);
     }
     wave_sync();
 
