@@ -307,7 +307,8 @@ bn_status bn_plan_destroy(bn_plan *plan);
 
 /* Run a planned ragged multiply: one persistent launch (both forms in one kernel when
  * the plan has both); wave k of W resident waves takes pairs k, k+W, ... of the
- * work-sorted list.  Pairs with
+ * work-sorted list, after the couples of small mad items that run two to a wave
+ * ("ragged.pair_small").  Pairs with
  * na + nb > 256 run through the batched path, one call each.  No allocation, no host
  * sync (the plan reserved the workspace; BN_ENOSPACE if it was given up since).
  * BN_EINVAL for a plan of another kind or one built on a context of another device. */
@@ -375,6 +376,10 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "mul.mfma_rows"                    Toeplitz rows per column block of the large MFMA
  *                                      kernel, in groups of 64: 1 or 2 (default 2: the same
  *                                      LDS reads feed twice the MFMAs)
+ *   "ragged.pair_small"                ragged multiplication plans built afterwards: mad
+ *                                      items of at most 32 product limbs whose shorter
+ *                                      operands have the same length run two to a wave, one
+ *                                      per half (1, default), or one each (0)
  *   "lookback.spin_limit"              look-back polls before a tile computes an
  *                                      unpublished predecessor's carry itself
  *   "debug.flags"                      bit 0: tile 0 never publishes its status

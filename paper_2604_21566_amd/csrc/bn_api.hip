@@ -540,6 +540,7 @@ bn_status bn_plan_destroy(bn_plan *plan) {
     DeviceGuard g(plan->device);
     (void)hipDeviceSynchronize();
     if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_pairs) (void)hipFree(plan->d_pairs);
     delete plan;
     return BN_OK;
 }
@@ -618,7 +619,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 static const char *kParamNames =
     "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,addsub.defer_tiles,"
     "mul.crossover_limbs,mul.small_crossover_limbs,mul.crossover_limbs_p64,mul.crossover_limbs_p128,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,mul.karatsuba_limbs,"
-    "lookback.spin_limit,debug.flags,workspace.auto_grow";
+    "ragged.pair_small,lookback.spin_limit,debug.flags,workspace.auto_grow";
 
 const char *bn_param_names(void) { return kParamNames; }
 
@@ -662,6 +663,9 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
     } else if (k == "mul.mfma_rows") {
         if (v != 1 && v != 2) return BN_EINVAL;
         t.mfma_rows = (int)v;
+    } else if (k == "ragged.pair_small") {
+        if (v != 0 && v != 1) return BN_EINVAL;
+        t.ragged_pair = (int)v;
     } else if (k == "lookback.spin_limit") {
         if (v < 0 || v > 0xffffffffll) return BN_EINVAL;
         t.spin_limit = (u32)v;
@@ -694,6 +698,7 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;
     else if (k == "mul.mfma_rows") *v = t.mfma_rows;
     else if (k == "mul.karatsuba_limbs") *v = t.karatsuba_limbs;
+    else if (k == "ragged.pair_small") *v = t.ragged_pair;
     else if (k == "lookback.spin_limit") *v = t.spin_limit;
     else if (k == "debug.flags") *v = t.debug_flags;
     else if (k == "workspace.auto_grow") *v = t.auto_grow;

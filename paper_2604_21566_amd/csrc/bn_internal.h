@@ -56,6 +56,9 @@ struct Tuning {
                                        // workgroups of the large MFMA kernel fit a CU up to 234);
                                        // 0: by size (mfma_window in k_mul.hip)
     int mfma_rows = 2;                 // Toeplitz row groups of 64 per column block (1 or 2)
+    int ragged_pair = 1;               // ragged multiplication plans: mad items of at most 32 product
+                                       // limbs whose shorter operands have the same length run two
+                                       // to a wave (1) or one each (0)
     i64 karatsuba_limbs = 4096;        // BN_KARATSUBA_AUTO: smallest half that is split again
     int auto_grow = 0;                 // 1: a compute call whose workspace is short grows it
                                        // (allocation + device synchronisation, never during a
@@ -112,6 +115,8 @@ struct bn_plan {
     u32 nsmall = 0;                // items run by the persistent kernels
     u32 nsmall_mad = 0;            // of which mad form (they come first in d_items)
     RItem *d_items = nullptr;      // device copy of the small items, each form sorted by work
+    u32 npaired = 0;               // mad items that run two to a wave (d_pairs holds them as
+    RItem *d_pairs = nullptr;      // consecutive couples; they are not among the nsmall)
     std::vector<RItem> large;      // mul items too big for one wave: one batched launch each
     u32 nmad = 0, nmfma = 0;       // items per form
     u64 work = 0;                  // sum of na * nb (mul) or n (add)

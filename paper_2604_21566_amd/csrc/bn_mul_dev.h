@@ -148,6 +148,70 @@ __device__ void mul_item_mad(const u64 *__restrict__ a, u32 na, const u64 *__res
     wave_normalise_store<L>(vlo, vhi, na + nb, r);
 }
 
+// mac96 with the digit x in a vector register (it differs between the two halves of
+// the wave in mul_item_mad_pair).
+__device__ __forceinline__ void mac96v(u64 &lo, u32 &hi, u32 x, u32 y) {
+    u64 cc;
+    asm("v_mad_u64_u32 %0, %1, %3, %4, %0\n\t"
+        "v_addc_co_u32 %2, %1, 0, %2, %1"
+        : "+v"(lo), "=&s"(cc), "+v"(hi)
+        : "v"(x), "v"(y));
+}
+
+// Two products of at most 32 limbs each on one wave: lanes 0-31 compute item 0 as
+// mul_item_mad<1> would on 32 lanes (lane l owns 32-bit columns 2l, 2l + 1), lanes
+// 32-63 item 1.  The shorter operands of the two items must have the same length, so
+// both halves run the same digit steps; the digits of each half's shorter operand come
+// from vector loads of half-uniform addresses.  Lane 32 starts item 1's window: the
+// wave-wide shift would hand it lane 31's element, so it takes 0 instead.  The carry
+// pass runs as two 32-lane scans (each half's masks on their own).
+__device__ void mul_item_mad_pair(const RItem &m0, const RItem &m1, const u64 *__restrict__ a,
+                                  const u64 *__restrict__ b, u64 *__restrict__ r) {
+    const int lane = threadIdx.x & 63;
+    const bool h = lane >= 32;
+    const u32 hl = (u32)lane & 31u;
+    // each item's shorter operand is x (its digits are the steps), the other y
+    const bool sw0 = m0.na > m0.nb, sw1 = m1.na > m1.nb;
+    const u64 *x0 = sw0 ? b + m0.b_off : a + m0.a_off, *y0 = sw0 ? a + m0.a_off : b + m0.b_off;
+    const u64 *x1 = sw1 ? b + m1.b_off : a + m1.a_off, *y1 = sw1 ? a + m1.a_off : b + m1.b_off;
+    const u32 nx = 2 * (sw0 ? m0.nb : m0.na);  // digits of x, the same for both items
+    const u32 ny = h ? 2 * (sw1 ? m1.na : m1.nb) : 2 * (sw0 ? m0.na : m0.nb);
+    const u32 *x32 = reinterpret_cast<const u32 *>(h ? x1 : x0);
+    const u32 *y32 = reinterpret_cast<const u32 *>(h ? y1 : y0);
+    const u32 t0 = 2 * hl;
+    u32 R[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) R[q] = t0 + q < ny ? y32[t0 + q] : 0u;
+    u64 lo[2] = {0, 0};
+    u32 hi[2] = {0, 0};
+    for (u32 s0 = 0; s0 < nx; s0 += 4) {
+        u32 ad[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) ad[s] = s0 + s < nx ? x32[s0 + s] : 0u;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) mac96v(lo[q], hi[q], ad[s], R[(q - s + 4) % 2]);
+            const int k = (1 - s + 4) % 2;
+            const u32 sh = (u32)__builtin_amdgcn_update_dpp(0, (int)R[k], BN_DPP_WAVE_SHR1, 0xf, 0xf, true);
+            R[k] = lane == 32 ? 0u : sh;
+        }
+    }
+    // limb hl of this half's product: V = lo0 + 2^32 lo1 + 2^64 hi0 + 2^96 hi1
+    const u128 v = (u128)lo[0] + ((u128)hi[0] << 64) + ((u128)lo[1] << 32) + ((u128)hi[1] << 96);
+    const u64 vlo = (u64)v, vhi = (u64)(v >> 64);
+    const u32 P = h ? m1.na + m1.nb : m0.na + m0.nb;
+    u64 prev = __shfl_up(vhi, 1);
+    if (hl == 0) prev = 0;
+    const u64 x = vlo + prev;
+    const bool valid = hl < P;
+    const u64 Gm = __ballot(valid && x < prev), Pm = __ballot(valid && x == ~0ull);
+    const u32 G0 = (u32)Gm, P0 = (u32)Pm, G1 = (u32)(Gm >> 32), P1 = (u32)(Pm >> 32);
+    const u32 C0 = ((G0 << 1) + P0) ^ P0, C1 = ((G1 << 1) + P1) ^ P1;
+    const u64 c = ((h ? C1 : C0) >> hl) & 1u;
+    if (valid) r[(h ? m1.r_off : m0.r_off) + hl] = x + c;
+}
+
 // ----------------------------------------------------------------- MFMA form ----
 // Digit convolution as block-Toeplitz products.  With 8-bit digits a_i, b_j and
 // output digit columns t = 32 W + rr (rr < 32):

@@ -17,9 +17,19 @@ namespace {
 
 constexpr int RAGGED_LDS_U64 = SmallMfma<2>::LDS_U64;
 
+// Couples of small mad items (mul_item_mad_pair), wave k taking couples k, k + W, ...
+__device__ __forceinline__ void run_pairs(const RItem *__restrict__ pairs, u32 npaired, u64 *__restrict__ r,
+                                          const u64 *__restrict__ a, const u64 *__restrict__ b) {
+    const u32 W = gridDim.x * 4;
+    for (u32 c = blockIdx.x * 4 + (u32)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6); 2 * c < npaired; c += W)
+        mul_item_mad_pair(pairs[2 * c], pairs[2 * c + 1], a, b, r);
+}
+
 __global__ __launch_bounds__(256) void k_mul_ragged_mad(const RItem *__restrict__ items, u32 nitems,
                                                         u64 *__restrict__ r, const u64 *__restrict__ a,
-                                                        const u64 *__restrict__ b) {
+                                                        const u64 *__restrict__ b, const RItem *__restrict__ pairs,
+                                                        u32 npaired) {
+    run_pairs(pairs, npaired, r, a, b);
     const u32 W = gridDim.x * 4;
     // wave-uniform item index: descriptors, sizes and loop bounds stay scalar
     u32 it = blockIdx.x * 4 + (u32)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -69,8 +79,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
 // six waves and 80 bytes per lane spilled; C4 7% slower).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_mul_ragged_mixed(const RItem *__restrict__ items, u32 nitems,
                                                           u64 *__restrict__ r, const u64 *__restrict__ a,
-                                                          const u64 *__restrict__ b) {
+                                                          const u64 *__restrict__ b, const RItem *__restrict__ pairs,
+                                                          u32 npaired) {
     __shared__ u64 lds[4 * RAGGED_LDS_U64];
+    run_pairs(pairs, npaired, r, a, b);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const u32 W = gridDim.x * 4;
     for (u32 it = blockIdx.x * 4 + w; it < nitems; it += W) {
@@ -205,7 +217,54 @@ bn_status plan_mul_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, int 
         if (x.form != y.form) return x.form == BN_MUL_MAD;
         return (u64)x.na * x.nb > (u64)y.na * y.nb;
     });
+    // Mad items of at most 32 product limbs go two to a wave when their shorter operands
+    // have the same length (the couple then runs the same digit steps): couples by
+    // shorter length, largest first; an item left without a partner stays single.
+    std::vector<RItem> couples;
+    if (ctx->tune.ragged_pair) {
+        std::vector<RItem> rest;
+        rest.reserve(small.size());
+        std::vector<RItem> cand;
+        for (const RItem &x : small) {
+            if (x.form == BN_MUL_MAD && (u64)x.na + x.nb <= 32) cand.push_back(x);
+            else rest.push_back(x);
+        }
+        std::stable_sort(cand.begin(), cand.end(),
+                         [](const RItem &x, const RItem &y) { return std::min(x.na, x.nb) > std::min(y.na, y.nb); });
+        for (size_t i = 0; i < cand.size();) {
+            if (i + 1 < cand.size() && std::min(cand[i].na, cand[i].nb) == std::min(cand[i + 1].na, cand[i + 1].nb)) {
+                couples.push_back(cand[i]);
+                couples.push_back(cand[i + 1]);
+                i += 2;
+            } else {
+                rest.push_back(cand[i]);
+                i += 1;
+            }
+        }
+        if (!couples.empty()) {
+            small.swap(rest);
+            std::stable_sort(small.begin(), small.end(), [](const RItem &x, const RItem &y) {
+                if (x.form != y.form) return x.form == BN_MUL_MAD;
+                return (u64)x.na * x.nb > (u64)y.na * y.nb;
+            });
+        }
+    }
     pl->nsmall_mad = (u32)std::count_if(small.begin(), small.end(), [](const RItem &x) { return x.form == BN_MUL_MAD; });
+    pl->npaired = (u32)couples.size();
+    if (!couples.empty()) {
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+            bn_plan_destroy(pl);
+            return BN_EHIP;
+        }
+        if (hipMalloc(&pl->d_pairs, couples.size() * sizeof(RItem)) != hipSuccess) {
+            bn_plan_destroy(pl);
+            return BN_ENOMEM;
+        }
+        if (hipMemcpy(pl->d_pairs, couples.data(), couples.size() * sizeof(RItem), hipMemcpyHostToDevice) != hipSuccess) {
+            bn_plan_destroy(pl);
+            return BN_EHIP;
+        }
+    }
     bn_status st = upload_plan(ctx, pl, small);
     if (st != BN_OK) {
         bn_plan_destroy(pl);
@@ -244,14 +303,16 @@ bn_status plan_add_ragged(bn_ctx *ctx, const bn_pair *pairs, size_t npairs, bn_p
 
 bn_status launch_mul_ragged(bn_ctx *ctx, const bn_plan *pl, u64 *r, const u64 *a, const u64 *b, hipStream_t s) {
     const u32 nmad = pl->nsmall_mad, nmfma = pl->nsmall - pl->nsmall_mad;
-    if (nmad && nmfma) {
-        hipLaunchKernelGGL(k_mul_ragged_mixed, dim3(persistent_blocks<k_mul_ragged_mixed>(ctx, pl->nsmall)), dim3(256), 0,
-                           s, pl->d_items, pl->nsmall, r, a, b);
+    // work units for the grid size: a couple of paired items counts once
+    const u32 units = pl->nsmall + pl->npaired / 2;
+    if (nmfma && (nmad || pl->npaired)) {
+        hipLaunchKernelGGL(k_mul_ragged_mixed, dim3(persistent_blocks<k_mul_ragged_mixed>(ctx, units)), dim3(256), 0,
+                           s, pl->d_items, pl->nsmall, r, a, b, pl->d_pairs, pl->npaired);
         bn_status st = bn_launch_status();
         if (st != BN_OK) return st;
-    } else if (nmad) {
-        hipLaunchKernelGGL(k_mul_ragged_mad, dim3(persistent_blocks<k_mul_ragged_mad>(ctx, nmad)), dim3(256), 0, s, pl->d_items, nmad,
-                           r, a, b);
+    } else if (nmad || pl->npaired) {
+        hipLaunchKernelGGL(k_mul_ragged_mad, dim3(persistent_blocks<k_mul_ragged_mad>(ctx, units)), dim3(256), 0, s, pl->d_items, nmad,
+                           r, a, b, pl->d_pairs, pl->npaired);
         bn_status st = bn_launch_status();
         if (st != BN_OK) return st;
     } else if (nmfma) {

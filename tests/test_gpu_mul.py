@@ -211,6 +211,92 @@ def test_ragged_c4_full_graph_replay(bnctx):
             bn.bn_plan_destroy(plan)
 
 
+def _check_pool(got, want, desc, what):
+    """Item limbs equal the oracle's; limbs between items keep the -1 fill (nothing is
+    written outside a product)."""
+    inside = np.zeros(got.size, bool)
+    for _, _, ro, na, nb in desc:
+        inside[int(ro):int(ro) + int(na) + int(nb)] = True
+    bad = np.flatnonzero(inside & (got != want))
+    assert bad.size == 0, f"{what}: {bad.size} limbs differ, first at {bad[0]}"
+    assert (got[~inside] == np.uint64(MAX)).all(), f"{what}: a limb outside every product was written"
+
+
+def _tiny_ragged(g, shapes):
+    """Pool layout for the given (na, nb) shapes, gaps between them; every 5th item all-ones."""
+    desc, a_off, b_off, r_off = [], 0, 0, 0
+    for na, nb in shapes:
+        gap = int(g.integers(0, 2))
+        a_off, b_off, r_off = a_off + gap, b_off + gap, r_off + gap
+        desc.append((a_off, b_off, r_off, na, nb))
+        a_off, b_off, r_off = a_off + na, b_off + nb, r_off + na + nb
+    a, b = _rand(g, a_off), _rand(g, b_off)
+    for i in range(0, len(desc), 5):
+        ao, bo, _, na, nb = desc[i]
+        a[ao:ao + na] = MAX
+        b[bo:bo + nb] = MAX
+    return a, b, np.array(desc, np.uint64), r_off
+
+
+@pytest.mark.parametrize("pair", [1, 0])
+@pytest.mark.parametrize("form", ["auto", "mad"])
+def test_ragged_small_mad_pairs(bnctx, form, pair):
+    """Mad items of at most 32 product limbs run two to a wave when their shorter operands
+    have equal length (ragged.pair_small 1, the default): couples at every shorter length
+    1..16, products of exactly 32 limbs, items of 33 limbs beside them (never paired),
+    items left without a partner, the larger operand first or second, all-ones items (the
+    longest carries); every limb against the oracle, and the same with pairing off."""
+    g = np.random.default_rng(21 + pair)
+    shapes = []
+    for s in range(1, 17):
+        for _ in range(int(g.integers(1, 6))):  # odd counts leave an item without a partner
+            l = int(g.integers(s, 33 - s + 1))  # longer operand: product of at most 32 limbs
+            shapes.append((s, l) if g.integers(0, 2) else (l, s))
+    shapes += [(16, 16), (16, 16), (1, 31), (31, 1), (17, 16), (16, 17), (1, 32), (32, 1), (20, 13)]
+    shapes += [(int(x), int(y)) for x, y in g.integers(1, 30, (300, 2))]
+    order = g.permutation(len(shapes))
+    a, b, desc, rsz = _tiny_ragged(g, [shapes[i] for i in order])
+    announce("ragged mul: small mad pairs", form, f"pair={pair}", f"items={len(desc)}")
+    old = bn.bn_get_param(bnctx, "ragged.pair_small")
+    bn.bn_set_param(bnctx, "ragged.pair_small", pair)
+    try:
+        plan = bn.bn_plan_mul_ragged(bnctx, desc, form)
+    finally:
+        bn.bn_set_param(bnctx, "ragged.pair_small", old)
+    try:
+        tr = torch.full((rsz,), -1, dtype=torch.int64, device="cuda")
+        bn.bn_mul_ragged(bnctx, plan, tr, D(a), D(b))
+        torch.cuda.synchronize()
+        _check_pool(H(tr), oracle.mul_ragged(a, b, desc, rsz), desc, f"{form} pair={pair}")
+    finally:
+        bn.bn_plan_destroy(plan)
+
+
+def test_ragged_only_pairs(bnctx):
+    """A batch of nothing but pairable items (one kernel path: couples, no single items),
+    captured in a graph and replayed."""
+    g = np.random.default_rng(23)
+    shapes = [(7, 9), (9, 7), (7, 25), (3, 3), (3, 29), (12, 20), (20, 12)] * 40
+    a, b, desc, rsz = _tiny_ragged(g, shapes)
+    announce("ragged mul: pairs only", f"items={len(desc)}")
+    rr = oracle.mul_ragged(a, b, desc, rsz)
+    ta, tb = D(a), D(b)
+    tr = torch.full((rsz,), -1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    plan = bn.bn_plan_mul_ragged(bnctx, desc, "mad")
+    g_ = bn.bn_graph_capture_mul_ragged(bnctx, plan, tr, ta, tb, s)
+    try:
+        for rep in range(2):
+            tr.fill_(-1)
+            torch.cuda.synchronize()
+            bn.bn_graph_launch(g_, s)
+            s.synchronize()
+            _check_pool(H(tr), rr, desc, f"replay {rep}")
+    finally:
+        bn.bn_graph_destroy(g_)
+        bn.bn_plan_destroy(plan)
+
+
 def test_ragged_add(bnctx):
     announce("ragged add")
     g = np.random.default_rng(8)
