@@ -6,8 +6,10 @@
 // resident wave count; wave k takes items k, k + W, k + 2W, ... of the sorted
 // list, so every wave gets a similar mix of large and small pairs without any
 // shared counter (same-address atomics serialise at about 10-30 ns each on this
-// part, which would cost more than the products of a 2^16-pair batch).  The
-// launches hold no state between calls, so they can be captured in a HIP graph
+// part, which would cost more than the products of a 2^16-pair batch).  Mad items
+// of at most 32 product limbs whose shorter operands have the same length are
+// coupled by the plan and run two to a wave, one per half, before the other items.
+// The launches hold no state between calls, so they can be captured in a HIP graph
 // and replayed.
 #include "bn_mul_dev.h"
 
