@@ -272,6 +272,24 @@ def test_ragged_small_mad_pairs(bnctx, form, pair):
         bn.bn_plan_destroy(plan)
 
 
+def test_ragged_pairs_and_mfma_items(bnctx):
+    """Couples of small mad items beside MFMA items and no single mad item (the mixed
+    kernel runs the couples, then a list of MFMA items only)."""
+    g = np.random.default_rng(24)
+    shapes = [(5, 9), (9, 5), (11, 21), (21, 11)] * 30 + [(28, 100), (40, 40), (64, 64), (128, 100), (30, 226)] * 12
+    order = g.permutation(len(shapes))
+    a, b, desc, rsz = _tiny_ragged(g, [shapes[i] for i in order])
+    announce("ragged mul: couples and MFMA items", f"items={len(desc)}")
+    plan = bn.bn_plan_mul_ragged(bnctx, desc, "auto")
+    try:
+        tr = torch.full((rsz,), -1, dtype=torch.int64, device="cuda")
+        bn.bn_mul_ragged(bnctx, plan, tr, D(a), D(b))
+        torch.cuda.synchronize()
+        _check_pool(H(tr), oracle.mul_ragged(a, b, desc, rsz), desc, "couples + MFMA")
+    finally:
+        bn.bn_plan_destroy(plan)
+
+
 def test_ragged_only_pairs(bnctx):
     """A batch of nothing but pairable items (one kernel path: couples, no single items),
     captured in a graph and replayed."""
