@@ -147,29 +147,50 @@ def bn_version() -> str:
 
 
 # ------------------------------------------------------------------ marshalling ----
+_torch = None      # the torch module, imported on first use
+_LIMB_DTYPES = ()  # int64, uint64
+
+
+def _tm():
+    global _torch, _LIMB_DTYPES
+    if _torch is None:
+        import torch
+        _LIMB_DTYPES = (torch.int64, torch.uint64)
+        _torch = torch
+    return _torch
+
+
 def _ptr(t, what: str, need: int | None = None):
     """Device pointer of a contiguous int64/uint64 torch tensor (None -> NULL).  `need`:
     the limbs the call will touch through this pointer; a smaller tensor is refused
     here, because a device pointer carries no extent that the library could check."""
     if t is None:
         return None
-    import torch
+    torch = _tm()
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{what}: expected a torch tensor")
     if not t.is_cuda:
         raise ValueError(f"{what}: tensor must live on the GPU")
-    if t.dtype not in (torch.int64, torch.uint64):
+    if t.dtype not in _LIMB_DTYPES:
         raise TypeError(f"{what}: limbs must be int64/uint64, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{what}: tensor must be contiguous")
-    if need is not None and t.numel() < need:
-        raise ValueError(f"{what}: tensor holds {t.numel()} limbs, the call touches {need}")
-    return t.data_ptr() if t.numel() else None
+    n = t.numel()
+    if need is not None and n < need:
+        raise ValueError(f"{what}: tensor holds {n} limbs, the call touches {need}")
+    return t.data_ptr() if n else None
 
 
 def _stream(stream):
+    """The hipStream_t of `stream` (a torch stream or a raw handle); None: torch's current
+    stream on the current device (read through torch's raw-stream query, a tenth of the
+    host cost of building a torch.cuda.Stream object, when this torch has it)."""
     if stream is None:
-        import torch
+        torch = _tm()
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        dev = getattr(torch._C, "_cuda_getDevice", None)
+        if raw is not None and dev is not None:
+            return raw(dev())
         stream = torch.cuda.current_stream()
     if isinstance(stream, int):
         return stream
