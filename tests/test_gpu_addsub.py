@@ -101,6 +101,20 @@ def test_c3_full(bnctx, op, kind):
 
 
 @pytest.mark.parametrize("op", ["add", "sub"])
+@pytest.mark.parametrize("kind", ["runs", "worst"])
+def test_c3_full_waiting_form(bnctx, op, kind):
+    """2^26 limbs in the waiting form (addsub.defer_tiles 0: every tile looks back before
+    it finishes), the second form the benchmark times at this size."""
+    a, b = wl.c3(op, worst=kind == "worst")
+    old = bn.bn_get_param(bnctx, "addsub.defer_tiles")
+    bn.bn_set_param(bnctx, "addsub.defer_tiles", 0)
+    try:
+        _check(bnctx, op, a, b, a.size, 1)
+    finally:
+        bn.bn_set_param(bnctx, "addsub.defer_tiles", old)
+
+
+@pytest.mark.parametrize("op", ["add", "sub"])
 @pytest.mark.parametrize("waves,rows", [(w, r) for w in (1, 2, 4, 8) for r in (1, 2, 4, 8, 16) if w * r < 128])
 def test_every_tile_shape(bnctx, op, waves, rows):
     keys = ("addsub.batch_waves", "addsub.batch_rows", "addsub.chain_waves", "addsub.chain_rows")
