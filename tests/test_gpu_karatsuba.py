@@ -116,7 +116,7 @@ def test_sign_pieces(bnctx, n):
         _check(bnctx, a, b, n, len(positions), levels, "mfma")
 
 
-@pytest.mark.parametrize("levels", [1, 2])
+@pytest.mark.parametrize("levels", [1, 2, 3])
 def test_c5_full(bnctx, c5_oracle, levels):
     """64 pairs x 16384 limbs (incl. all-ones x all-ones and zero x zero): every limb of
     every product against the oracle; residues as an extra check."""
