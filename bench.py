@@ -85,10 +85,12 @@ def gpu_time(fn, reps: int, warmup: int = 1):
     return float(np.mean(ts)), ts
 
 
-def queued_time(torch, fn, k: int, reps: int = 20) -> float:
+def queued_time(torch, fn, k: int, reps: int = 20):
     """Median device-side ms per fn() when k calls sit in the stream behind a spin
     kernel (about 1 ms): the events then time the GPU's work and its dispatch gaps,
-    not the host's enqueue."""
+    not the host's enqueue.  None when this torch has no spin kernel (torch.cuda._sleep)."""
+    if not hasattr(torch.cuda, "_sleep"):
+        return None
     for _ in range(3):
         fn()
     torch.cuda.synchronize()
@@ -400,9 +402,10 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
             # captured into one graph (the runtime's per-graph launch cost shared by 8).
             g = bn.bn_graph_capture_batch(ctx, 2, tr, ta, tb, 4, 4, 1088, None, op[4:], s) if op.startswith("mul") \
                 else bn.bn_graph_capture_batch(ctx, 0 if op == "add" else 1, tr, ta, tb, 4, 0, 1088, tc, 0, s)
+            us = lambda ms, per=1: None if ms is None else ms * 1e3 / per
             with torch.cuda.stream(s):
-                c1[op + "_device_us"] = queued_time(torch, lambda: bn.bn_graph_launch(g, s), 8) * 1e3
-                c1[op + "_direct_device_us"] = queued_time(torch, fn, 8) * 1e3
+                c1[op + "_device_us"] = us(queued_time(torch, lambda: bn.bn_graph_launch(g, s), 8))
+                c1[op + "_direct_device_us"] = us(queued_time(torch, fn, 8))
             bn.bn_graph_destroy(g)
             torch.cuda.synchronize()
             ref = tr.clone()
@@ -412,7 +415,7 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
                 for _ in range(8):
                     fn()
             with torch.cuda.stream(s):
-                c1[op + "_graph8_us_per_batch"] = queued_time(torch, g8.replay, 1) * 1e3 / 8
+                c1[op + "_graph8_us_per_batch"] = us(queued_time(torch, g8.replay, 1), 8)
                 ms, _ = gpu_time(g8.replay, 50, 5)
             c1[op + "_graph8_alone_us_per_batch"] = ms * 1e3 / 8
             torch.cuda.synchronize()
