@@ -359,7 +359,8 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *                                      8192, 0 = never) defer the stores of tiles that
  *                                      propagate through every limb to a fill pass (bn_add)
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
- *                                      (na + nb > 1024: the column-workspace kernels)
+ *                                      (na + nb > 1024: the column-workspace kernels; default
+ *                                      1, MFMA for every such product)
  *   "mul.small_crossover_limbs"        the same for na + nb <= 1024 (one wave per product)
  *   "mul.crossover_limbs_p64",          the same for products of at most 64 limbs and of 65-128
  *   "mul.crossover_limbs_p128"         limbs (the mad form's lanes hold 1 or 2 limbs there, the

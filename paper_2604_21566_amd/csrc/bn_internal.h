@@ -46,7 +46,7 @@ struct Tuning {
     int batch_rows = 1;
     int chain_waves = 4;
     int chain_rows = 8;
-    i64 mul_crossover_limbs = 256;     // BN_MUL_AUTO, na + nb > 256: MFMA when min(na, nb) >= this
+    i64 mul_crossover_limbs = 1;       // BN_MUL_AUTO, na + nb > 1024: MFMA when min(na, nb) >= this
     i64 mul_small_crossover_limbs = 28;  // BN_MUL_AUTO, na + nb <= 1024 (one-wave kernels): the same
     i64 mul_crossover_p64 = -1;        // the same for na + nb <= 64 (-1: mul_small_crossover_limbs)
     i64 mul_crossover_p128 = -1;       // the same for 64 < na + nb <= 128 (-1: mul_small_crossover_limbs)

@@ -276,9 +276,11 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         t.chain_rows = shapes[bk][1];
     }
 
-    // 2) mad vs MFMA crossovers: square products, equal total work per size; products
-    // in the one-wave range (mul_small_range) and larger ones each get the smallest
-    // size from which MFMA wins at every larger size of the range
+    // 2) mad vs MFMA crossovers, equal total work per shape.  The one-wave range
+    // (mul_small_range) from square products, the larger range from products of a
+    // 2048-limb operand with a shorter one of s limbs (the crossover is a bound on the
+    // shorter length, and squares of more than 512 limbs would only test it from 1024
+    // up); each range gets the smallest length from which MFMA wins at every larger one.
     i64 crossover = -1, small_crossover = -1;
     for (u64 n = 4; n <= 4096; n *= 2) {
         u64 npairs = std::max<u64>(1, std::min<u64>((1ull << 26) / (n * n), NBIG / n));
@@ -289,11 +291,27 @@ extern "C" bn_status bn_autotune(bn_ctx *ctx, const char *out_json) {
         snprintf(line, sizeof line, "    \"sweep.n%llu\": \"mad %.4f ms, mfma %.4f ms, pairs %llu\",\n",
                  (unsigned long long)n, tm, tf, (unsigned long long)npairs);
         log += line;
-        i64 &x = mul_small_range(2 * n) ? small_crossover : crossover;
+        if (!mul_small_range(2 * n)) continue;
         if (tf < tm) {
-            if (x < 0) x = (i64)n;
+            if (small_crossover < 0) small_crossover = (i64)n;
         } else {
-            x = -1;
+            small_crossover = -1;
+        }
+    }
+    for (u64 sl = 1; sl <= 2048; sl *= 2) {
+        const u64 nl = 2048;
+        u64 npairs = std::max<u64>(1, std::min<u64>((1ull << 26) / (nl * sl), NBIG / nl));
+        npairs = std::min<u64>(npairs, 65535);
+        const float tm = time_ms([&] { launch_mul_batch(ctx, r, a, b, nl, sl, npairs, BN_MUL_MAD, nullptr); }, 3);
+        const float tf = time_ms([&] { launch_mul_batch(ctx, r, a, b, nl, sl, npairs, BN_MUL_MFMA, nullptr); }, 3);
+        char line[160];
+        snprintf(line, sizeof line, "    \"sweep.n2048x%llu\": \"mad %.4f ms, mfma %.4f ms, pairs %llu\",\n",
+                 (unsigned long long)sl, tm, tf, (unsigned long long)npairs);
+        log += line;
+        if (tf < tm) {
+            if (crossover < 0) crossover = (i64)sl;
+        } else {
+            crossover = -1;
         }
     }
     t.mul_crossover_limbs = crossover > 0 ? crossover : (i64)1 << 40;
