@@ -377,7 +377,7 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *                                      launches whose shorter operand has >= 10240 limbs,
  *                                      224 otherwise
  *   "mul.karatsuba_limbs"              BN_KARATSUBA_AUTO splits while the halves keep at
- *                                      least this many limbs (default 4096, >= 1)
+ *                                      least this many limbs (default 2048, >= 1)
  *   "mul.mfma_rows"                    Toeplitz rows per column block of the large MFMA
  *                                      kernel, in groups of 64: 1 or 2 (default 2: the same
  *                                      LDS reads feed twice the MFMAs)

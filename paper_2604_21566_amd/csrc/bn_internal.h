@@ -61,7 +61,7 @@ struct Tuning {
     int ragged_pair = 1;               // ragged multiplication plans: mad items of at most 32 product
                                        // limbs whose shorter operands have the same length run two
                                        // to a wave (1) or one each (0)
-    i64 karatsuba_limbs = 4096;        // BN_KARATSUBA_AUTO: smallest half that is split again
+    i64 karatsuba_limbs = 2048;        // BN_KARATSUBA_AUTO: smallest half that is split again
     int auto_grow = 0;                 // 1: a compute call whose workspace is short grows it
                                        // (allocation + device synchronisation, never during a
                                        // capture); 0: it returns BN_ENOSPACE
