@@ -366,9 +366,10 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "mul.crossover_limbs_p128"         limbs (the mad form's lanes hold 1 or 2 limbs there, the
  *                                      MFMA form runs one column block); -1 (default): use
  *                                      "mul.small_crossover_limbs"
- *   "mul.crossover_limbs_p256",         the same for products of 129-256 and of 257-512 limbs
- *   "mul.crossover_limbs_p512"         (default 4 for both: the mad form's per-step work grows
- *                                      with the product there, the MFMA form's far less);
+ *   "mul.crossover_limbs_p256",         the same for products of 129-256, 257-512 and 513-1024
+ *   "mul.crossover_limbs_p512",         limbs (defaults 2, 2 and 40: the mad form's per-step work
+ *   "mul.crossover_limbs_p1024"        grows with the product, the one-wave MFMA form's far
+ *                                      less; above 512 limbs MFMA runs on the workspace path);
  *                                      -1: use "mul.small_crossover_limbs"
  *   "mul.mad_xchunk"                   32-bit digits of a per large mad work item
  *   "mul.mfma_chunk"                   Toeplitz steps staged in LDS per round by the large

@@ -618,7 +618,7 @@ bn_status bn_graph_destroy(bn_graph *graph) {
 // ------------------------------------------------------------------ params ----
 static const char *kParamNames =
     "addsub.batch_waves,addsub.batch_rows,addsub.chain_waves,addsub.chain_rows,addsub.defer_tiles,"
-    "mul.crossover_limbs,mul.small_crossover_limbs,mul.crossover_limbs_p64,mul.crossover_limbs_p128,mul.crossover_limbs_p256,mul.crossover_limbs_p512,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,mul.karatsuba_limbs,"
+    "mul.crossover_limbs,mul.small_crossover_limbs,mul.crossover_limbs_p64,mul.crossover_limbs_p128,mul.crossover_limbs_p256,mul.crossover_limbs_p512,mul.crossover_limbs_p1024,mul.mad_xchunk,mul.mfma_chunk,mul.mfma_rows,mul.karatsuba_limbs,"
     "ragged.pair_small,lookback.spin_limit,debug.flags,workspace.auto_grow";
 
 const char *bn_param_names(void) { return kParamNames; }
@@ -649,12 +649,13 @@ bn_status bn_set_param(bn_ctx *ctx, const char *key, int64_t v) {
         if (v < 1) return BN_EINVAL;
         t.mul_small_crossover_limbs = v;
     } else if (k == "mul.crossover_limbs_p64" || k == "mul.crossover_limbs_p128" || k == "mul.crossover_limbs_p256" ||
-               k == "mul.crossover_limbs_p512") {
+               k == "mul.crossover_limbs_p512" || k == "mul.crossover_limbs_p1024") {
         if (v < -1 || v == 0) return BN_EINVAL;
         (k == "mul.crossover_limbs_p64"    ? t.mul_crossover_p64
          : k == "mul.crossover_limbs_p128" ? t.mul_crossover_p128
          : k == "mul.crossover_limbs_p256" ? t.mul_crossover_p256
-                                           : t.mul_crossover_p512) = v;
+         : k == "mul.crossover_limbs_p512" ? t.mul_crossover_p512
+                                           : t.mul_crossover_p1024) = v;
     } else if (k == "mul.mad_xchunk") {
         if (v < 64 || v > (1 << 20) || (v % 8)) return BN_EINVAL;
         t.mad_xchunk = (int)v;
@@ -700,6 +701,7 @@ bn_status bn_get_param(bn_ctx *ctx, const char *key, int64_t *v) {
     else if (k == "mul.crossover_limbs_p128") *v = t.mul_crossover_p128;
     else if (k == "mul.crossover_limbs_p256") *v = t.mul_crossover_p256;
     else if (k == "mul.crossover_limbs_p512") *v = t.mul_crossover_p512;
+    else if (k == "mul.crossover_limbs_p1024") *v = t.mul_crossover_p1024;
     else if (k == "mul.mad_xchunk") *v = t.mad_xchunk;
     else if (k == "mul.mfma_chunk") *v = t.mfma_chunk;
     else if (k == "mul.mfma_rows") *v = t.mfma_rows;

@@ -50,8 +50,9 @@ struct Tuning {
     i64 mul_small_crossover_limbs = 28;  // BN_MUL_AUTO, na + nb <= 1024 (one-wave kernels): the same
     i64 mul_crossover_p64 = -1;        // the same for na + nb <= 64 (-1: mul_small_crossover_limbs)
     i64 mul_crossover_p128 = -1;       // the same for 64 < na + nb <= 128 (-1: mul_small_crossover_limbs)
-    i64 mul_crossover_p256 = 4;        // the same for 128 < na + nb <= 256
-    i64 mul_crossover_p512 = 4;        // the same for 256 < na + nb <= 512
+    i64 mul_crossover_p256 = 2;        // the same for 128 < na + nb <= 256
+    i64 mul_crossover_p512 = 2;        // the same for 256 < na + nb <= 512
+    i64 mul_crossover_p1024 = 40;      // the same for 512 < na + nb <= 1024 (MFMA on the workspace path)
     int mad_cols = 8;                  // 32-bit columns per lane in the large mad kernel
     int mad_xchunk = 4096;             // x-range (32-bit digits) per mad work item
     int mfma_chunk = 0;                // Toeplitz steps staged in LDS per round (even, 16..256; three

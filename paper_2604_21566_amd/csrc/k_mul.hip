@@ -590,14 +590,16 @@ static u32 mfma_window(const bn_ctx *ctx, u64 na, u64 nb, u32 nslices) {
 int mul_pick_form(const bn_ctx *ctx, u64 na, u64 nb, int form) {
     if (form != BN_MUL_AUTO) return form;
     // products of at most 1024 limbs (mad: one wave; MFMA: one wave up to 512 limbs)
-    // and larger ones (column-workspace kernels) have a crossover each; one-wave
-    // products of at most 64, 65-128, 129-256 and 257-512 limbs may have their own
-    // (the mad form's lanes hold 1, 2, 4 or 8 limbs there while its steps follow the
-    // shorter operand, and the MFMA form runs 1, 2 or 4 column blocks)
+    // and larger ones (column-workspace kernels) have a crossover each; products of at
+    // most 64, 65-128, 129-256, 257-512 and 513-1024 limbs may have their own (the mad
+    // form's lanes hold 1, 2, 4, 8 or 16 limbs there while its steps follow the shorter
+    // operand; the MFMA form runs 1, 2 or 4 column blocks in one wave, then the
+    // workspace kernels)
     const u64 P = na + nb;
     i64 x = mul_small_range(P) ? ctx->tune.mul_small_crossover_limbs : ctx->tune.mul_crossover_limbs;
     const i64 cls = P <= 64 ? ctx->tune.mul_crossover_p64 : P <= 128 ? ctx->tune.mul_crossover_p128
-                  : P <= 256 ? ctx->tune.mul_crossover_p256 : P <= 512 ? ctx->tune.mul_crossover_p512 : -1;
+                  : P <= 256 ? ctx->tune.mul_crossover_p256 : P <= 512 ? ctx->tune.mul_crossover_p512
+                  : mul_small_range(P) ? ctx->tune.mul_crossover_p1024 : -1;
     if (cls >= 0) x = cls;
     return (i64)std::min(na, nb) >= x ? BN_MUL_MFMA : BN_MUL_MAD;
 }

@@ -506,29 +506,32 @@ def test_graph_survives_workspace_growth(form):
         bn.bn_destroy(ctx)
 
 
-@pytest.mark.parametrize("p256,p512", [(1, 1), (1 << 30, 1 << 30), (1, 1 << 30), (8, 4), (-1, -1)])
-def test_crossover_classes_256_512(bnctx, p256, p512):
-    """The automatic form's crossovers for products of 129-256 and of 257-512 limbs at
-    either extreme, the defaults and the small crossover (-1): skewed and square uniform
-    batches of both classes, and ragged items of 257-512 limbs (batched path per item),
-    against the oracle."""
-    announce("crossover classes 256/512", p256, p512)
-    keys = ("mul.crossover_limbs_p256", "mul.crossover_limbs_p512")
+@pytest.mark.parametrize("p256,p512,p1024", [(1, 1, 1), (1 << 30, 1 << 30, 1 << 30), (1, 1 << 30, 1),
+                                              (2, 2, 40), (-1, -1, -1)])
+def test_crossover_classes_256_512_1024(bnctx, p256, p512, p1024):
+    """The automatic form's crossovers for products of 129-256, 257-512 and 513-1024
+    limbs at either extreme, the defaults and the small crossover (-1): skewed and square
+    uniform batches of each class, and ragged items of 257-1024 limbs (batched path per
+    item), against the oracle."""
+    announce("crossover classes 256/512/1024", p256, p512, p1024)
+    keys = ("mul.crossover_limbs_p256", "mul.crossover_limbs_p512", "mul.crossover_limbs_p1024")
     old = tuple(bn.bn_get_param(bnctx, k) for k in keys)
     try:
-        bn.bn_set_param(bnctx, keys[0], p256)
-        bn.bn_set_param(bnctx, keys[1], p512)
-        g = np.random.default_rng(abs(p256) * 7 + abs(p512))
+        for k, v in zip(keys, (p256, p512, p1024)):
+            bn.bn_set_param(bnctx, k, v)
+        g = np.random.default_rng(abs(p256) * 7 + abs(p512) + abs(p1024) * 3)
         for na, nb, npairs in ((150, 8, 20), (4, 250, 9), (128, 128, 5), (200, 30, 7),
-                               (300, 4, 11), (12, 480, 5), (256, 256, 3), (400, 100, 3)):
+                               (300, 4, 11), (12, 480, 5), (256, 256, 3), (400, 100, 3),
+                               (700, 40, 3), (28, 990, 2), (600, 16, 3), (512, 512, 2)):
             _check(bnctx, _rand(g, na * npairs), _rand(g, nb * npairs), na, nb, npairs, "auto")
-        a, b, desc, rsz = _tiny_ragged(g, [(300, 4), (4, 300), (256, 200), (500, 12), (20, 20), (130, 9)])
+        a, b, desc, rsz = _tiny_ragged(g, [(300, 4), (4, 300), (256, 200), (500, 12), (20, 20), (130, 9),
+                                           (700, 40), (30, 900)])
         plan = bn.bn_plan_mul_ragged(bnctx, desc, "auto")
         try:
             tr = torch.full((rsz,), -1, dtype=torch.int64, device="cuda")
             bn.bn_mul_ragged(bnctx, plan, tr, D(a), D(b))
             torch.cuda.synchronize()
-            _check_pool(H(tr), oracle.mul_ragged(a, b, desc, rsz), desc, "ragged 257-512")
+            _check_pool(H(tr), oracle.mul_ragged(a, b, desc, rsz), desc, "ragged 257-1024")
         finally:
             bn.bn_plan_destroy(plan)
     finally:
