@@ -132,3 +132,28 @@ def test_square_mfma_random(bnctx, seed):
     torch.cuda.synchronize()
     got = H(tr)
     assert (got == want).all(), f"n={n} npairs={npairs}: first bad limb {np.argmax(got != want)}"
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_auto_form_class_boundaries(bnctx, seed):
+    """The automatic form around its size classes: products whose length sits on either
+    side of a class boundary (64/65, 128/129, 256/257, 512/513, 1024/1025 limbs) with a
+    shorter operand just below, at and above the class's crossover, random batch counts
+    and operand order, against the oracle (either form is exact; this checks the dispatch
+    and the workspace each class picks)."""
+    g = np.random.default_rng(5000 + seed)
+    P = int(g.choice([64, 65, 128, 129, 256, 257, 512, 513, 1024, 1025]))
+    cross = {64: 28, 128: 28, 256: 2, 512: 2, 1024: 40}[min(c for c in (64, 128, 256, 512, 1024) if c >= P)
+                                                          if P <= 1024 else 1024]
+    s = max(1, min(P // 2, cross + int(g.integers(-2, 3))))
+    na, nb = (P - s, s) if g.integers(0, 2) else (s, P - s)
+    npairs = int(g.integers(1, 40))
+    a, b = _rand(g, na * npairs), _rand(g, nb * npairs)
+    want = oracle.mul_batch(a, b, na, nb, npairs)
+    announce("auto form class boundary", seed, na, nb, npairs)
+    bn.bn_reserve_for(bnctx, bn.BN_OP_MUL, na, nb, npairs, "auto", 0)
+    tr = torch.full(((na + nb) * npairs,), -1, dtype=torch.int64, device="cuda")
+    bn.bn_mul_n_batch(bnctx, tr, D(a), D(b), na, nb, npairs, "auto")
+    torch.cuda.synchronize()
+    got = H(tr)
+    assert (got == want).all(), f"{na}x{nb} npairs={npairs}: first bad limb {np.argmax(got != want)}"
