@@ -361,7 +361,9 @@ bn_status bn_graph_destroy(bn_graph *graph);
  *   "mul.crossover_limbs"              BN_MUL_AUTO uses MFMA when min(na,nb) >= this
  *                                      (na + nb > 1024: the column-workspace kernels; default
  *                                      1, MFMA for every such product)
- *   "mul.small_crossover_limbs"        the same for na + nb <= 1024 (one wave per product)
+ *   "mul.small_crossover_limbs"        the same for na + nb <= 1024 (one wave per product) in
+ *                                      each size class below whose own parameter is -1 (by
+ *                                      default the classes of at most 128 limbs; default 28)
  *   "mul.crossover_limbs_p64",          the same for products of at most 64 limbs and of 65-128
  *   "mul.crossover_limbs_p128"         limbs (the mad form's lanes hold 1 or 2 limbs there, the
  *                                      MFMA form runs one column block); -1 (default): use
