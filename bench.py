@@ -587,13 +587,15 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
             # buffer runs out), so that every size fills the device
             npairs = int(max(1, min((1 << 32) // (n * n), (1 << 25) // n)))
             row = {}
-            for form in ("mad", "mfma"):
+            for form in ("mad", "mfma", "auto"):
                 bn.bn_reserve_for(ctx, bn.BN_OP_MUL, n, n, npairs, form)
                 ms, ts = gpu_time(lambda: bn.bn_mul_n_batch(ctx, out, big, big, n, n, npairs, form), REPS, 2)
                 row[form + "_limb_products_per_s"] = npairs * n * n / (ms * 1e-3)
                 row[form + "_ms"] = ms
                 row[form + "_ci95_ms"] = ci95(ts)
             row["pairs"] = npairs
+            # the automatic form against the faster of the two (1.0: it picked the faster)
+            row["auto_over_best"] = row["auto_ms"] / min(row["mad_ms"], row["mfma_ms"])
             sweep[str(n)] = row
             faster = row["mfma_limb_products_per_s"] > row["mad_limb_products_per_s"]
             if faster and crossover is None:
@@ -601,7 +603,8 @@ def extra_workloads(ctx, bn, wl, torch, only=None):
             elif not faster:
                 crossover = None
             n *= 2
-        res["crossover"] = {"sweep": sweep, "mfma_faster_from_limbs": crossover}
+        res["crossover"] = {"sweep": sweep, "mfma_faster_from_limbs": crossover,
+                            "auto_over_best_max": max(r["auto_over_best"] for r in sweep.values())}
 
     res["lookback_self_help_latch"] = bn.bn_check(ctx)
     return res
